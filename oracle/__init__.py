@@ -1,0 +1,168 @@
+"""FP64 CPU oracle for QAOA on k-NAE-SAT: Python access to ``oracle.c``.
+
+TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU baseline leg
+of the benchmark import this package. The GPU library and its binding never
+import it, and it imports nothing from them.
+
+``build()`` compiles ``oracle.c`` with gcc and OpenMP into ``liboracle.so``
+beside it; the loaders below use what is built and build only when nothing is.
+The dense checker in :mod:`oracle.dense` is a second, independent construction
+(NumPy only) used to pin this one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_F64P = ctypes.POINTER(ctypes.c_double)
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build() -> str:
+    """Compile the oracle (gcc, -O2, OpenMP). Returns the library path."""
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_cost.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _I32P]
+    lib.oracle_count_solutions.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _U64P]
+    lib.oracle_state.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P, _F64P]
+    lib.oracle_qaoa.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P, _F64P, _F64P]
+    lib.oracle_qaoa_grad.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P,
+                                     ctypes.c_double, ctypes.c_double, _F64P, _F64P, _F64P]
+    lib.oracle_num_threads.argtypes = []
+    for fn in (lib.oracle_cost, lib.oracle_count_solutions, lib.oracle_state,
+               lib.oracle_qaoa, lib.oracle_qaoa_grad, lib.oracle_num_threads):
+        fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_I32P)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_F64P)
+
+
+def _instance(clauses, n):
+    cl = np.asarray(clauses, dtype=np.int32)
+    if cl.ndim != 2:
+        raise ValueError("clauses must be an [m, k] array of literals")
+    m, k = cl.shape
+    return np.ascontiguousarray(cl), m, max(k, 1)
+
+
+def cost(clauses, n: int) -> np.ndarray:
+    """C(x) for all x in [0, 2^n) as int32 (Section 3.2, eq. knaesatobj)."""
+    cl, m, k = _instance(clauses, n)
+    out = np.empty(1 << n, dtype=np.int32)
+    rc = _load().oracle_cost(n, m, k, cl.ctypes.data_as(_I32P), out.ctypes.data_as(_I32P))
+    if rc:
+        raise ValueError("oracle_cost: invalid instance")
+    return out
+
+
+def count_solutions(clauses, n: int) -> int:
+    """#{x : C(x) = 0}."""
+    cl, m, k = _instance(clauses, n)
+    c = ctypes.c_uint64(0)
+    rc = _load().oracle_count_solutions(n, m, k, cl.ctypes.data_as(_I32P), ctypes.byref(c))
+    if rc:
+        raise ValueError("oracle_count_solutions: invalid instance")
+    return int(c.value)
+
+
+def _angles(gammas, betas):
+    g, gp = _f64(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
+    b, bp = _f64(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
+    if g.shape != b.shape:
+        raise ValueError("gammas and betas differ in length")
+    return g, gp, b, bp
+
+
+def state(cost_arr, n: int, gammas, betas) -> np.ndarray:
+    """Final QAOA state as complex128[2^n]."""
+    c, cp = _i32(cost_arr)
+    g, gp, b, bp = _angles(gammas, betas)
+    psi = np.empty(2 << n, dtype=np.float64)
+    rc = _load().oracle_state(n, cp, len(g), gp, bp, psi.ctypes.data_as(_F64P))
+    if rc:
+        raise ValueError("oracle_state: invalid arguments")
+    return psi.view(np.complex128)
+
+
+def qaoa(cost_arr, n: int, gammas, betas):
+    """(p_succ, E[C], norm) of the depth-p QAOA state."""
+    c, cp = _i32(cost_arr)
+    g, gp, b, bp = _angles(gammas, betas)
+    out = np.zeros(3, dtype=np.float64)
+    rc = _load().oracle_qaoa(n, cp, len(g), gp, bp, None, out.ctypes.data_as(_F64P))
+    if rc:
+        raise ValueError("oracle_qaoa: invalid arguments")
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def qaoa_grad(cost_arr, n: int, gammas, betas, w_psucc: float = 1.0, w_energy: float = 0.0):
+    """Adjoint gradient of w_psucc*p_succ + w_energy*E[C].
+
+    Returns (dgammas, dbetas, (p_succ, E[C], norm))."""
+    c, cp = _i32(cost_arr)
+    g, gp, b, bp = _angles(gammas, betas)
+    p = len(g)
+    dg = np.zeros(p, dtype=np.float64)
+    db = np.zeros(p, dtype=np.float64)
+    out = np.zeros(3, dtype=np.float64)
+    rc = _load().oracle_qaoa_grad(n, cp, p, gp, bp, float(w_psucc), float(w_energy),
+                                  dg.ctypes.data_as(_F64P), db.ctypes.data_as(_F64P),
+                                  out.ctypes.data_as(_F64P))
+    if rc:
+        raise ValueError("oracle_qaoa_grad: invalid arguments")
+    return dg, db, (float(out[0]), float(out[1]), float(out[2]))
+
+
+def finite_difference_grad(cost_arr, n: int, gammas, betas, w_psucc=1.0, w_energy=0.0, h=1e-4):
+    """Central differences (F(theta + h e_i) - F(theta - h e_i)) / 2h on the
+    oracle forward, for every gamma_i and beta_i."""
+    g = np.asarray(gammas, dtype=np.float64)
+    b = np.asarray(betas, dtype=np.float64)
+
+    def F(gg, bb):
+        ps, e, _ = qaoa(cost_arr, n, gg, bb)
+        return w_psucc * ps + w_energy * e
+
+    dg = np.zeros_like(g)
+    db = np.zeros_like(b)
+    for i in range(len(g)):
+        e = np.zeros_like(g)
+        e[i] = h
+        dg[i] = (F(g + e, b) - F(g - e, b)) / (2 * h)
+        db[i] = (F(g, b + e) - F(g, b - e)) / (2 * h)
+    return dg, db
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
