@@ -1,0 +1,144 @@
+/*
+ * qnae: statevector simulation of depth-p QAOA on k-NAE-SAT for AMD MI355X
+ * (gfx950). C ABI of libqnae.so.
+ *
+ * Method: Elkadi & Bondesan, "Quantum Approximate Optimisation for
+ * Not-All-Equal SAT". The cost is the number of NAE-violated clauses
+ * (Section 3.2), the QAOA state is prod_l U_B(beta_l) U_C(gamma_l) |+>
+ * (Section 3.3), the phase is the diagonal unitary exp(-i gamma C(x))
+ * (Appendix A.4) and the mixer is prod_j exp(-i beta X_j) applied as
+ * butterflies on qubit pairs (Appendix A.4). The readouts are the success
+ * probability <psi|{H_C = 0}|psi> (Definition of the success probability,
+ * eq. psuccnae) and the expected cost <psi|H_C|psi> (Section 2.1).
+ *
+ * Conventions:
+ *  - literals are DIMACS-style int32: +(v+1) is x_v, -(v+1) is NOT x_v, with
+ *    0 <= v < n; a clause array is m rows of k literals, row-major;
+ *  - basis index x = sum_v x_v 2^v (variable v is bit v of x);
+ *  - the state is complex64 (interleaved float re, im), 2^n entries, in
+ *    natural index order;
+ *  - layer 0 is applied first; within a layer the phase comes before the mixer;
+ *  - p_succ and E[C] are raw expectations on the evolved state, with no
+ *    renormalisation; the norm is reported beside them.
+ *
+ * Every call returns an int status: QNAE_OK (0) or a negative error code. No
+ * call throws. qnae_last_error() gives a message for the last failure of the
+ * calling thread. Device pointers are plain HIP device addresses (for example
+ * a torch tensor's data_ptr()); streams are hipStream_t passed as void*
+ * (NULL is the default stream).
+ */
+#ifndef QNAE_H
+#define QNAE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qnae_ctx qnae_ctx;
+
+typedef struct {
+    double p_success;     /* sum over C(x) = 0 of |psi(x)|^2 */
+    double expected_cost; /* sum over x of C(x) |psi(x)|^2   */
+    double norm;          /* sum over x of |psi(x)|^2        */
+} qnae_result;
+
+enum { QNAE_U8 = 1, QNAE_U16 = 2 };
+
+enum {
+    QNAE_OK = 0,
+    QNAE_EINVAL = -1,   /* invalid argument; nothing was enqueued */
+    QNAE_ENOMEM = -2,   /* device or pinned host allocation failed */
+    QNAE_EHIP = -3,     /* HIP runtime error (message has hipGetErrorString) */
+    QNAE_EBUSY = -4,    /* server queue or pool full */
+    QNAE_ETIMEDOUT = -5 /* server wait timed out */
+};
+
+/* Largest number of variables (qubits) accepted: 2^34 complex64 amplitudes
+ * are 128 GiB, within one MI355X's 288 GB of HBM. */
+#define QNAE_MAX_N 34
+
+/* Create a context on HIP device `device` (make it current first if the
+ * caller uses several). The context owns reusable device scratch (the state
+ * when the caller passes none, block partial sums, phase tables) and pinned
+ * host staging. *out is set to NULL on failure. */
+int qnae_create(qnae_ctx **out, int device);
+
+/* Release the context and everything it owns. Waits for its work. NULL is a
+ * no-op. */
+int qnae_destroy(qnae_ctx *ctx);
+
+/* Message of the calling thread's last failed call (empty if none). The
+ * pointer stays valid until the thread's next qnae call. ctx may be NULL. */
+const char *qnae_last_error(const qnae_ctx *ctx);
+
+/* Build the cost diagonal C(x) = number of clauses that are NAE-violated at
+ * x, i.e. whose literals are all false or all true (Section 3.2,
+ * eq. knaesatobj; Appendix A.2, eq. demorgannae), for every x in [0, 2^n).
+ * Each literal is evaluated on its own, so a clause holding a variable with
+ * both signs is never violated.
+ *
+ *   clauses      host, m * k int32 literals (read before the call returns;
+ *                may be NULL when m = 0)
+ *   m, n, k      0 <= m <= 65535, 1 <= n <= QNAE_MAX_N, 1 <= k <= 64
+ *   cost_dev     caller-owned device buffer of 2^n elements of cost_dtype
+ *   cost_dtype   QNAE_U8 (requires m <= 255) or QNAE_U16
+ *   num_solutions  optional host pointer; if not NULL the call waits for the
+ *                stream and stores #{x : C(x) = 0}
+ *   stream       hipStream_t the work is enqueued on
+ *
+ * Exact integer result (bit-exact). Without num_solutions the call is
+ * asynchronous with respect to the host. Errors: QNAE_EINVAL for any bad
+ * argument or literal (0, or |literal| > n), QNAE_EHIP, QNAE_ENOMEM. */
+int qnae_build_cost_diagonal(qnae_ctx *ctx, const int32_t *clauses, int32_t m,
+                             int32_t n, int32_t k, void *cost_dev,
+                             int32_t cost_dtype, uint64_t *num_solutions,
+                             void *stream);
+
+/* Run depth-p QAOA from |+> on the cost diagonal and read out p_succ, E[C]
+ * and the norm (Section 3.3; Definition of the success probability).
+ *
+ *   cost_dev     device, 2^n elements of cost_dtype, values in [0, m]
+ *   n, m         1 <= n <= QNAE_MAX_N; m bounds the cost values (phase table
+ *                length m + 1); m <= 255 for QNAE_U8, m <= 65535 for U16
+ *   gammas, betas host FP64 arrays of length p (may be NULL when p = 0);
+ *                layer l applies exp(-i gammas[l] C) then
+ *                prod_j exp(-i betas[l] X_j)
+ *   p            0 <= p <= 100000; p = 0 reads out |+>
+ *   state_dev    optional caller-owned device complex64[2^n]; if not NULL
+ *                it receives the final state, otherwise context scratch is
+ *                used and the state is not kept
+ *   out          host result
+ *   stream       hipStream_t the work is enqueued on
+ *
+ * Synchronous: returns after *out is filled. Cost values above m give
+ * undefined results. Errors: QNAE_EINVAL, QNAE_ENOMEM, QNAE_EHIP. */
+int qnae_qaoa_run(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype,
+                  int32_t n, int32_t m, const double *gammas,
+                  const double *betas, int32_t p, void *state_dev,
+                  qnae_result *out, void *stream);
+
+/* Kernel timing with HIP events, for measurement. While enabled, the context
+ * records an event pair around every kernel it launches, on the stream the
+ * kernel runs on, and tallies per kernel kind the number of launches, the
+ * summed event time and the algorithmic bytes (the state, cost and table
+ * traffic the method needs, not what the hardware moved).
+ * qnae_profile_read waits for the recorded events, writes up to `capacity`
+ * entries, sets *count to the number of kinds seen and clears the tallies.
+ * `name` points to static storage. */
+typedef struct {
+    const char *name;
+    uint64_t launches;
+    double total_ms;
+    double bytes;
+} qnae_kernel_stat;
+
+int qnae_profile_enable(qnae_ctx *ctx, int on);
+int qnae_profile_read(qnae_ctx *ctx, qnae_kernel_stat *out, int32_t capacity, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QNAE_H */

@@ -41,17 +41,19 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_cost.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _I32P]
+    lib.oracle_cost_at.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _U64P,
+                                   ctypes.c_int64, _I32P]
     lib.oracle_count_solutions.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _U64P]
     lib.oracle_state.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P, _F64P]
     lib.oracle_qaoa.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P, _F64P, _F64P]
     lib.oracle_qaoa_grad.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P,
                                      ctypes.c_double, ctypes.c_double, _F64P, _F64P, _F64P]
     lib.oracle_num_threads.argtypes = []
-    for fn in (lib.oracle_cost, lib.oracle_count_solutions, lib.oracle_state,
+    for fn in (lib.oracle_cost, lib.oracle_cost_at, lib.oracle_count_solutions, lib.oracle_state,
                lib.oracle_qaoa, lib.oracle_qaoa_grad, lib.oracle_num_threads):
         fn.restype = ctypes.c_int
     _lib = lib
@@ -83,6 +85,18 @@ def cost(clauses, n: int) -> np.ndarray:
     rc = _load().oracle_cost(n, m, k, cl.ctypes.data_as(_I32P), out.ctypes.data_as(_I32P))
     if rc:
         raise ValueError("oracle_cost: invalid instance")
+    return out
+
+
+def cost_at(clauses, n: int, xs) -> np.ndarray:
+    """C(x) at the given basis states (int32)."""
+    cl, m, k = _instance(clauses, n)
+    x = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
+    out = np.empty(x.shape[0], dtype=np.int32)
+    rc = _load().oracle_cost_at(n, m, k, cl.ctypes.data_as(_I32P), x.ctypes.data_as(_U64P),
+                                x.shape[0], out.ctypes.data_as(_I32P))
+    if rc:
+        raise ValueError("oracle_cost_at: invalid arguments")
     return out
 
 

@@ -39,19 +39,34 @@ def first_satisfiable(n, k, m, start=0):
         seed += 1
 
 
-def run(name):
+def angles(recipe, p):
+    """'ramp' is the workload's linear ramp; 'ramp_min' negates every beta,
+    which under exp(-i beta H_B) turns the ramp towards lower cost."""
+    g, b = inst.ramp_angles(p)
+    if recipe == "ramp_min":
+        b = -b
+    return g, b
+
+
+def run(name, old=None):
     n, k, r, p, recipe = inst.SINGLE_WORKLOADS[name]
     m = inst.clause_count(n, r)
     t0 = time.time()
-    seed, cl, sols = first_satisfiable(n, k, m)
-    assert recipe == "ramp"
-    g, b = inst.ramp_angles(p)
+    if old and old.get("m") == m and "seed" in old:
+        seed = old["seed"]
+        cl = inst.instance(n, k, m, seed)
+        sols = old["num_solutions"]
+    else:
+        seed, cl, sols = first_satisfiable(n, k, m)
     cost = oracle.cost(cl, n)
-    ps, e, norm = oracle.qaoa(cost, n, g, b)
+    rec = {"n": n, "k": k, "r": r, "m": m, "p": p, "seed": seed, "num_solutions": sols,
+           "oracle_threads": oracle.num_threads(), "results": {}}
+    for rcp in ("ramp", "ramp_min"):
+        g, b = angles(rcp, p)
+        ps, e, norm = oracle.qaoa(cost, n, g, b)
+        rec["results"][rcp] = {"p_success": ps, "expected_cost": e, "norm": norm}
     del cost
-    rec = {"n": n, "k": k, "r": r, "m": m, "p": p, "angles": recipe, "seed": seed,
-           "num_solutions": sols, "p_success": ps, "expected_cost": e, "norm": norm,
-           "oracle_threads": oracle.num_threads(), "oracle_seconds": round(time.time() - t0, 1)}
+    rec["oracle_seconds"] = round(time.time() - t0, 1)
     print(name, rec, flush=True)
     return rec
 
@@ -62,7 +77,7 @@ def main(names):
         with open(OUT) as f:
             data = json.load(f)
     for name in names or list(inst.SINGLE_WORKLOADS):
-        data[name] = run(name)
+        data[name] = run(name, data.get(name))
         with open(OUT, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
 

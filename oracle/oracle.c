@@ -77,6 +77,21 @@ int oracle_cost(int n, int m, int k, const int32_t *lits, int32_t *cost) {
     return 0;
 }
 
+/* C(x) at the given basis states only (same definition as oracle_cost). */
+int oracle_cost_at(int n, int m, int k, const int32_t *lits, const uint64_t *xs,
+                   int64_t count, int32_t *cost) {
+    if (check_instance(n, m, k, lits) || xs == NULL || cost == NULL || count < 0) return -1;
+    for (int64_t q = 0; q < count; q++)
+        if (n < 64 && (xs[q] >> n) != 0) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < count; q++) {
+        int32_t c = 0;
+        for (int i = 0; i < m; i++) c += clause_violated(xs[q], lits + (int64_t)i * k, k);
+        cost[q] = c;
+    }
+    return 0;
+}
+
 /* Number of NAE solutions, #{x : C(x) = 0}, without storing C. Used to keep
  * only satisfiable instances (Section 3.3: evaluation sets are satisfiable). */
 int oracle_count_solutions(int n, int m, int k, const int32_t *lits, uint64_t *count) {

@@ -1,1 +1,19 @@
-"""placeholder"""
+"""qnae: MI355X-native statevector simulation of depth-p QAOA on k-NAE-SAT.
+
+Thin Python binding (argument marshalling only) over the C ABI of
+``libqnae.so`` (see ``include/qnae.h``). Every step of the computation runs in
+the library's HIP kernels; PyTorch provides device memory and streams. There
+is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    QNAEError,
+    Context,
+    Result,
+    build_cost_diagonal,
+    default_context,
+    library_path,
+    load_library,
+    qaoa_run,
+)

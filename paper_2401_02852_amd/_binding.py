@@ -1,0 +1,199 @@
+"""ctypes binding of libqnae.so (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import NamedTuple, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libqnae.so"
+
+QNAE_U8 = 1
+QNAE_U16 = 2
+_STATUS = {0: "QNAE_OK", -1: "QNAE_EINVAL", -2: "QNAE_ENOMEM", -3: "QNAE_EHIP",
+           -4: "QNAE_EBUSY", -5: "QNAE_ETIMEDOUT"}
+
+
+class QNAEError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Result(NamedTuple):
+    p_success: float
+    expected_cost: float
+    norm: float
+
+
+class _CResult(ctypes.Structure):
+    _fields_ = [("p_success", ctypes.c_double), ("expected_cost", ctypes.c_double),
+                ("norm", ctypes.c_double)]
+
+
+class _CKernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load libqnae.so (built in-tree by ``paper_2401_02852_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run `python -m paper_2401_02852_amd.build`")
+        lib = ctypes.CDLL(path)
+        vp = ctypes.c_void_p
+        lib.qnae_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        lib.qnae_destroy.argtypes = [vp]
+        lib.qnae_last_error.argtypes = [vp]
+        lib.qnae_last_error.restype = ctypes.c_char_p
+        lib.qnae_build_cost_diagonal.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), vp]
+        lib.qnae_qaoa_run.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
+                                      ctypes.c_int32, vp, ctypes.POINTER(_CResult), vp]
+        lib.qnae_profile_enable.argtypes = [vp, ctypes.c_int]
+        lib.qnae_profile_read.argtypes = [vp, ctypes.POINTER(_CKernelStat), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
+        for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
+                   lib.qnae_profile_enable, lib.qnae_profile_read):
+            fn.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        msg = load_library().qnae_last_error(ctx).decode(errors="replace")
+        raise QNAEError(status, msg)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    """Owns a qnae_ctx (device scratch, phase tables, pinned staging)."""
+
+    def __init__(self, device: Optional[int] = None):
+        import torch
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib.qnae_create(ctypes.byref(h), self.device))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise QNAEError(-1, "context destroyed")
+        return self._h
+
+    def profile(self, on: bool = True):
+        """Enable or disable event timing of every kernel this context launches."""
+        _check(load_library().qnae_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kind: (launches, total_ms, algorithmic_bytes)}; clears the tallies."""
+        buf = (_CKernelStat * 16)()
+        cnt = ctypes.c_int32(0)
+        _check(load_library().qnae_profile_read(self.handle, buf, 16, ctypes.byref(cnt)))
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].bytes))
+                for i in range(min(cnt.value, 16))}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().qnae_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def default_context() -> Context:
+    import torch
+    dev = torch.cuda.current_device()
+    if dev not in _default:
+        _default[dev] = Context(dev)
+    return _default[dev]
+
+
+def cost_dtype_for(m: int):
+    import torch
+    return torch.uint8 if m <= 255 else torch.uint16
+
+
+def build_cost_diagonal(clauses, n: int, *, out=None, count_solutions: bool = False,
+                        ctx: Optional[Context] = None, stream=None):
+    """C(x) for x in [0, 2^n) on the current device, uint8 when m <= 255 else
+    uint16. ``clauses`` is an [m, k] int array of DIMACS-style literals.
+    Returns the tensor, or (tensor, #solutions) with count_solutions."""
+    import torch
+    cl = np.ascontiguousarray(np.asarray(clauses, dtype=np.int32))
+    if cl.ndim != 2:
+        raise ValueError("clauses must be an [m, k] literal array")
+    m, k = cl.shape
+    dtype = cost_dtype_for(m)
+    if out is None:
+        out = torch.empty(1 << n, dtype=dtype, device="cuda")
+    code = QNAE_U8 if out.dtype == torch.uint8 else QNAE_U16
+    ctx = ctx or default_context()
+    sols = ctypes.c_uint64(0)
+    _check(load_library().qnae_build_cost_diagonal(
+        ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1),
+        ctypes.c_void_p(out.data_ptr()), code,
+        ctypes.byref(sols) if count_solutions else None, _stream(stream)))
+    return (out, int(sols.value)) if count_solutions else out
+
+
+def qaoa_run(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[Context] = None,
+             stream=None) -> Result:
+    """Depth-p QAOA from |+> on the cost diagonal; returns (p_success,
+    expected_cost, norm). ``state``, if given, is a complex64 device tensor of
+    2^n entries that receives the final state."""
+    import torch
+    g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
+    if g.shape != b.shape or g.ndim != 1:
+        raise ValueError("gammas and betas must be 1-D of equal length")
+    if cost.numel() != (1 << n):
+        raise ValueError(f"cost has {cost.numel()} entries, expected 2^{n}")
+    if state is not None and (state.dtype != torch.complex64 or state.numel() != (1 << n)):
+        raise ValueError("state must be complex64 with 2^n entries")
+    code = QNAE_U8 if cost.dtype == torch.uint8 else QNAE_U16
+    ctx = ctx or default_context()
+    res = _CResult()
+    p = g.shape[0]
+    _check(load_library().qnae_qaoa_run(
+        ctx.handle, ctypes.c_void_p(cost.data_ptr()), code, n, m,
+        g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
+        ctypes.c_void_p(state.data_ptr()) if state is not None else None,
+        ctypes.byref(res), _stream(stream)))
+    return Result(res.p_success, res.expected_cost, res.norm)

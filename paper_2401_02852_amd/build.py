@@ -1,0 +1,46 @@
+"""Build libqnae.so (HIP, gfx950) in-tree, next to this file.
+
+    python -m paper_2401_02852_amd.build
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libqnae.so")
+SOURCES = ["qnae.cpp", "cost.hip", "sweep.hip"]
+ARCH = os.environ.get("QNAE_OFFLOAD_ARCH", "gfx950")
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    objs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(CSRC, src + ".o")
+        cmd = [hipcc, "-c", "-fPIC", "-O3", "-std=c++17", "-Wall", "-Wno-unused-result",
+               f"--offload-arch={ARCH}"]
+        if src.endswith(".hip"):
+            # Keep the compiler from forming packed FP32 instructions.
+            cmd += ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+        cmd += ["-o", obj, path]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-q" not in sys.argv))

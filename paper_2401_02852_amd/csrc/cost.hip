@@ -1,0 +1,134 @@
+// Cost diagonal kernel: C(x) = number of NAE-violated clauses, for every basis
+// state x (Section 3.2, eq. knaesatobj; Appendix A.2, eq. demorgannae).
+//
+// Bit-sliced: each thread owns an aligned run of 32 consecutive states. For one
+// clause, its violation pattern over the run is a 32-bit word: the part of the
+// clause on variables >= 5 is constant over the run (one compare against the
+// thread's index), and the part on variables 0..4 is a per-clause table built
+// on the host. The per-state counters are kept as NP bit-planes (a vertical
+// ripple-carry counter), so one clause costs about 2 NP + 6 integer operations
+// per 32 states. At the end the planes are transposed into bytes (uint8) or
+// half-words (uint16) and written with 16-byte stores.
+#include "internal.h"
+
+namespace qnae {
+namespace {
+
+template <int NP, bool WIDE, bool U16>
+__global__ __launch_bounds__(256) void cost_kernel(const CostArgs a) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nthreads = a.n >= 5 ? (1ull << (a.n - 5)) : 1ull;
+    uint32_t zeros = 0;
+    if (tid < nthreads) {
+        const uint64_t xbase = tid << 5;
+        const uint32_t xlo = (uint32_t)xbase, xhi = (uint32_t)(xbase >> 32);
+        uint32_t plane[NP];
+#pragma unroll
+        for (int b = 0; b < NP; ++b) plane[b] = 0u;
+        for (int i = 0; i < a.num_clauses; ++i) {
+            const ClauseRec r = a.clauses[i];
+            const uint32_t hlo = (xlo ^ r.pat_lo) & r.mask_hi_lo;
+            bool none, all;
+            if (WIDE) {
+                const uint32_t hhi = (xhi ^ r.pat_hi) & r.mask_hi_hi;
+                none = (hlo | hhi) == 0u;
+                all = (hlo == r.mask_hi_lo) && (hhi == r.mask_hi_hi);
+            } else {
+                none = hlo == 0u;
+                all = hlo == r.mask_hi_lo;
+            }
+            uint32_t carry = (none ? r.zero_tab : 0u) | (all ? r.full_tab : 0u);
+#pragma unroll
+            for (int b = 0; b < NP; ++b) {
+                const uint32_t t = plane[b] & carry;
+                plane[b] ^= carry;
+                carry = t;
+            }
+        }
+        const uint32_t valid = a.n >= 5 ? 0xffffffffu : ((1u << (1u << a.n)) - 1u);
+        uint32_t any = 0u;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) any |= plane[b];
+        zeros = (uint32_t)__popc(~any & valid);
+
+        if (!U16) {
+            // 32 bytes: byte j = sum_b bit j of plane b, shifted to bit b.
+            uint32_t word[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                uint32_t wv = 0u;
+#pragma unroll
+                for (int b = 0; b < NP; ++b) {
+                    const uint32_t nib = (plane[b] >> (4 * q)) & 0xfu;
+                    wv |= ((nib * 0x00204081u) & 0x01010101u) << b;
+                }
+                word[q] = wv;
+            }
+            uint8_t* out = (uint8_t*)a.cost + xbase;
+            if (a.n >= 5) {
+                ((uint4*)out)[0] = make_uint4(word[0], word[1], word[2], word[3]);
+                ((uint4*)out)[1] = make_uint4(word[4], word[5], word[6], word[7]);
+            } else {
+                for (uint32_t j = 0; j < (1u << a.n); ++j) out[j] = (uint8_t)(word[j >> 2] >> (8 * (j & 3)));
+            }
+        } else {
+            // 64 bytes: half-word j = sum_b bit j of plane b, shifted to bit b.
+            uint32_t word[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                uint32_t wv = 0u;
+#pragma unroll
+                for (int b = 0; b < NP; ++b) {
+                    const uint32_t pair = (plane[b] >> (2 * q)) & 3u;
+                    wv |= ((pair * 0x8001u) & 0x10001u) << b;
+                }
+                word[q] = wv;
+            }
+            uint16_t* out = (uint16_t*)a.cost + xbase;
+            if (a.n >= 5) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ((uint4*)out)[q] = make_uint4(word[4 * q], word[4 * q + 1], word[4 * q + 2], word[4 * q + 3]);
+            } else {
+                for (uint32_t j = 0; j < (1u << a.n); ++j) out[j] = (uint16_t)(word[j >> 1] >> (16 * (j & 1)));
+            }
+        }
+    }
+    if (a.zeros) {
+        __shared__ uint32_t blk;
+        if (threadIdx.x == 0) blk = 0u;
+        __syncthreads();
+        // wave-level sum first, then one LDS atomic per wave
+        uint32_t z = zeros;
+        for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off);
+        if ((threadIdx.x & 63) == 0 && z) atomicAdd(&blk, z);
+        __syncthreads();
+        if (threadIdx.x == 0 && blk) atomicAdd(a.zeros, (unsigned long long)blk);
+    }
+}
+
+template <int NP, bool U16>
+hipError_t launch_np(const CostArgs& a, hipStream_t s) {
+    const uint64_t nthreads = a.n >= 5 ? (1ull << (a.n - 5)) : 1ull;
+    const uint64_t blocks = (nthreads + 255) / 256;
+    if (a.n > 32)
+        hipLaunchKernelGGL((cost_kernel<NP, true, U16>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((cost_kernel<NP, false, U16>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cost(const CostArgs& a, int dtype, hipStream_t s) {
+    // Enough planes to count up to the number of (normalised) clauses.
+    const int need = 32 - __builtin_clz((unsigned)a.num_clauses | 1u);
+    if (dtype == 1) {
+        if (need <= 6) return launch_np<6, false>(a, s);
+        return launch_np<8, false>(a, s);
+    }
+    if (need <= 12) return launch_np<12, true>(a, s);
+    return launch_np<16, true>(a, s);
+}
+
+}  // namespace qnae
