@@ -40,40 +40,52 @@ hipError_t launch_cost(const CostArgs& a, int dtype, hipStream_t s);
 // Mixer of one layer in the form used on the device. With t = tan(beta) when
 // |tan(beta)| <= 1:  R(beta) = cos(beta) (I - i t X); otherwise, with
 // t = -cot(beta):    R(beta) = (-i sin(beta)) X (I - i t X).
-// Each butterfly therefore costs two FMAs per amplitude; `swap` applies the
-// extra X, and the scalar factor is folded into the next phase table (or the
-// readout).
+// Each butterfly therefore costs two FMAs per amplitude. The scalar factor is
+// folded into the next phase table (or the readout). The X of the cot form
+// (`flip`) is not applied: X on every qubit of the layer is a relabelling
+// x -> NOT x of the stored state, so the runtime tracks the parity of flipped
+// layers and reads the cost at the complemented index where it matters
+// (phase and readout), undoing the relabelling only if the final state is
+// returned.
 struct MixForm {
     float t;
-    int swap;
+    int flip;
 };
 
-enum SweepFlags {
-    SW_INIT = 1,    // start from the phase table instead of loading psi
-    SW_PHASE = 2,   // apply the phase table between the pre- and post-mixers
-    SW_REDUCE = 4,  // write block partial sums of the readout
-    SW_STORE = 8,   // store psi back
-    SW_SCALE = 16,  // multiply by store_scale when storing (final state)
+// Sweep kinds: which steps a sweep performs.
+enum SweepKind {
+    SK_FIRST = 0,     // phase table 0 as initial state, mix, store
+    SK_MIDDLE = 1,    // load, mix, store
+    SK_BOUNDARY = 2,  // load, mix (layer l), phase (l + 1), mix (l + 1), store
+    SK_FINAL = 3,     // load, mix, readout partials (optional store)
+    SK_P0 = 4,        // phase table 0 as state, readout (p = 0)
 };
 
 struct SweepArgs {
     float2* psi;
     const void* cost;
     const float2* lut;     // phase table of this sweep (lut_len entries)
-    double* partials;      // 3 doubles per block when SW_REDUCE
+    double* partials;      // 3 doubles per block for readout kinds
     int32_t n;
-    int32_t c;             // tile: bits [0, c) and [H, H + TB - c)
-    int32_t H;
+    int32_t nw;            // n - TB: block-index bits
+    uint64_t tile_bits;    // global bits spanned by a tile
+    uint8_t pos[16];       // tile bit i -> bit pos[i] of x (pos[0..3] = 0..3)
+    uint64_t wmask;        // bits of x outside the tile (filled by the tile index)
     int32_t lut_len;
     uint32_t pre_mask;     // tile bits mixed before the phase
     uint32_t post_mask;    // tile bits mixed after the phase
-    MixForm pre, post;
-    float2 store_scale;
-    int32_t flags;
-    int32_t xcd_remap;     // spread consecutive tiles over one XCD
+    float pre_t, post_t;
+    float2 store_scale;    // readout kinds with store: final scalar factor
+    int32_t store;         // readout kinds: also store the state
+    int32_t cflip;         // read the cost at the complemented index
+    int32_t persistent;    // one block per resident slot, prefetching the next tile
 };
 
-hipError_t launch_sweep(int tb, int dtype, const SweepArgs& a, hipStream_t s);
+// Launches a persistent grid of at most (resident blocks per CU) x (CUs)
+// blocks; *grid_out receives the grid size (readout kinds write 3 partial sums
+// per block).
+hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out);
+hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s);
 
 // Whole circuit for n <= 14 in one workgroup (state resident in LDS).
 struct ResidentArgs {

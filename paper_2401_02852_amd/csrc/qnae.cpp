@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -126,8 +127,10 @@ struct qnae_ctx {
     DevBuf state, partials, luts, clauses, forms, small;  // small: zeros counter + 3 result doubles
     HostBuf h_luts, h_clauses, h_forms, h_small;
     hipEvent_t staging_done = nullptr;  // last async copy out of pinned staging
-    int tile_bits = 14;                 // tile size of the plain sweeps
+    int tile_bits = 13;                 // tile size of the plain sweeps (log2 amplitudes)
     int min_low_run = 4;                // minimum contiguous low run (log2 amplitudes)
+    int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes
+    int persistent = 0;                 // persistent prefetching sweep grids
 };
 
 namespace {
@@ -179,11 +182,11 @@ Layer mixer_form(double beta, int n) {
     Layer L;
     if (std::fabs(sb) <= std::fabs(cb)) {
         L.form.t = (float)(sb / cb);
-        L.form.swap = 0;
+        L.form.flip = 0;
         L.scale = std::pow(std::complex<double>(cb, 0.0), n);
     } else {
         L.form.t = (float)(-cb / sb);
-        L.form.swap = 1;
+        L.form.flip = 1;
         L.scale = std::pow(std::complex<double>(0.0, -sb), n);
     }
     return L;
@@ -216,35 +219,75 @@ std::complex<double> build_tables(int n, int m, const double* gammas, const doub
 // ---------------------------------------------------------------------------
 
 struct Group {
-    int c, H;
-    uint32_t mask;  // tile bits this group mixes
+    std::vector<int> pos;  // global bit of each tile bit
+    uint32_t mask;         // tile bits this group mixes
 };
 
 struct Op {
     int group;
-    int flags;
+    int kind;                              // qnae::SweepKind
     int pre_layer, post_layer, lut_layer;  // -1 when unused
 };
 
-// Groups: A = the contiguous low TB bits; the high bits [TB, n) split into
-// pieces of at most TB - c_min bits, each tiled together with the low run
-// [0, c).
-std::vector<Group> make_groups(int n, int TB, int cmin) {
+// Qubit groups of the sweeps. Group A holds the low run [0, cA) of x and a
+// few high bits; every other group holds the low run [0, cmin) (not mixed,
+// for contiguous global accesses) and a piece of the remaining high bits.
+// Bits at or above `page` select a 2 MiB page of the state (8-byte
+// amplitudes); a tile that spans k of them touches 2^k pages, so these bits
+// are dealt out evenly over the groups to keep every tile within a few TLB
+// entries.
+std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
     std::vector<Group> g;
-    g.push_back({TB, TB, (1u << TB) - 1u});
+    Group A;
+    if (n <= TB) {
+        for (int i = 0; i < TB; ++i) A.pos.push_back(i);
+        A.mask = (1u << TB) - 1u;
+        g.push_back(A);
+        return g;
+    }
     const int rest = n - TB;
-    if (rest <= 0) return g;
     const int h = (rest + (TB - cmin) - 1) / (TB - cmin);
-    const int s = (rest + h - 1) / h;
-    const int cB = TB - s;
-    int lo = TB;
+    std::vector<int> P;
+    for (int b = std::max(page, TB); b < n; ++b) P.push_back(b);
+    const int target = ((int)P.size() + h) / (h + 1);
+    const int a = std::min(std::min(target, TB - cmin), (int)P.size());
+    const int cA = TB - a;
+    std::vector<int> atop(P.end() - a, P.end());
+    for (int i = 0; i < cA; ++i) A.pos.push_back(i);
+    for (int b : atop) A.pos.push_back(b);
+    A.mask = (1u << TB) - 1u;
+    g.push_back(A);
+    // bits left for the other groups, page bits first
+    std::vector<int> RP, RN;
+    for (int b = cA; b < n; ++b) {
+        if (std::find(atop.begin(), atop.end(), b) != atop.end()) continue;
+        (b >= page ? RP : RN).push_back(b);
+    }
+    const int R = (int)(RP.size() + RN.size());
+    std::vector<std::vector<int>> piece(h);
+    std::vector<int> size(h);
+    for (int i = 0; i < h; ++i) size[i] = R / h + (i < R % h ? 1 : 0);
+    for (size_t q = 0; q < RP.size(); ++q) piece[q % h].push_back(RP[q]);
+    size_t nx = 0;
+    for (int i = 0; i < h; ++i)
+        while ((int)piece[i].size() < size[i]) piece[i].push_back(RN[nx++]);
     for (int i = 0; i < h; ++i) {
-        const int size = rest / h + (i < rest % h ? 1 : 0);
-        const int hi = lo + size;
-        const int H = hi - s;
-        const uint32_t mask = ((1u << size) - 1u) << (cB + (lo - H));
-        g.push_back({cB, H, mask});
-        lo = hi;
+        Group B;
+        std::vector<int> bits = piece[i];
+        // fill up to TB - cmin bits with unmixed bits just above the low run
+        std::vector<int> fill;
+        for (int b = cmin; (int)(bits.size() + fill.size()) < TB - cmin; ++b)
+            if (std::find(bits.begin(), bits.end(), b) == bits.end()) fill.push_back(b);
+        std::vector<int> all = fill;
+        all.insert(all.end(), bits.begin(), bits.end());
+        std::sort(all.begin(), all.end());
+        for (int b = 0; b < cmin; ++b) B.pos.push_back(b);
+        B.mask = 0u;
+        for (int b : all) {
+            if (std::find(bits.begin(), bits.end(), b) != bits.end()) B.mask |= 1u << B.pos.size();
+            B.pos.push_back(b);
+        }
+        g.push_back(B);
     }
     return g;
 }
@@ -254,36 +297,35 @@ std::vector<Group> make_groups(int n, int TB, int cmin) {
 // every layer after the first costs (number of groups - 1) sweeps. The first
 // sweep starts from the phase table (no load) and the last one only reads the
 // state for the readout unless the final state is kept.
-std::vector<Op> make_plan(int ngroups, int p, bool keep) {
+std::vector<Op> make_plan(int ngroups, int p) {
     using namespace qnae;
-    const int fin = SW_REDUCE | (keep ? SW_STORE | SW_SCALE : 0);
     std::vector<Op> ops;
     if (p == 0) {
-        ops.push_back({0, SW_INIT | SW_REDUCE | (keep ? SW_STORE : 0), -1, -1, 0});
+        ops.push_back({0, SK_P0, -1, -1, 0});
         return ops;
     }
-    ops.push_back({0, SW_INIT | SW_STORE, -1, 0, 0});
+    ops.push_back({0, SK_FIRST, -1, 0, 0});
     std::vector<int> pending;  // groups not yet mixed for layer l
     for (int g = 1; g < ngroups; ++g) pending.push_back(g);
     for (int l = 0;; ++l) {
         if (pending.empty()) {  // one group: the previous sweep mixed it already
             if (l == p - 1) {
-                ops.push_back({0, fin, -1, -1, -1});
+                ops.push_back({0, SK_FINAL, -1, -1, -1});
                 return ops;
             }
-            ops.push_back({0, SW_PHASE | SW_STORE, -1, l + 1, l + 1});
+            ops.push_back({0, SK_BOUNDARY, -1, l + 1, l + 1});
             continue;
         }
         int last = pending.back();
         for (int g : pending)
             if (g != 0) last = g;
         for (int g : pending)
-            if (g != last) ops.push_back({g, SW_STORE, l, -1, -1});
+            if (g != last) ops.push_back({g, SK_MIDDLE, l, -1, -1});
         if (l == p - 1) {
-            ops.push_back({last, fin, l, -1, -1});
+            ops.push_back({last, SK_FINAL, l, -1, -1});
             return ops;
         }
-        ops.push_back({last, SW_PHASE | SW_STORE, l, l + 1, l + 1});
+        ops.push_back({last, SK_BOUNDARY, l, l + 1, l + 1});
         pending.clear();
         for (int g = 0; g < ngroups; ++g)
             if (g != last) pending.push_back(g);
@@ -319,6 +361,11 @@ int qnae_create(qnae_ctx** out, int device) {
     if (const char* tb = std::getenv("QNAE_TILE_BITS")) {
         const int v = std::atoi(tb);
         if (v >= 12 && v <= 14) ctx->tile_bits = v;
+    }
+    if (const char* ps = std::getenv("QNAE_PERSISTENT")) ctx->persistent = std::atoi(ps) != 0;
+    if (const char* pb = std::getenv("QNAE_PAGE_BIT")) {
+        const int v = std::atoi(pb);
+        if (v >= 4 && v <= 64) ctx->page_bit = v;
     }
     *out = ctx;
     return QNAE_OK;
@@ -468,10 +515,15 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
             HIP_TRY(ctx->state.reserve(sizeof(float2) << n));
             psi = (float2*)ctx->state.ptr;
         }
-        const int64_t blocks = 1ll << (n - TB);
+        const int64_t blocks = 1ll << (n - TB);  // upper bound on any sweep's grid
+        int64_t reduce_blocks = 0;
         HIP_TRY(ctx->partials.reserve(sizeof(double) * 3 * (size_t)blocks));
-        const std::vector<Group> groups = make_groups(n, TB, ctx->min_low_run);
-        const std::vector<Op> ops = make_plan((int)groups.size(), p, keep);
+        const std::vector<Group> groups = make_groups(n, TB, ctx->min_low_run, ctx->page_bit);
+        const std::vector<Op> ops = make_plan((int)groups.size(), p);
+        // flips_before[l]: parity of cot-form layers among 0 .. l-1
+        std::vector<int> flips_before(T + 1, 0);
+        for (int l = 0; l < p; ++l) flips_before[l + 1] = flips_before[l] ^ forms[l].flip;
+        const int cb = cost_dtype == QNAE_U8 ? 1 : 2;
         for (const Op& op : ops) {
             const Group& g = groups[op.group];
             SweepArgs a;
@@ -480,29 +532,42 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
             a.lut = op.lut_layer >= 0 ? (const float2*)ctx->luts.ptr + (size_t)op.lut_layer * lut_len : nullptr;
             a.partials = (double*)ctx->partials.ptr;
             a.n = n;
-            a.c = g.c;
-            a.H = g.H;
+            a.nw = n - TB;
+            a.tile_bits = 0;
+            for (int i = 0; i < TB; ++i) {
+                a.pos[i] = (uint8_t)g.pos[i];
+                a.tile_bits |= 1ull << g.pos[i];
+            }
+            a.wmask = ((1ull << n) - 1ull) & ~a.tile_bits;
+            a.persistent = ctx->persistent;
             a.lut_len = lut_len;
             a.pre_mask = op.pre_layer >= 0 ? g.mask : 0u;
             a.post_mask = op.post_layer >= 0 ? g.mask : 0u;
-            a.pre = op.pre_layer >= 0 ? forms[op.pre_layer] : MixForm{0.f, 0};
-            a.post = op.post_layer >= 0 ? forms[op.post_layer] : MixForm{0.f, 0};
+            a.pre_t = op.pre_layer >= 0 ? forms[op.pre_layer].t : 0.f;
+            a.post_t = op.post_layer >= 0 ? forms[op.post_layer].t : 0.f;
             a.store_scale = store_scale;
-            a.flags = op.flags;
-            a.xcd_remap = blocks >= 8 ? 1 : 0;
-            const int f = op.flags;
-            const bool uses_cost = (f & (qnae::SW_INIT | qnae::SW_PHASE | qnae::SW_REDUCE)) != 0;
-            const double per_amp = ((f & qnae::SW_INIT) ? 0.0 : 8.0) + ((f & qnae::SW_STORE) ? 8.0 : 0.0) +
-                                   (uses_cost ? (cost_dtype == QNAE_U8 ? 1.0 : 2.0) : 0.0);
-            const int kind = (f & qnae::SW_INIT) ? K_FIRST
-                             : (f & qnae::SW_REDUCE) ? K_FINAL
-                             : (f & qnae::SW_PHASE) ? K_BOUNDARY
-                                                    : K_MIDDLE;
+            a.store = keep ? 1 : 0;
+            a.cflip = op.kind == qnae::SK_BOUNDARY ? flips_before[op.lut_layer]
+                      : op.kind == qnae::SK_FINAL  ? flips_before[p]
+                                                   : 0;
+            double per_amp = 0.0;
+            int kind = K_MIDDLE;
+            switch (op.kind) {
+                case qnae::SK_FIRST: per_amp = 8.0 + cb; kind = K_FIRST; break;
+                case qnae::SK_MIDDLE: per_amp = 16.0; kind = K_MIDDLE; break;
+                case qnae::SK_BOUNDARY: per_amp = 16.0 + cb; kind = K_BOUNDARY; break;
+                default: per_amp = (op.kind == qnae::SK_FINAL ? 8.0 : 0.0) + cb + (keep ? 8.0 : 0.0); kind = K_FINAL;
+            }
+            uint32_t grid = 0;
             HIP_TRY(timed(ctx, kind, per_amp * std::ldexp(1.0, n), s,
-                          [&] { return qnae::launch_sweep(TB, cost_dtype, a, s); }));
+                          [&] { return qnae::launch_sweep(TB, cost_dtype, op.kind, a, s, &grid); }));
+            if (op.kind == qnae::SK_FINAL || op.kind == qnae::SK_P0) reduce_blocks = grid;
         }
-        HIP_TRY(timed(ctx, K_REDUCE, 24.0 * blocks, s, [&] {
-            return qnae::launch_final_reduce((const double*)ctx->partials.ptr, blocks, out_dev, s);
+        if (keep && p > 0 && flips_before[p])
+            HIP_TRY(timed(ctx, K_FINAL, 16.0 * std::ldexp(1.0, n), s,
+                          [&] { return qnae::launch_reverse(psi, 1ull << n, s); }));
+        HIP_TRY(timed(ctx, K_REDUCE, 24.0 * reduce_blocks, s, [&] {
+            return qnae::launch_final_reduce((const double*)ctx->partials.ptr, reduce_blocks, out_dev, s);
         }));
     }
     HIP_TRY(hipMemcpyAsync(ctx->h_small.ptr, out_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -19,7 +19,7 @@
 // {0, 7..10}, L1 owns {1..5}, L2 owns {6, 11 .. TB-1}.
 //
 // The butterfly on a pair (a, b) is own' = own - i t partner (two FMAs per
-// amplitude); see MixForm for how t, the optional X and the scalar factor
+// amplitude); see MixForm for how t, the dropped X and the scalar factor
 // encode R(beta) = cos(beta) I - i sin(beta) X.
 #include "internal.h"
 
@@ -30,70 +30,100 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
-// Butterfly on register bit S of a register array of size NE.
-template <int NE, int S, bool SWAP>
+// Butterfly on register bit S of a register array of size NE:
+// own' = own - i t partner for both members of each pair.
+template <int NE, int S>
 __device__ __forceinline__ void bfly(float2 (&v)[NE], float t) {
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
         if (j & (1 << S)) continue;
         const float2 a = v[j], b = v[j | (1 << S)];
-        const float2 na = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
-        const float2 nb = make_float2(fmaf(t, a.y, b.x), fmaf(-t, a.x, b.y));
-        if (SWAP) {
-            v[j] = nb;
-            v[j | (1 << S)] = na;
-        } else {
-            v[j] = na;
-            v[j | (1 << S)] = nb;
-        }
+        v[j] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
+        v[j | (1 << S)] = make_float2(fmaf(t, a.y, b.x), fmaf(-t, a.x, b.y));
     }
 }
 
-template <bool SWAP>
-__device__ __forceinline__ void mix_slots32(float2 (&v)[32], uint32_t sm, float t) {
-    if (sm & 1u) bfly<32, 0, SWAP>(v, t);
-    if (sm & 2u) bfly<32, 1, SWAP>(v, t);
-    if (sm & 4u) bfly<32, 2, SWAP>(v, t);
-    if (sm & 8u) bfly<32, 3, SWAP>(v, t);
-    if (sm & 16u) bfly<32, 4, SWAP>(v, t);
+__device__ __forceinline__ void mix32(float2 (&v)[32], uint32_t sm, float t) {
+    if (sm & 1u) bfly<32, 0>(v, t);
+    if (sm & 2u) bfly<32, 1>(v, t);
+    if (sm & 4u) bfly<32, 2>(v, t);
+    if (sm & 8u) bfly<32, 3>(v, t);
+    if (sm & 16u) bfly<32, 4>(v, t);
 }
 
-__device__ __forceinline__ void mix32(float2 (&v)[32], uint32_t sm, const MixForm f) {
-    if (sm == 0u) return;
-    if (f.swap) mix_slots32<true>(v, sm, f.t);
-    else mix_slots32<false>(v, sm, f.t);
-}
+// Bit positions of layout L2 (tile bits held by slots, lanes and waves). For
+// TB <= 13 the slots also hold tile bits 4 and 5, so a group whose low tile
+// bits are an unmixed run of 4 (a high-qubit tile) mixes everything in L0 and
+// L2 and skips L1.
+template <int TB>
+struct L2Map;
+template <>
+struct L2Map<14> {
+    static constexpr int slot[5] = {6, 11, 12, 13, 7};
+    static constexpr int lane[6] = {0, 1, 2, 3, 4, 5};
+    static constexpr int wave[3] = {8, 9, 10};
+};
+template <>
+struct L2Map<13> {
+    static constexpr int slot[5] = {6, 11, 12, 4, 5};
+    static constexpr int lane[6] = {0, 1, 2, 3, 7, 8};
+    static constexpr int wave[2] = {9, 10};
+};
+template <>
+struct L2Map<12> {
+    static constexpr int slot[5] = {6, 11, 4, 5, 7};
+    static constexpr int lane[6] = {0, 1, 2, 3, 8, 9};
+    static constexpr int wave[1] = {10};
+};
 
-// Tile-local element index of register slot j in each layout.
+// Tile-local element index of register slot j in each layout, split into a
+// thread part and a slot part with disjoint bits (e = t | s).
+//   L0  slots = e{0, 7, 8, 9, 10}, lanes = e{1..6},  waves = e{11..}
+//   L1  slots = e{1..5},           lanes = e{0, 6..10}, waves = e{11..}
+//   L2  see L2Map
+// Round ownership: L0 mixes tile bits {0, 7..10}; L1 mixes {1..5}; L2 mixes
+// {6, 11..}, and also {4, 5} when L1 has nothing else to do (TB <= 13).
 template <int TB>
 struct Lay {
     static constexpr int WB = TB - 11;  // wave bits
-    __device__ static __forceinline__ uint32_t e0(uint32_t lane, uint32_t wave, int j) {
-        return (uint32_t)(j & 1) | (lane << 1) | ((uint32_t)(j >> 1) << 7) | (wave << 11);
-    }
-    __device__ static __forceinline__ uint32_t e1(uint32_t lane, uint32_t wave, int j) {
-        return (lane & 1u) | ((uint32_t)j << 1) | ((lane >> 1) << 6) | (wave << 11);
-    }
-    __device__ static __forceinline__ uint32_t e2(uint32_t lane, uint32_t wave, int j) {
-        return lane | ((uint32_t)(j & 1) << 6) | ((uint32_t)((j >> 1) & ((1 << WB) - 1)) << 11) |
-               ((uint32_t)(j >> (1 + WB)) << 7) | (wave << (11 - WB));
-    }
-    // Thread and slot parts of e0 / e2 (disjoint bit sets, so e = t | s).
+    using M = L2Map<TB>;
+    static constexpr bool L2_HAS_45 = TB <= 13;
     __device__ static __forceinline__ uint32_t t0(uint32_t lane, uint32_t wave) { return (lane << 1) | (wave << 11); }
     __device__ static __forceinline__ constexpr uint32_t s0(int j) { return (uint32_t)(j & 1) | ((uint32_t)(j >> 1) << 7); }
-    __device__ static __forceinline__ uint32_t t1(uint32_t lane, uint32_t wave) { return (lane & 1u) | ((lane >> 1) << 6) | (wave << 11); }
+    __device__ static __forceinline__ uint32_t t1(uint32_t lane, uint32_t wave) {
+        return (lane & 1u) | ((lane >> 1) << 6) | (wave << 11);
+    }
     __device__ static __forceinline__ constexpr uint32_t s1(int j) { return (uint32_t)j << 1; }
-    __device__ static __forceinline__ uint32_t t2(uint32_t lane, uint32_t wave) { return lane | (wave << (11 - WB)); }
+    __device__ static __forceinline__ uint32_t t2(uint32_t lane, uint32_t wave) {
+        uint32_t e = 0u;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) e |= ((lane >> i) & 1u) << M::lane[i];
+#pragma unroll
+        for (int i = 0; i < WB; ++i) e |= ((wave >> i) & 1u) << M::wave[i];
+        return e;
+    }
     __device__ static __forceinline__ constexpr uint32_t s2(int j) {
-        return ((uint32_t)(j & 1) << 6) | ((uint32_t)((j >> 1) & ((1 << WB) - 1)) << 11) | ((uint32_t)(j >> (1 + WB)) << 7);
+        uint32_t e = 0u;
+        for (int i = 0; i < 5; ++i) e |= (uint32_t)((j >> i) & 1) << M::slot[i];
+        return e;
     }
-    // Slot masks of the tile bits each round owns.
-    __device__ static __forceinline__ uint32_t sm0(uint32_t m) {
-        return (m & 1u) | (((m >> 7) & 15u) << 1);
+    // Does L1 mix tile bits 4 and 5 for mask m?
+    __device__ static __forceinline__ bool r1_takes_45(uint32_t m) { return !L2_HAS_45 || (m & 0xeu) != 0u; }
+    // Slot masks of the tile bits each round mixes.
+    __device__ static __forceinline__ uint32_t sm0(uint32_t m) { return (m & 1u) | (((m >> 7) & 15u) << 1); }
+    __device__ static __forceinline__ uint32_t sm1(uint32_t m) {
+        return r1_takes_45(m) ? (m >> 1) & 31u : (m >> 1) & 7u;
     }
-    __device__ static __forceinline__ uint32_t sm1(uint32_t m) { return (m >> 1) & 31u; }
     __device__ static __forceinline__ uint32_t sm2(uint32_t m) {
-        return ((m >> 6) & 1u) | (((m >> 11) & ((1u << WB) - 1u)) << 1);
+        const bool with45 = !r1_takes_45(m);
+        uint32_t sm = 0u;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const int eb = M::slot[i];
+            const bool own = eb == 6 || eb >= 11 || (with45 && (eb == 4 || eb == 5));
+            if (own && ((m >> eb) & 1u)) sm |= 1u << i;
+        }
+        return sm;
     }
 };
 
@@ -146,163 +176,242 @@ __device__ __forceinline__ void from_lds(const float2* lds, float2 (&v)[32], uin
     }
 }
 
-template <int TB, typename CT>
+// One sweep. The grid is persistent: block b handles tiles b, b + gridDim.x,
+// ... and loads the next tile's amplitudes and cost values into registers
+// before it works on the current one, so every workgroup keeps global loads
+// in flight while it mixes.
+template <int TB, typename CT, int KIND>
 __global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs a) {
     constexpr int WB = TB - 11;
     constexpr int NT = 64 << WB;
+    constexpr bool INIT = KIND == SK_FIRST || KIND == SK_P0;  // start from phase table 0
+    constexpr bool PRE = KIND == SK_MIDDLE || KIND == SK_BOUNDARY || KIND == SK_FINAL;
+    constexpr bool PHASE = KIND == SK_BOUNDARY;
+    constexpr bool POST = KIND == SK_FIRST || KIND == SK_BOUNDARY;
+    constexpr bool REDUCE = KIND == SK_FINAL || KIND == SK_P0;
+    constexpr bool NEED_COST = INIT || PHASE || REDUCE;
+    constexpr bool NEED_LUT = INIT || PHASE;
+    constexpr bool LUT_LDS = sizeof(CT) == 1;
+    constexpr int PK = 4 / (int)sizeof(CT);  // cost values per packed register
+    constexpr int NC = NEED_COST ? 32 / PK : 1;
     using L = Lay<TB>;
     __shared__ float2 lds[lds_elems<TB>()];
-    __shared__ float2 lut_s[256];
+    __shared__ float2 lut_s[NEED_LUT && LUT_LDS ? 256 : 1];
     __shared__ double red[3][1 << WB];
 
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    const uint32_t G = gridDim.x, b = blockIdx.x;
-    const uint64_t w = a.xcd_remap ? (uint64_t)(b & 7u) * (G >> 3) + (b >> 3) : (uint64_t)b;
-    const int c = a.c, H = a.H;
-    const uint64_t base = ((w & ((1ull << (H - c)) - 1ull)) << c) | ((w >> (H - c)) << (H + TB - c));
-    const uint32_t lowmask = (1u << c) - 1u;
-    // Global offset of tile element e. It is additive over disjoint bit sets
-    // of e, so an address splits into a per-thread pointer and a per-slot
-    // offset that is the same for every lane (scalar registers).
-    auto scat = [&](uint32_t e) -> uint64_t { return (uint64_t)(e & lowmask) | ((uint64_t)(e >> c) << H); };
-    float2* const p0 = a.psi + base + scat(L::t0(lane, wave));
-    float2* const p2 = a.psi + base + scat(L::t2(lane, wave));
-
-    const int flags = a.flags;
-    const bool need_cost = (flags & (SW_INIT | SW_PHASE | SW_REDUCE)) != 0;
-    const CT* cost = (const CT*)a.cost;
-    constexpr bool LUT_LDS = sizeof(CT) == 1;
-
-    // Cost values of the 32 amplitudes in layout L2, loaded early.
-    // Packed: 4 (uint8) or 2 (uint16) cost values per register.
-    constexpr int PK = 4 / (int)sizeof(CT);
-    uint32_t cvp[32 / PK];
-    const CT* const c2 = cost + base + scat(L::t2(lane, wave));
-    if (need_cost) {
+    const uint32_t ntiles = 1u << a.nw;
+    // Tile bit i sits at bit pos[i] of x; the tile index fills the other
+    // bits (wpos, ascending). Both maps are bit deposits, so offsets are
+    // additive (XOR-linear) over disjoint bit sets of e: an address splits
+    // into a per-thread offset and a per-slot offset that is the same for
+    // every lane (scalar registers).
+    uint64_t bitval[TB];
 #pragma unroll
-        for (int i = 0; i < 32 / PK; ++i) {
-            uint32_t wv = 0u;
+    for (int i = 0; i < TB; ++i) bitval[i] = 1ull << a.pos[i];
+    auto scat = [&](uint32_t e) -> uint64_t {
+        uint64_t x = 0;
 #pragma unroll
-            for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2(PK * i + q))] << (8 * sizeof(CT) * q);
-            cvp[i] = wv;
-        }
-        if (LUT_LDS && (flags & (SW_INIT | SW_PHASE)))
-            for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
-    }
-    // Cost values above m are a caller error; the clamp keeps table reads in bounds.
-    const uint32_t lut_last = (uint32_t)a.lut_len - 1u;
-    auto lut = [&](uint32_t cidx) -> float2 { return LUT_LDS ? lut_s[cidx] : a.lut[min(cidx, lut_last)]; };
-    auto cval = [&](int j) -> uint32_t {
-        return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
+        for (int i = 0; i < TB; ++i)
+            if ((e >> i) & 1u) x |= bitval[i];
+        return x;
     };
+    // Consecutive tiles go to one XCD (blocks are dealt round-robin over the
+    // 8 XCDs), so tiles that share cache lines of the cost diagonal share an L2.
+    const bool remap = ntiles >= 8;
+    // Bit deposit of the tile index into the bits outside the tile (uniform:
+    // scalar ALU only).
+    auto tile_base = [&](uint32_t t) -> uint64_t {
+        uint64_t w = remap ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
+        uint64_t base = 0;
+        for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull) {
+            if (w & 1ull) base |= m & (~m + 1ull);
+            w >>= 1;
+        }
+        return base;
+    };
+    const uint64_t o0 = scat(L::t0(lane, wave));
+    const uint64_t o2 = scat(L::t2(lane, wave));
+    // With cflip the stored state is the true one with every qubit flipped
+    // (see MixForm), so cost values are read at the complemented index:
+    // complemented tile base, thread part and slot.
+    const bool cf = a.cflip != 0;
+    const uint64_t cflipmask = cf ? ((((uint64_t)1 << a.n) - 1ull) ^ a.tile_bits) : 0ull;
+    const uint64_t oc = cf ? scat(L::t2(lane, wave) ^ L::t2(63u, (1u << WB) - 1u)) : o2;
+    const int cj = cf ? 31 : 0;
 
-    float2 v[32];
-    if (flags & SW_INIT) {
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = lut(cval(j));
-    } else {
+    auto load_state = [&](uint64_t base, float2 (&v)[32]) {
+        const float2* const p0 = a.psi + base + o0;
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             const float4 q = *(const float4*)(p0 + scat(L::s0(2 * jj)));
             v[2 * jj] = make_float2(q.x, q.y);
             v[2 * jj + 1] = make_float2(q.z, q.w);
         }
-        const uint32_t m = a.pre_mask;
-        mix32(v, L::sm0(m), a.pre);
-        if (L::sm1(m)) {
-            to_lds<TB, 0>(lds, v, lane, wave);
-            __syncthreads();
-            from_lds<TB, 1>(lds, v, lane, wave);
-            mix32(v, L::sm1(m), a.pre);
-            __syncthreads();
-            to_lds<TB, 1>(lds, v, lane, wave);
-        } else {
-            to_lds<TB, 0>(lds, v, lane, wave);
+    };
+    auto load_cost = [&](uint64_t base, uint32_t (&cv)[NC]) {
+        const CT* const c2 = (const CT*)a.cost + (base ^ cflipmask) + oc;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            uint32_t wv = 0u;
+#pragma unroll
+            for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2((PK * i + q) ^ cj))] << (8 * sizeof(CT) * q);
+            cv[i] = wv;
         }
-        __syncthreads();
-        from_lds<TB, 2>(lds, v, lane, wave);
-        mix32(v, L::sm2(m), a.pre);
-        if (flags & SW_PHASE) {
+    };
+
+    if (NEED_LUT && LUT_LDS)
+        for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
+    // Cost values above m are a caller error; the clamp keeps table reads in bounds.
+    const uint32_t lut_last = (uint32_t)a.lut_len - 1u;
+    auto lut = [&](uint32_t cidx) -> float2 { return LUT_LDS ? lut_s[cidx] : a.lut[min(cidx, lut_last)]; };
+
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    uint32_t t = blockIdx.x;
+    uint64_t base = tile_base(t);
+    float2 v[32];
+    uint32_t cvp[NC];
+    if (!INIT) load_state(base, v);
+    if (NEED_COST) load_cost(base, cvp);
+    __syncthreads();  // phase table visible
+    // A grid smaller than the tile count is persistent and prefetches.
+    const bool persistent = gridDim.x < ntiles;
+    for (;;) {
+        const uint32_t tn = t + gridDim.x;
+        const bool more = tn < ntiles;
+        // Loads for the next tile (the current one again on the last pass,
+        // unused) go out before any work on this tile.
+        const uint64_t nbase = tile_base(more ? tn : t);
+        float2 nv[32];
+        uint32_t ncv[NC];
+        if (persistent) {
+            if (!INIT) load_state(nbase, nv);
+            if (NEED_COST) load_cost(nbase, ncv);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        auto cval = [&](int j) -> uint32_t {
+            return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
+        };
+
+        if (INIT) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) v[j] = lut(cval(j));
+        }
+        if (PRE) {
+            const uint32_t m = a.pre_mask;
+            const float tt = a.pre_t;
+            mix32(v, L::sm0(m), tt);
+            to_lds<TB, 0>(lds, v, lane, wave);
+            if (L::sm1(m)) {
+                __syncthreads();
+                from_lds<TB, 1>(lds, v, lane, wave);
+                mix32(v, L::sm1(m), tt);
+                __syncthreads();
+                to_lds<TB, 1>(lds, v, lane, wave);
+            }
+            __syncthreads();
+            from_lds<TB, 2>(lds, v, lane, wave);
+            mix32(v, L::sm2(m), tt);
+        }
+        if (PHASE) {
 #pragma unroll
             for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], lut(cval(j)));
         }
+        if (POST) {
+            const uint32_t m = a.post_mask;
+            const float tt = a.post_t;
+            mix32(v, L::sm2(m), tt);
+            if (PRE) __syncthreads();
+            to_lds<TB, 2>(lds, v, lane, wave);
+            __syncthreads();
+            if (L::sm1(m)) {
+                from_lds<TB, 1>(lds, v, lane, wave);
+                mix32(v, L::sm1(m), tt);
+                __syncthreads();
+                to_lds<TB, 1>(lds, v, lane, wave);
+                __syncthreads();
+            }
+            from_lds<TB, 0>(lds, v, lane, wave);
+            mix32(v, L::sm0(m), tt);
+            float2* const p0 = a.psi + base + o0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+                *(float4*)(p0 + scat(L::s0(2 * jj))) =
+                    make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
+        }
+        if (REDUCE) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const float pr = fmaf(v[j].x, v[j].x, v[j].y * v[j].y);
+                const uint32_t c = cval(j);
+                s2 += pr;
+                s1 = fmaf((float)c, pr, s1);
+                s0 += c == 0u ? pr : 0.f;
+            }
+            acc0 += s0;
+            acc1 += s1;
+            acc2 += s2;
+        }
+        if (KIND == SK_MIDDLE || (REDUCE && a.store)) {
+            if (REDUCE) {
+#pragma unroll
+                for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], a.store_scale);
+            }
+            float2* const p2 = a.psi + base + o2;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) p2[scat(L::s2(j))] = v[j];
+        }
+        if (!more) break;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = nv[j];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) cvp[i] = ncv[i];
+        t = tn;
+        base = nbase;
+        if (PRE || POST) __syncthreads();  // LDS is rewritten by the next tile
     }
 
-    if (a.post_mask) {
-        const uint32_t m = a.post_mask;
-        mix32(v, L::sm2(m), a.post);
-        __syncthreads();
-        to_lds<TB, 2>(lds, v, lane, wave);
-        __syncthreads();
-        if (L::sm1(m)) {
-            from_lds<TB, 1>(lds, v, lane, wave);
-            mix32(v, L::sm1(m), a.post);
-            __syncthreads();
-            to_lds<TB, 1>(lds, v, lane, wave);
-            __syncthreads();
-        }
-        from_lds<TB, 0>(lds, v, lane, wave);
-        mix32(v, L::sm0(m), a.post);
-        if (flags & SW_SCALE) {
-#pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], a.store_scale);
-        }
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj)
-            *(float4*)(p0 + scat(L::s0(2 * jj))) =
-                make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
-        return;
-    }
-
-    if (flags & SW_REDUCE) {
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const float pr = fmaf(v[j].x, v[j].x, v[j].y * v[j].y);
-            s2 += pr;
-            const uint32_t cj = cval(j);
-            s1 = fmaf((float)cj, pr, s1);
-            s0 += cj == 0u ? pr : 0.f;
-        }
-        double d0 = s0, d1 = s1, d2 = s2;
+    if (REDUCE) {
         for (int off = 32; off > 0; off >>= 1) {
-            d0 += __shfl_xor(d0, off);
-            d1 += __shfl_xor(d1, off);
-            d2 += __shfl_xor(d2, off);
+            acc0 += __shfl_xor(acc0, off);
+            acc1 += __shfl_xor(acc1, off);
+            acc2 += __shfl_xor(acc2, off);
         }
         if (lane == 0) {
-            red[0][wave] = d0;
-            red[1][wave] = d1;
-            red[2][wave] = d2;
+            red[0][wave] = acc0;
+            red[1][wave] = acc1;
+            red[2][wave] = acc2;
         }
         __syncthreads();
         if (threadIdx.x < 3) {
-            double t = 0.0;
-            for (int q = 0; q < (1 << WB); ++q) t += red[threadIdx.x][q];
-            a.partials[(size_t)b * 3 + threadIdx.x] = t;
+            double sum = 0.0;
+            for (int q = 0; q < (1 << WB); ++q) sum += red[threadIdx.x][q];
+            a.partials[(size_t)blockIdx.x * 3 + threadIdx.x] = sum;
         }
     }
-    if (flags & SW_STORE) {
-        if (flags & SW_SCALE) {
-#pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], a.store_scale);
-        }
-#pragma unroll
-        for (int j = 0; j < 32; ++j) p2[scat(L::s2(j))] = v[j];
-    }
+}
+
+// psi[x] <-> psi[N - 1 - x]: undoes an X on every qubit (N >= 4).
+__global__ __launch_bounds__(256) void reverse_kernel(float2* psi, uint64_t N) {
+    const uint64_t i = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 2;
+    if (i >= N / 2) return;
+    float4* lo = (float4*)(psi + i);
+    float4* hi = (float4*)(psi + (N - 2 - i));
+    const float4 a = *lo, b = *hi;
+    *lo = make_float4(b.z, b.w, b.x, b.y);
+    *hi = make_float4(a.z, a.w, a.x, a.y);
 }
 
 // ---------------------------------------------------------------------------
 // Whole circuit in one workgroup for n <= 14 (state resident in LDS).
 // ---------------------------------------------------------------------------
 
-template <bool SWAP>
 __device__ __forceinline__ void mix16(float2 (&v)[16], int nb, float t) {
-    if (nb > 0) bfly<16, 0, SWAP>(v, t);
-    if (nb > 1) bfly<16, 1, SWAP>(v, t);
-    if (nb > 2) bfly<16, 2, SWAP>(v, t);
-    if (nb > 3) bfly<16, 3, SWAP>(v, t);
+    if (nb > 0) bfly<16, 0>(v, t);
+    if (nb > 1) bfly<16, 1>(v, t);
+    if (nb > 2) bfly<16, 2>(v, t);
+    if (nb > 3) bfly<16, 3>(v, t);
 }
 
 template <typename CT>
@@ -313,11 +422,15 @@ __global__ __launch_bounds__(256) void resident_kernel(const ResidentArgs a) {
     const uint32_t N = 1u << n;
     const uint32_t tid = threadIdx.x;
     const CT* cost = (const CT*)a.cost;
+    const uint32_t last = (uint32_t)a.lut_len - 1u;
     const int layers = a.p > 0 ? a.p : 1;
+    // The butterflies drop the X of the cot form; `flip` records that the
+    // stored state is the true one with every qubit flipped.
+    uint32_t flip = 0u;
     for (int l = 0; l < layers; ++l) {
         const float2* lut = a.luts + (size_t)l * a.lut_len;
         for (uint32_t x = tid; x < N; x += 256) {
-            const float2 e = lut[min((uint32_t)cost[x], (uint32_t)a.lut_len - 1u)];
+            const float2 e = lut[min((uint32_t)cost[x ^ flip], last)];
             s[x] = l == 0 ? e : cmul(s[x], e);
         }
         __syncthreads();
@@ -331,24 +444,24 @@ __global__ __launch_bounds__(256) void resident_kernel(const ResidentArgs a) {
                 float2 v[16];
 #pragma unroll
                 for (int i = 0; i < 16; ++i) v[i] = i < (1 << nb) ? s[bs | ((uint32_t)i << g0)] : make_float2(0.f, 0.f);
-                if (f.swap) mix16<true>(v, nb, f.t);
-                else mix16<false>(v, nb, f.t);
+                mix16(v, nb, f.t);
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
                     if (i < (1 << nb)) s[bs | ((uint32_t)i << g0)] = v[i];
             }
             __syncthreads();
         }
+        if (f.flip) flip ^= N - 1u;
     }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
     for (uint32_t x = tid; x < N; x += 256) {
         const float2 q = s[x];
         const float pr = fmaf(q.x, q.x, q.y * q.y);
-        const uint32_t cx = cost[x];
+        const uint32_t cx = cost[x ^ flip];
         s2 += pr;
         s1 = fmaf((float)cx, pr, s1);
         s0 += cx == 0u ? pr : 0.f;
-        if (a.state_out) a.state_out[x] = cmul(q, a.store_scale);
+        if (a.state_out) a.state_out[x ^ flip] = cmul(q, a.store_scale);
     }
     double d0 = s0, d1 = s1, d2 = s2;
     for (int off = 32; off > 0; off >>= 1) {
@@ -391,25 +504,72 @@ __global__ __launch_bounds__(1024) void final_reduce_kernel(const double* partia
     }
 }
 
-template <int TB>
-hipError_t launch_tb(int dtype, const SweepArgs& a, hipStream_t s) {
-    const uint32_t blocks = 1u << (a.n - TB);
-    if (dtype == 1)
-        hipLaunchKernelGGL((sweep_kernel<TB, uint8_t>), dim3(blocks), dim3(64 << (TB - 11)), 0, s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<TB, uint16_t>), dim3(blocks), dim3(64 << (TB - 11)), 0, s, a);
+// Resident workgroups per CU of a kernel, cached after the first query.
+template <typename K>
+int blocks_per_cu(K kernel, int block) {
+    static int cached = 0;
+    if (cached == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1) nb = 1;
+        cached = nb;
+    }
+    return cached;
+}
+
+int num_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <int TB, typename CT, int KIND>
+hipError_t launch_kind(const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
+    const int block = 64 << (TB - 11);
+    auto kern = sweep_kernel<TB, CT, KIND>;
+    const uint64_t ntiles = 1ull << a.nw;
+    const uint64_t cap = a.persistent ? (uint64_t)blocks_per_cu(kern, block) * num_cus() : ntiles;
+    const uint32_t grid = (uint32_t)(ntiles < cap ? ntiles : cap);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a);
+    if (grid_out) *grid_out = grid;
     return hipGetLastError();
+}
+
+template <int TB, typename CT>
+hipError_t launch_tb(int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
+    switch (kind) {
+        case SK_FIRST: return launch_kind<TB, CT, SK_FIRST>(a, s, grid_out);
+        case SK_MIDDLE: return launch_kind<TB, CT, SK_MIDDLE>(a, s, grid_out);
+        case SK_BOUNDARY: return launch_kind<TB, CT, SK_BOUNDARY>(a, s, grid_out);
+        case SK_FINAL: return launch_kind<TB, CT, SK_FINAL>(a, s, grid_out);
+        case SK_P0: return launch_kind<TB, CT, SK_P0>(a, s, grid_out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TB>
+hipError_t launch_tb_dt(int dtype, int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
+    return dtype == 1 ? launch_tb<TB, uint8_t>(kind, a, s, grid_out) : launch_tb<TB, uint16_t>(kind, a, s, grid_out);
 }
 
 }  // namespace
 
-hipError_t launch_sweep(int tb, int dtype, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
     switch (tb) {
-        case 12: return launch_tb<12>(dtype, a, s);
-        case 13: return launch_tb<13>(dtype, a, s);
-        case 14: return launch_tb<14>(dtype, a, s);
+        case 12: return launch_tb_dt<12>(dtype, kind, a, s, grid_out);
+        case 13: return launch_tb_dt<13>(dtype, kind, a, s, grid_out);
+        case 14: return launch_tb_dt<14>(dtype, kind, a, s, grid_out);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s) {
+    const uint64_t threads = N / 4;
+    hipLaunchKernelGGL(reverse_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, psi, N);
+    return hipGetLastError();
 }
 
 hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s) {
