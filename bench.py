@@ -58,15 +58,49 @@ def cpu_baseline(sample_n: int):
                       f"3-NAE-SAT instance, n={n}, m={m}"}
 
 
+def measured_traffic(stats):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    weighted by this run's launches per sweep kind; None when the kernel
+    sources changed since the counters were taken."""
+    from paper_2401_02852_amd import profiling
+    path = os.path.join(ROOT, "profiles", "sweep_n30_p10_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    per_kind, sha = profiling.read_traffic(path)
+    if sha != profiling.kernel_source_hash():
+        return None
+    tot, launches = 0.0, 0
+    for kind, (cnt, _ms, _b) in stats.items():
+        if not kind.startswith("sweep_"):
+            continue
+        match = [v for k, v in per_kind.items() if k.endswith(" " + kind)]
+        if not match:
+            return None
+        tot += cnt * (match[0][0] + match[0][1])
+        launches += cnt
+    return tot / launches if launches else None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="nae3_n30_p10")
-    ap.add_argument("--cpu-sample-n", type=int, default=26)
+    ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy << 20}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(instances would shard by the top state bits across GPUs, not implemented)", file=sys.stderr)
@@ -122,7 +156,7 @@ def main():
                    "angles": "linear ramp", "seed": rec["seed"], "state": "complex64",
                    "cost": "uint8" if m <= 255 else "uint16"},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(stats),
                      "launches": sw_launches, "avg_launch_ms": sw_ms / max(sw_launches, 1),
                      "algorithmic_bytes_per_launch": sw_bytes / max(sw_launches, 1)},
         "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1),
