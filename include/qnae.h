@@ -119,6 +119,45 @@ int qnae_qaoa_run(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype,
                   const double *betas, int32_t p, void *state_dev,
                   qnae_result *out, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent instances per launch (one GPU, ragged sizes).
+ * ------------------------------------------------------------------------- */
+
+/* One cost diagonal of a batch: the arguments of qnae_build_cost_diagonal. */
+typedef struct {
+    const int32_t *clauses;   /* host, m * k literals (NULL when m = 0) */
+    int32_t m, n, k;
+    void *cost_dev;           /* caller-owned device buffer, 2^n of cost_dtype */
+    int32_t cost_dtype;       /* QNAE_U8 (m <= 255) or QNAE_U16 */
+    uint64_t *num_solutions;  /* optional host pointer (the call then waits) */
+} qnae_cost_job;
+
+/* Builds `count` cost diagonals (same definition as qnae_build_cost_diagonal)
+ * with one kernel launch per cost type. Clause arrays are read before the call
+ * returns. Errors: QNAE_EINVAL (names the offending job), QNAE_ENOMEM,
+ * QNAE_EHIP; nothing is enqueued when an argument is invalid. */
+int qnae_build_cost_diagonal_batched(qnae_ctx *ctx, const qnae_cost_job *jobs, int32_t count, void *stream);
+
+/* One QAOA solve of a batch: the arguments of qnae_qaoa_run. */
+typedef struct {
+    const void *cost_dev;  /* device, 2^n of cost_dtype, values in [0, m] */
+    int32_t cost_dtype, n, m, p;
+    const double *gammas;  /* host, p entries (layer 0 first) */
+    const double *betas;   /* host, p entries */
+    void *state_dev;       /* optional device complex64[2^n] for the final state */
+} qnae_instance;
+
+/* Runs `count` independent depth-p QAOA solves (Section 3.3) together and
+ * writes out[i] for inst[i]: instances with n <= 14 each run whole in one
+ * workgroup, larger ones advance one sweep per launch side by side with the
+ * others (tiles of all instances in one grid). Results equal qnae_qaoa_run on
+ * each instance alone up to FP32 rounding order. States the caller does not
+ * provide live in context scratch (sum of 2^n * 8 bytes). Synchronous.
+ * Errors: QNAE_EINVAL (names the offending instance), QNAE_ENOMEM,
+ * QNAE_EHIP. */
+int qnae_qaoa_run_batched(qnae_ctx *ctx, const qnae_instance *inst, int32_t count, qnae_result *out,
+                          void *stream);
+
 /* Kernel timing with HIP events, for measurement. While enabled, the context
  * records an event pair around every kernel it launches, on the stream the
  * kernel runs on, and tallies per kernel kind the number of launches, the

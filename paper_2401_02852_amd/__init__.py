@@ -12,8 +12,10 @@ from ._binding import (  # noqa: F401
     Context,
     Result,
     build_cost_diagonal,
+    build_cost_diagonals,
     default_context,
     library_path,
     load_library,
     qaoa_run,
+    qaoa_run_batched,
 )

@@ -34,6 +34,18 @@ class _CResult(ctypes.Structure):
                 ("norm", ctypes.c_double)]
 
 
+class _CCostJob(ctypes.Structure):
+    _fields_ = [("clauses", ctypes.POINTER(ctypes.c_int32)), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32),
+                ("num_solutions", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class _CInstance(ctypes.Structure):
+    _fields_ = [("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("gammas", ctypes.POINTER(ctypes.c_double)),
+                ("betas", ctypes.POINTER(ctypes.c_double)), ("state_dev", ctypes.c_void_p)]
+
+
 class _CKernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -71,8 +83,12 @@ def load_library():
         lib.qnae_profile_enable.argtypes = [vp, ctypes.c_int]
         lib.qnae_profile_read.argtypes = [vp, ctypes.POINTER(_CKernelStat), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]
+        lib.qnae_build_cost_diagonal_batched.argtypes = [vp, ctypes.POINTER(_CCostJob), ctypes.c_int32, vp]
+        lib.qnae_qaoa_run_batched.argtypes = [vp, ctypes.POINTER(_CInstance), ctypes.c_int32,
+                                              ctypes.POINTER(_CResult), vp]
         for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
-                   lib.qnae_profile_enable, lib.qnae_profile_read):
+                   lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
+                   lib.qnae_qaoa_run_batched):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -197,3 +213,62 @@ def qaoa_run(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[C
         ctypes.c_void_p(state.data_ptr()) if state is not None else None,
         ctypes.byref(res), _stream(stream)))
     return Result(res.p_success, res.expected_cost, res.norm)
+
+
+def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = False,
+                         ctx: Optional[Context] = None, stream=None):
+    """Batched build_cost_diagonal: one tensor per (clauses, n) pair, built
+    with one launch per cost type. Returns the list of tensors, or
+    (tensors, solution counts) with count_solutions."""
+    import torch
+    arrs = [np.ascontiguousarray(np.asarray(c, dtype=np.int32)) for c in clause_sets]
+    if len(arrs) != len(ns):
+        raise ValueError("clause_sets and ns differ in length")
+    if outs is None:
+        outs = [torch.empty(1 << n, dtype=cost_dtype_for(a.shape[0]), device="cuda") for a, n in zip(arrs, ns)]
+    jobs = (_CCostJob * len(arrs))()
+    sols = [ctypes.c_uint64(0) for _ in arrs]
+    for i, (a, n, o) in enumerate(zip(arrs, ns, outs)):
+        if a.ndim != 2:
+            raise ValueError("clauses must be [m, k] literal arrays")
+        m, k = a.shape
+        jobs[i].clauses = a.ctypes.data_as(_I32P) if m else None
+        jobs[i].m, jobs[i].n, jobs[i].k = m, int(n), max(k, 1)
+        jobs[i].cost_dev = o.data_ptr()
+        jobs[i].cost_dtype = QNAE_U8 if o.dtype == torch.uint8 else QNAE_U16
+        jobs[i].num_solutions = ctypes.pointer(sols[i]) if count_solutions else None
+    ctx = ctx or default_context()
+    _check(load_library().qnae_build_cost_diagonal_batched(ctx.handle, jobs, len(arrs), _stream(stream)))
+    return (outs, [int(v.value) for v in sols]) if count_solutions else outs
+
+
+def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, ctx: Optional[Context] = None,
+                     stream=None):
+    """Batched qaoa_run over many instances; returns a list of Result."""
+    import torch
+    count = len(costs)
+    if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
+        raise ValueError("argument lists differ in length")
+    inst = (_CInstance * count)()
+    keep = []
+    for i in range(count):
+        g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas[i], dtype=np.float64)))
+        b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas[i], dtype=np.float64)))
+        if g.shape != b.shape or g.ndim != 1:
+            raise ValueError(f"instance {i}: gammas and betas must be 1-D of equal length")
+        if costs[i].numel() != (1 << int(ns[i])):
+            raise ValueError(f"instance {i}: cost has {costs[i].numel()} entries, expected 2^{ns[i]}")
+        keep += [g, b]
+        st = states[i] if states is not None else None
+        if st is not None and (st.dtype != torch.complex64 or st.numel() != (1 << int(ns[i]))):
+            raise ValueError(f"instance {i}: state must be complex64 with 2^n entries")
+        inst[i].cost_dev = costs[i].data_ptr()
+        inst[i].cost_dtype = QNAE_U8 if costs[i].dtype == torch.uint8 else QNAE_U16
+        inst[i].n, inst[i].m, inst[i].p = int(ns[i]), int(ms[i]), g.shape[0]
+        inst[i].gammas = g.ctypes.data_as(_F64P) if g.shape[0] else None
+        inst[i].betas = b.ctypes.data_as(_F64P) if g.shape[0] else None
+        inst[i].state_dev = st.data_ptr() if st is not None else None
+    res = (_CResult * count)()
+    ctx = ctx or default_context()
+    _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))
+    return [Result(r.p_success, r.expected_cost, r.norm) for r in res]

@@ -14,9 +14,9 @@
 namespace qnae {
 namespace {
 
+// Thread `tid` of one diagonal: states [32 tid, 32 tid + 32).
 template <int NP, bool WIDE, bool U16>
-__global__ __launch_bounds__(256) void cost_kernel(const CostArgs a) {
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cost_chunk(const CostArgs& a, uint64_t tid) {
     const uint64_t nthreads = a.n >= 5 ? (1ull << (a.n - 5)) : 1ull;
     uint32_t zeros = 0;
     if (tid < nthreads) {
@@ -107,6 +107,24 @@ __global__ __launch_bounds__(256) void cost_kernel(const CostArgs a) {
     }
 }
 
+template <int NP, bool WIDE, bool U16>
+__global__ __launch_bounds__(256) void cost_kernel(const CostArgs a) {
+    cost_chunk<NP, WIDE, U16>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Many diagonals at once: instance i owns blocks first[i] .. first[i+1]-1.
+template <int NP, bool WIDE, bool U16>
+__global__ __launch_bounds__(256) void cost_batch_kernel(const CostArgs* args, const uint32_t* first, int count) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const CostArgs a = args[lo];
+    cost_chunk<NP, WIDE, U16>(a, (uint64_t)(blockIdx.x - first[lo]) * blockDim.x + threadIdx.x);
+}
+
 template <int NP, bool U16>
 hipError_t launch_np(const CostArgs& a, hipStream_t s) {
     const uint64_t nthreads = a.n >= 5 ? (1ull << (a.n - 5)) : 1ull;
@@ -129,6 +147,22 @@ hipError_t launch_cost(const CostArgs& a, int dtype, hipStream_t s) {
     }
     if (need <= 12) return launch_np<12, true>(a, s);
     return launch_np<16, true>(a, s);
+}
+
+hipError_t launch_cost_batch(const CostArgs* args, const uint32_t* first, int count, uint32_t blocks, int dtype,
+                             int max_clauses, bool wide, hipStream_t s) {
+    const int need = 32 - __builtin_clz((unsigned)max_clauses | 1u);
+    if (dtype == 1) {
+        if (wide) hipLaunchKernelGGL((cost_batch_kernel<8, true, false>), dim3(blocks), dim3(256), 0, s, args, first, count);
+        else hipLaunchKernelGGL((cost_batch_kernel<8, false, false>), dim3(blocks), dim3(256), 0, s, args, first, count);
+    } else if (need <= 12) {
+        if (wide) hipLaunchKernelGGL((cost_batch_kernel<12, true, true>), dim3(blocks), dim3(256), 0, s, args, first, count);
+        else hipLaunchKernelGGL((cost_batch_kernel<12, false, true>), dim3(blocks), dim3(256), 0, s, args, first, count);
+    } else {
+        if (wide) hipLaunchKernelGGL((cost_batch_kernel<16, true, true>), dim3(blocks), dim3(256), 0, s, args, first, count);
+        else hipLaunchKernelGGL((cost_batch_kernel<16, false, true>), dim3(blocks), dim3(256), 0, s, args, first, count);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace qnae

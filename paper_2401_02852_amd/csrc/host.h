@@ -1,0 +1,150 @@
+// Host-side internals of libqnae.so shared by the ABI translation units:
+// the context, error reporting, growable buffers, kernel timing, mixer forms
+// and phase tables, and the sweep planner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/qnae.h"
+#include "internal.h"
+
+namespace qnae_host {
+
+// Sets the calling thread's error message and returns `code`.
+int fail(int code, const char* fmt, ...);
+const char* last_error();
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return ::qnae_host::fail(e_ == hipErrorOutOfMemory ? QNAE_ENOMEM : QNAE_EHIP, "%s: %s (%s:%d)", \
+                                     #expr, hipGetErrorString(e_), __FILE__, __LINE__);                \
+    } while (0)
+
+// Device buffer that only grows (waits for the device before it reallocates).
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t reserve(size_t need);
+    void release();
+};
+
+// Pinned host buffer that only grows.
+struct HostBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t reserve(size_t need);
+    void release();
+};
+
+// Event-timed kernel tallies (qnae_profile_*).
+enum { K_COST, K_FIRST, K_MIDDLE, K_BOUNDARY, K_FINAL, K_RESIDENT, K_REDUCE, K_BATCH_COST, K_BATCH_RESIDENT,
+       K_BATCH_SWEEP, K_BATCH_REDUCE, K_KINDS };
+
+struct Profiler {
+    struct Rec {
+        int kind;
+        double bytes;
+        hipEvent_t start, stop;
+    };
+    static const char* name(int k);
+    bool on = false;
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    uint64_t launches[K_KINDS] = {};
+    double ms[K_KINDS] = {}, bytes[K_KINDS] = {};
+    hipEvent_t get();
+};
+
+constexpr int kResidentMaxN = 14;
+
+}  // namespace qnae_host
+
+struct qnae_ctx {
+    int device = 0;
+    qnae_host::Profiler prof;
+    // single-instance path
+    qnae_host::DevBuf state, partials, luts, clauses, forms, small;  // small: zeros counter + 3 result doubles
+    qnae_host::HostBuf h_luts, h_clauses, h_forms, h_small;
+    // batched path: uploaded tables and work lists, states, partial sums, results
+    qnae_host::DevBuf b_blob, b_states, b_partials, b_results;
+    qnae_host::HostBuf h_blob, h_results;
+    hipEvent_t staging_done = nullptr;  // last async copy out of pinned staging
+    int tile_bits = 13;                 // tile size of the plain sweeps (log2 amplitudes)
+    int min_low_run = 4;                // minimum contiguous low run (log2 amplitudes)
+    int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes
+};
+
+namespace qnae_host {
+
+// Makes the context's device current and waits until pinned staging is free.
+int enter(qnae_ctx* ctx);
+int check_cost_args(int32_t n, int32_t m, int32_t dtype);
+int check_run_args(int32_t n, int32_t m, int32_t dtype, const void* cost, const double* gammas, const double* betas,
+                   int32_t p);
+
+// Launch through `fn`, bracketed by profiling events when enabled.
+template <typename F>
+hipError_t timed(qnae_ctx* ctx, int kind, double bytes, hipStream_t s, F&& fn) {
+    Profiler& P = ctx->prof;
+    if (!P.on) return fn();
+    Profiler::Rec r{kind, bytes, P.get(), P.get()};
+    hipError_t e = hipEventRecord(r.start, s);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(r.stop, s);
+    P.pending.push_back(r);
+    return e;
+}
+
+// Clause records for the cost kernel (drops clauses that can never be
+// violated); returns the number written to `out` (room for m records).
+int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* out);
+// QNAE_EINVAL if some literal is 0 or outside +-[1, n].
+int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k);
+
+// Phase tables (p tables of m + 1 entries, or one when p = 0) and per-layer
+// mixer forms; returns the scalar factor left after the last layer.
+std::complex<double> build_tables(int n, int m, const double* gammas, const double* betas, int p, float2* tables,
+                                  qnae::MixForm* forms);
+
+struct Group {
+    std::vector<int> pos;  // global bit of each tile bit
+    uint32_t mask;         // tile bits this group mixes
+};
+
+struct Op {
+    int group;
+    int kind;                              // qnae::SweepKind
+    int pre_layer, post_layer, lut_layer;  // -1 when unused
+};
+
+std::vector<Group> make_groups(int n, int TB, int cmin, int page);
+std::vector<Op> make_plan(int ngroups, int p);
+
+// A tiled (n > kResidentMaxN) solve: groups, op sequence and per-layer data.
+struct SweepPlan {
+    int n = 0, m = 0, p = 0, TB = 13, dtype = QNAE_U8, lut_len = 1;
+    bool keep = false;
+    std::vector<Group> groups;
+    std::vector<Op> ops;
+    std::vector<qnae::MixForm> forms;
+    std::vector<int> flips_before;  // parity of cot-form layers among 0 .. l-1
+    std::complex<double> final_scale;
+};
+
+// Plans a tiled solve; `forms` are the per-layer mixer forms from build_tables.
+void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, bool keep,
+                 const qnae::MixForm* forms, std::complex<double> final_scale);
+// Kernel arguments of one op.
+void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost, const float2* luts, double* partials,
+                qnae::SweepArgs* a);
+// Algorithmic bytes of one op and its profiling kind.
+double op_bytes(const SweepPlan& P, const Op& op);
+int op_profile_kind(const Op& op);
+
+}  // namespace qnae_host

@@ -32,6 +32,11 @@ struct CostArgs {
 };
 
 hipError_t launch_cost(const CostArgs& a, int dtype, hipStream_t s);
+// Many diagonals of one cost type: instance i owns 256-thread blocks
+// first[i] .. first[i+1]-1 (32 states per thread). max_clauses bounds every
+// instance's clause count; wide when some instance has n > 32.
+hipError_t launch_cost_batch(const CostArgs* args, const uint32_t* first, int count, uint32_t blocks, int dtype,
+                             int max_clauses, bool wide, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // State sweeps
@@ -78,13 +83,20 @@ struct SweepArgs {
     float2 store_scale;    // readout kinds with store: final scalar factor
     int32_t store;         // readout kinds: also store the state
     int32_t cflip;         // read the cost at the complemented index
-    int32_t persistent;    // one block per resident slot, prefetching the next tile
 };
 
-// Launches a persistent grid of at most (resident blocks per CU) x (CUs)
-// blocks; *grid_out receives the grid size (readout kinds write 3 partial sums
-// per block).
-hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out);
+hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s);
+
+// Tile size of batched sweeps (log2 amplitudes).
+constexpr int kBatchTileBits = 13;
+
+// One sweep step over `count` states at once. Instance i owns blocks
+// first[i] .. first[i+1]-1 (first has count+1 entries, first[count] =
+// blocks), one per tile of its own geometry; args[i].partials receives 3
+// doubles per tile for readout kinds. Every instance must use
+// kBatchTileBits.
+hipError_t launch_sweep_batch(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
+                              uint32_t blocks, hipStream_t s);
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s);
 
 // Whole circuit for n <= 14 in one workgroup (state resident in LDS).
@@ -99,8 +111,12 @@ struct ResidentArgs {
 };
 
 hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s);
+hipError_t launch_resident_batch(int dtype, const ResidentArgs* args, int count, hipStream_t s);
 
 // Sum of 3-double block partials into out[3], FP64.
 hipError_t launch_final_reduce(const double* partials, int64_t blocks, double* out, hipStream_t s);
+// Instance i: sum of blocks[i] triples at partials[i] -> outs[i][0..2].
+hipError_t launch_final_reduce_batch(const double* const* partials, const uint32_t* blocks, double* const* outs,
+                                     int count, hipStream_t s);
 
 }  // namespace qnae

@@ -1,0 +1,375 @@
+// Host runtime helpers of libqnae.so: errors, buffers, timing, argument
+// checks, clause records, mixer forms and phase tables, and the sweep planner.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "host.h"
+
+using qnae::MixForm;
+
+namespace qnae_host {
+
+namespace {
+thread_local std::string g_err;
+
+struct Layer {
+    MixForm form;
+    std::complex<double> scale;  // scalar factor of the whole layer's mixer
+};
+
+// R(beta) = cos(beta) I - i sin(beta) X for every qubit. Device butterflies
+// apply (I - i t X), optionally followed by X; the product of the n scalar
+// factors is returned in `scale`.
+Layer mixer_form(double beta, int n) {
+    const double cb = std::cos(beta), sb = std::sin(beta);
+    Layer L;
+    if (std::fabs(sb) <= std::fabs(cb)) {
+        L.form.t = (float)(sb / cb);
+        L.form.flip = 0;
+        L.scale = std::pow(std::complex<double>(cb, 0.0), n);
+    } else {
+        L.form.t = (float)(-cb / sb);
+        L.form.flip = 1;
+        L.scale = std::pow(std::complex<double>(0.0, -sb), n);
+    }
+    return L;
+}
+
+}  // namespace
+
+// Phase tables: table l holds prev_scale * exp(-i gamma_l c) for c = 0..m,
+// where prev_scale is the previous layer's mixer factor (2^{-n/2}, the
+// amplitude of |+>, for layer 0). Returns the factor left after the last layer.
+std::complex<double> build_tables(int n, int m, const double* gammas, const double* betas, int p,
+                                  float2* tables, MixForm* forms) {
+    std::complex<double> prev(std::pow(2.0, -0.5 * n), 0.0);
+    const int T = p > 0 ? p : 1;
+    for (int l = 0; l < T; ++l) {
+        const double g = p > 0 ? gammas[l] : 0.0;
+        for (int c = 0; c <= m; ++c) {
+            const std::complex<double> e = prev * std::complex<double>(std::cos(g * c), -std::sin(g * c));
+            tables[(size_t)l * (m + 1) + c] = make_float2((float)e.real(), (float)e.imag());
+        }
+        if (p > 0) {
+            const Layer L = mixer_form(betas[l], n);
+            forms[l] = L.form;
+            prev = L.scale;
+        }
+    }
+    return p > 0 ? prev : std::complex<double>(1.0, 0.0);
+}
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+hipError_t DevBuf::reserve(size_t need) {
+    if (need <= bytes) return hipSuccess;
+    if (ptr) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ptr, need);
+    if (e == hipSuccess) bytes = need;
+    return e;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+hipError_t HostBuf::reserve(size_t need) {
+    if (need <= bytes) return hipSuccess;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&ptr, need, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = need;
+    return e;
+}
+
+void HostBuf::release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+const char* Profiler::name(int k) {
+    static const char* names[K_KINDS] = {"cost", "sweep_first", "sweep_middle", "sweep_boundary", "sweep_final",
+                                         "resident", "final_reduce", "batch_cost", "batch_resident", "batch_sweep",
+                                         "batch_reduce"};
+    return names[k];
+}
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+int enter(qnae_ctx* ctx) {
+    if (!ctx) return fail(QNAE_EINVAL, "null context");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipEventSynchronize(ctx->staging_done));
+    return QNAE_OK;
+}
+
+int check_cost_args(int32_t n, int32_t m, int32_t dtype) {
+    if (n < 1 || n > QNAE_MAX_N) return fail(QNAE_EINVAL, "n=%d outside [1, %d]", n, QNAE_MAX_N);
+    if (dtype != QNAE_U8 && dtype != QNAE_U16) return fail(QNAE_EINVAL, "cost_dtype=%d is not QNAE_U8/QNAE_U16", dtype);
+    if (m < 0 || m > 65535) return fail(QNAE_EINVAL, "m=%d outside [0, 65535]", m);
+    if (dtype == QNAE_U8 && m > 255) return fail(QNAE_EINVAL, "m=%d needs QNAE_U16 (QNAE_U8 holds m <= 255)", m);
+    return QNAE_OK;
+}
+
+int check_run_args(int32_t n, int32_t m, int32_t dtype, const void* cost, const double* gammas, const double* betas,
+                   int32_t p) {
+    if (int rc = check_cost_args(n, m, dtype)) return rc;
+    if (!cost) return fail(QNAE_EINVAL, "null cost_dev");
+    if (p < 0 || p > 100000) return fail(QNAE_EINVAL, "p=%d outside [0, 100000]", p);
+    if (p > 0 && (!gammas || !betas)) return fail(QNAE_EINVAL, "null angle arrays with p=%d", p);
+    for (int l = 0; l < p; ++l)
+        if (!std::isfinite(gammas[l]) || !std::isfinite(betas[l]))
+            return fail(QNAE_EINVAL, "non-finite angle at layer %d", l);
+    return QNAE_OK;
+}
+
+int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k) {
+    if (k < 1 || k > 64) return fail(QNAE_EINVAL, "k=%d outside [1, 64]", k);
+    if (m > 0 && !clauses) return fail(QNAE_EINVAL, "null clauses with m=%d", m);
+    for (int64_t i = 0; i < (int64_t)m * k; ++i) {
+        const int32_t l = clauses[i];
+        if (l == 0 || l > n || l < -n)
+            return fail(QNAE_EINVAL, "literal %d at index %lld outside +-[1, n=%d]", l, (long long)i, n);
+    }
+    return QNAE_OK;
+}
+
+int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* recs) {
+    int nrec = 0;
+    for (int i = 0; i < m; ++i) {
+        uint64_t mask = 0, pat = 0;
+        bool never = false;
+        for (int j = 0; j < k; ++j) {
+            const int32_t l = clauses[(size_t)i * k + j];
+            const uint64_t bit = 1ull << ((l > 0 ? l : -l) - 1);
+            const bool neg = l < 0;
+            if (mask & bit) {
+                if (((pat & bit) != 0) != neg) never = true;  // x and NOT x: never all equal
+            } else {
+                mask |= bit;
+                if (neg) pat |= bit;
+            }
+        }
+        if (never) continue;
+        qnae::ClauseRec r;
+        const uint64_t mh = mask & ~31ull;
+        r.mask_hi_lo = (uint32_t)mh;
+        r.mask_hi_hi = (uint32_t)(mh >> 32);
+        r.pat_lo = (uint32_t)pat;
+        r.pat_hi = (uint32_t)(pat >> 32);
+        const uint32_t lm = (uint32_t)(mask & 31u), lp = (uint32_t)(pat & 31u);
+        r.zero_tab = 0u;
+        r.full_tab = 0u;
+        for (uint32_t j = 0; j < 32; ++j) {
+            const uint32_t y = (j ^ lp) & lm;
+            if (y == 0u) r.zero_tab |= 1u << j;
+            if (y == lm) r.full_tab |= 1u << j;
+        }
+        recs[nrec++] = r;
+    }
+    return nrec;
+}
+
+// Qubit groups of the sweeps. Group A holds the low run [0, cA) of x and a
+// few high bits; every other group holds the low run [0, cmin) (not mixed,
+// for contiguous global accesses) and a piece of the remaining high bits.
+// Bits at or above `page` select a 2 MiB page of the state (8-byte
+// amplitudes); a tile that spans k of them touches 2^k pages, so these bits
+// are dealt out evenly over the groups to keep every tile within a few TLB
+// entries.
+std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
+    std::vector<Group> g;
+    Group A;
+    if (n <= TB) {
+        for (int i = 0; i < TB; ++i) A.pos.push_back(i);
+        A.mask = (1u << TB) - 1u;
+        g.push_back(A);
+        return g;
+    }
+    const int rest = n - TB;
+    const int h = (rest + (TB - cmin) - 1) / (TB - cmin);
+    std::vector<int> P;
+    for (int b = std::max(page, TB); b < n; ++b) P.push_back(b);
+    const int target = ((int)P.size() + h) / (h + 1);
+    const int a = std::min(std::min(target, TB - cmin), (int)P.size());
+    const int cA = TB - a;
+    std::vector<int> atop(P.end() - a, P.end());
+    for (int i = 0; i < cA; ++i) A.pos.push_back(i);
+    for (int b : atop) A.pos.push_back(b);
+    A.mask = (1u << TB) - 1u;
+    g.push_back(A);
+    // bits left for the other groups, page bits first
+    std::vector<int> RP, RN;
+    for (int b = cA; b < n; ++b) {
+        if (std::find(atop.begin(), atop.end(), b) != atop.end()) continue;
+        (b >= page ? RP : RN).push_back(b);
+    }
+    const int R = (int)(RP.size() + RN.size());
+    std::vector<std::vector<int>> piece(h);
+    std::vector<int> size(h);
+    for (int i = 0; i < h; ++i) size[i] = R / h + (i < R % h ? 1 : 0);
+    for (size_t q = 0; q < RP.size(); ++q) piece[q % h].push_back(RP[q]);
+    size_t nx = 0;
+    for (int i = 0; i < h; ++i)
+        while ((int)piece[i].size() < size[i]) piece[i].push_back(RN[nx++]);
+    for (int i = 0; i < h; ++i) {
+        Group B;
+        std::vector<int> bits = piece[i];
+        // fill up to TB - cmin bits with unmixed bits just above the low run
+        std::vector<int> fill;
+        for (int b = cmin; (int)(bits.size() + fill.size()) < TB - cmin; ++b)
+            if (std::find(bits.begin(), bits.end(), b) == bits.end()) fill.push_back(b);
+        std::vector<int> all = fill;
+        all.insert(all.end(), bits.begin(), bits.end());
+        std::sort(all.begin(), all.end());
+        for (int b = 0; b < cmin; ++b) B.pos.push_back(b);
+        B.mask = 0u;
+        for (int b : all) {
+            if (std::find(bits.begin(), bits.end(), b) != bits.end()) B.mask |= 1u << B.pos.size();
+            B.pos.push_back(b);
+        }
+        g.push_back(B);
+    }
+    return g;
+}
+
+// Each layer mixes every group once. The last group of a layer is fused with
+// the next layer's phase and with that layer's mixing of the same group, so
+// every layer after the first costs (number of groups - 1) sweeps. The first
+// sweep starts from the phase table (no load) and the last one only reads the
+// state for the readout unless the final state is kept.
+std::vector<Op> make_plan(int ngroups, int p) {
+    using namespace qnae;
+    std::vector<Op> ops;
+    if (p == 0) {
+        ops.push_back({0, SK_P0, -1, -1, 0});
+        return ops;
+    }
+    ops.push_back({0, SK_FIRST, -1, 0, 0});
+    std::vector<int> pending;  // groups not yet mixed for layer l
+    for (int g = 1; g < ngroups; ++g) pending.push_back(g);
+    for (int l = 0;; ++l) {
+        if (pending.empty()) {  // one group: the previous sweep mixed it already
+            if (l == p - 1) {
+                ops.push_back({0, SK_FINAL, -1, -1, -1});
+                return ops;
+            }
+            ops.push_back({0, SK_BOUNDARY, -1, l + 1, l + 1});
+            continue;
+        }
+        int last = pending.back();
+        for (int g : pending)
+            if (g != 0) last = g;
+        for (int g : pending)
+            if (g != last) ops.push_back({g, SK_MIDDLE, l, -1, -1});
+        if (l == p - 1) {
+            ops.push_back({last, SK_FINAL, l, -1, -1});
+            return ops;
+        }
+        ops.push_back({last, SK_BOUNDARY, l, l + 1, l + 1});
+        pending.clear();
+        for (int g = 0; g < ngroups; ++g)
+            if (g != last) pending.push_back(g);
+    }
+}
+
+void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, bool keep,
+                 const qnae::MixForm* forms, std::complex<double> final_scale) {
+    P.n = n;
+    P.m = m;
+    P.p = p;
+    P.TB = TB;
+    P.dtype = dtype;
+    P.lut_len = m + 1;
+    P.keep = keep;
+    P.groups = make_groups(n, TB, cmin, page);
+    P.ops = make_plan((int)P.groups.size(), p);
+    P.forms.assign(forms, forms + p);
+    P.flips_before.assign(p + 1, 0);
+    for (int l = 0; l < p; ++l) P.flips_before[l + 1] = P.flips_before[l] ^ forms[l].flip;
+    P.final_scale = final_scale;
+}
+
+void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost, const float2* luts, double* partials,
+                qnae::SweepArgs* a) {
+    const Group& g = P.groups[op.group];
+    std::memset(a, 0, sizeof *a);
+    a->psi = psi;
+    a->cost = cost;
+    a->lut = op.lut_layer >= 0 ? luts + (size_t)op.lut_layer * P.lut_len : nullptr;
+    a->partials = partials;
+    a->n = P.n;
+    a->nw = P.n - P.TB;
+    a->tile_bits = 0;
+    for (int i = 0; i < P.TB; ++i) {
+        a->pos[i] = (uint8_t)g.pos[i];
+        a->tile_bits |= 1ull << g.pos[i];
+    }
+    a->wmask = ((1ull << P.n) - 1ull) & ~a->tile_bits;
+    a->lut_len = P.lut_len;
+    a->pre_mask = op.pre_layer >= 0 ? g.mask : 0u;
+    a->post_mask = op.post_layer >= 0 ? g.mask : 0u;
+    a->pre_t = op.pre_layer >= 0 ? P.forms[op.pre_layer].t : 0.f;
+    a->post_t = op.post_layer >= 0 ? P.forms[op.post_layer].t : 0.f;
+    a->store_scale = make_float2((float)P.final_scale.real(), (float)P.final_scale.imag());
+    a->store = P.keep ? 1 : 0;
+    a->cflip = op.kind == qnae::SK_BOUNDARY ? P.flips_before[op.lut_layer]
+               : op.kind == qnae::SK_FINAL  ? P.flips_before[P.p]
+                                            : 0;
+}
+
+double op_bytes(const SweepPlan& P, const Op& op) {
+    const double cb = P.dtype == QNAE_U8 ? 1.0 : 2.0;
+    double per_amp;
+    switch (op.kind) {
+        case qnae::SK_FIRST: per_amp = 8.0 + cb; break;
+        case qnae::SK_MIDDLE: per_amp = 16.0; break;
+        case qnae::SK_BOUNDARY: per_amp = 16.0 + cb; break;
+        case qnae::SK_FINAL: per_amp = 8.0 + cb + (P.keep ? 8.0 : 0.0); break;
+        default: per_amp = cb + (P.keep ? 8.0 : 0.0);
+    }
+    return per_amp * std::ldexp(1.0, P.n);
+}
+
+int op_profile_kind(const Op& op) {
+    switch (op.kind) {
+        case qnae::SK_FIRST: return K_FIRST;
+        case qnae::SK_MIDDLE: return K_MIDDLE;
+        case qnae::SK_BOUNDARY: return K_BOUNDARY;
+        default: return K_FINAL;
+    }
+}
+
+}  // namespace qnae_host

@@ -176,12 +176,10 @@ __device__ __forceinline__ void from_lds(const float2* lds, float2 (&v)[32], uin
     }
 }
 
-// One sweep. The grid is persistent: block b handles tiles b, b + gridDim.x,
-// ... and loads the next tile's amplitudes and cost values into registers
-// before it works on the current one, so every workgroup keeps global loads
-// in flight while it mixes.
+// One workgroup's work on tile t of one sweep. Readout kinds write the three
+// block sums to partial[0..2].
 template <int TB, typename CT, int KIND>
-__global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs a) {
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, double* partial) {
     constexpr int WB = TB - 11;
     constexpr int NT = 64 << WB;
     constexpr bool INIT = KIND == SK_FIRST || KIND == SK_P0;  // start from phase table 0
@@ -202,7 +200,7 @@ __global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs 
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t ntiles = 1u << a.nw;
     // Tile bit i sits at bit pos[i] of x; the tile index fills the other
-    // bits (wpos, ascending). Both maps are bit deposits, so offsets are
+    // bits (wmask, ascending). Both maps are bit deposits, so offsets are
     // additive (XOR-linear) over disjoint bit sets of e: an address splits
     // into a per-thread offset and a per-slot offset that is the same for
     // every lane (scalar registers).
@@ -217,179 +215,165 @@ __global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs 
         return x;
     };
     // Consecutive tiles go to one XCD (blocks are dealt round-robin over the
-    // 8 XCDs), so tiles that share cache lines of the cost diagonal share an L2.
-    const bool remap = ntiles >= 8;
-    // Bit deposit of the tile index into the bits outside the tile (uniform:
-    // scalar ALU only).
-    auto tile_base = [&](uint32_t t) -> uint64_t {
-        uint64_t w = remap ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
-        uint64_t base = 0;
-        for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull) {
-            if (w & 1ull) base |= m & (~m + 1ull);
-            w >>= 1;
-        }
-        return base;
-    };
-    const uint64_t o0 = scat(L::t0(lane, wave));
-    const uint64_t o2 = scat(L::t2(lane, wave));
-    // With cflip the stored state is the true one with every qubit flipped
-    // (see MixForm), so cost values are read at the complemented index:
-    // complemented tile base, thread part and slot.
-    const bool cf = a.cflip != 0;
-    const uint64_t cflipmask = cf ? ((((uint64_t)1 << a.n) - 1ull) ^ a.tile_bits) : 0ull;
-    const uint64_t oc = cf ? scat(L::t2(lane, wave) ^ L::t2(63u, (1u << WB) - 1u)) : o2;
-    const int cj = cf ? 31 : 0;
+    // 8 XCDs), so tiles that share cache lines of the cost diagonal share an
+    // L2. The tile index is deposited into the bits outside the tile (scalar
+    // ALU only).
+    uint64_t w = ntiles >= 8 ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
+    uint64_t base = 0;
+    for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull) {
+        if (w & 1ull) base |= m & (~m + 1ull);
+        w >>= 1;
+    }
 
-    auto load_state = [&](uint64_t base, float2 (&v)[32]) {
-        const float2* const p0 = a.psi + base + o0;
+    // Cost values of the 32 amplitudes in layout L2, loaded first; packed 4
+    // (uint8) or 2 (uint16) per register. With cflip the stored state is the
+    // true one with every qubit flipped (see MixForm), so cost values are read
+    // at the complemented index: complemented tile base, thread part and slot.
+    uint32_t cvp[NC];
+    if (NEED_COST) {
+        const bool cf = a.cflip != 0;
+        const uint64_t cbase = cf ? base ^ ((((uint64_t)1 << a.n) - 1ull) ^ a.tile_bits) : base;
+        const uint32_t ct = cf ? L::t2(lane, wave) ^ L::t2(63u, (1u << WB) - 1u) : L::t2(lane, wave);
+        const int cj = cf ? 31 : 0;
+        const CT* const c2 = (const CT*)a.cost + cbase + scat(ct);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            uint32_t wv = 0u;
+#pragma unroll
+            for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2((PK * i + q) ^ cj))] << (8 * sizeof(CT) * q);
+            cvp[i] = wv;
+        }
+        if (NEED_LUT && LUT_LDS)
+            for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
+    }
+    // Cost values above m are a caller error; the clamp keeps table reads in bounds.
+    const uint32_t lut_last = (uint32_t)a.lut_len - 1u;
+    auto lut = [&](uint32_t cidx) -> float2 { return LUT_LDS ? lut_s[cidx] : a.lut[min(cidx, lut_last)]; };
+    auto cval = [&](int j) -> uint32_t {
+        return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
+    };
+
+    float2 v[32];
+    if (INIT) {
+        __syncthreads();  // phase table visible
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = lut(cval(j));
+    } else {
+        const float2* const p0 = a.psi + base + scat(L::t0(lane, wave));
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             const float4 q = *(const float4*)(p0 + scat(L::s0(2 * jj)));
             v[2 * jj] = make_float2(q.x, q.y);
             v[2 * jj + 1] = make_float2(q.z, q.w);
         }
-    };
-    auto load_cost = [&](uint64_t base, uint32_t (&cv)[NC]) {
-        const CT* const c2 = (const CT*)a.cost + (base ^ cflipmask) + oc;
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            uint32_t wv = 0u;
-#pragma unroll
-            for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2((PK * i + q) ^ cj))] << (8 * sizeof(CT) * q);
-            cv[i] = wv;
-        }
-    };
-
-    if (NEED_LUT && LUT_LDS)
-        for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
-    // Cost values above m are a caller error; the clamp keeps table reads in bounds.
-    const uint32_t lut_last = (uint32_t)a.lut_len - 1u;
-    auto lut = [&](uint32_t cidx) -> float2 { return LUT_LDS ? lut_s[cidx] : a.lut[min(cidx, lut_last)]; };
-
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    uint32_t t = blockIdx.x;
-    uint64_t base = tile_base(t);
-    float2 v[32];
-    uint32_t cvp[NC];
-    if (!INIT) load_state(base, v);
-    if (NEED_COST) load_cost(base, cvp);
-    __syncthreads();  // phase table visible
-    // A grid smaller than the tile count is persistent and prefetches.
-    const bool persistent = gridDim.x < ntiles;
-    for (;;) {
-        const uint32_t tn = t + gridDim.x;
-        const bool more = tn < ntiles;
-        // Loads for the next tile (the current one again on the last pass,
-        // unused) go out before any work on this tile.
-        const uint64_t nbase = tile_base(more ? tn : t);
-        float2 nv[32];
-        uint32_t ncv[NC];
-        if (persistent) {
-            if (!INIT) load_state(nbase, nv);
-            if (NEED_COST) load_cost(nbase, ncv);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        auto cval = [&](int j) -> uint32_t {
-            return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
-        };
-
-        if (INIT) {
-#pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = lut(cval(j));
-        }
-        if (PRE) {
-            const uint32_t m = a.pre_mask;
-            const float tt = a.pre_t;
-            mix32(v, L::sm0(m), tt);
-            to_lds<TB, 0>(lds, v, lane, wave);
-            if (L::sm1(m)) {
-                __syncthreads();
-                from_lds<TB, 1>(lds, v, lane, wave);
-                mix32(v, L::sm1(m), tt);
-                __syncthreads();
-                to_lds<TB, 1>(lds, v, lane, wave);
-            }
-            __syncthreads();
-            from_lds<TB, 2>(lds, v, lane, wave);
-            mix32(v, L::sm2(m), tt);
-        }
-        if (PHASE) {
-#pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], lut(cval(j)));
-        }
-        if (POST) {
-            const uint32_t m = a.post_mask;
-            const float tt = a.post_t;
-            mix32(v, L::sm2(m), tt);
-            if (PRE) __syncthreads();
-            to_lds<TB, 2>(lds, v, lane, wave);
-            __syncthreads();
-            if (L::sm1(m)) {
-                from_lds<TB, 1>(lds, v, lane, wave);
-                mix32(v, L::sm1(m), tt);
-                __syncthreads();
-                to_lds<TB, 1>(lds, v, lane, wave);
-                __syncthreads();
-            }
-            from_lds<TB, 0>(lds, v, lane, wave);
-            mix32(v, L::sm0(m), tt);
-            float2* const p0 = a.psi + base + o0;
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj)
-                *(float4*)(p0 + scat(L::s0(2 * jj))) =
-                    make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
-        }
-        if (REDUCE) {
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                const float pr = fmaf(v[j].x, v[j].x, v[j].y * v[j].y);
-                const uint32_t c = cval(j);
-                s2 += pr;
-                s1 = fmaf((float)c, pr, s1);
-                s0 += c == 0u ? pr : 0.f;
-            }
-            acc0 += s0;
-            acc1 += s1;
-            acc2 += s2;
-        }
-        if (KIND == SK_MIDDLE || (REDUCE && a.store)) {
-            if (REDUCE) {
-#pragma unroll
-                for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], a.store_scale);
-            }
-            float2* const p2 = a.psi + base + o2;
-#pragma unroll
-            for (int j = 0; j < 32; ++j) p2[scat(L::s2(j))] = v[j];
-        }
-        if (!more) break;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = nv[j];
-#pragma unroll
-        for (int i = 0; i < NC; ++i) cvp[i] = ncv[i];
-        t = tn;
-        base = nbase;
-        if (PRE || POST) __syncthreads();  // LDS is rewritten by the next tile
     }
-
+    if (PRE) {
+        const uint32_t m = a.pre_mask;
+        const float tt = a.pre_t;
+        mix32(v, L::sm0(m), tt);
+        to_lds<TB, 0>(lds, v, lane, wave);
+        if (L::sm1(m)) {
+            __syncthreads();
+            from_lds<TB, 1>(lds, v, lane, wave);
+            mix32(v, L::sm1(m), tt);
+            __syncthreads();
+            to_lds<TB, 1>(lds, v, lane, wave);
+        }
+        __syncthreads();
+        from_lds<TB, 2>(lds, v, lane, wave);
+        mix32(v, L::sm2(m), tt);
+    }
+    if (PHASE) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], lut(cval(j)));
+    }
+    if (POST) {
+        const uint32_t m = a.post_mask;
+        const float tt = a.post_t;
+        mix32(v, L::sm2(m), tt);
+        if (PRE) __syncthreads();
+        to_lds<TB, 2>(lds, v, lane, wave);
+        __syncthreads();
+        if (L::sm1(m)) {
+            from_lds<TB, 1>(lds, v, lane, wave);
+            mix32(v, L::sm1(m), tt);
+            __syncthreads();
+            to_lds<TB, 1>(lds, v, lane, wave);
+            __syncthreads();
+        }
+        from_lds<TB, 0>(lds, v, lane, wave);
+        mix32(v, L::sm0(m), tt);
+        float2* const p0 = a.psi + base + scat(L::t0(lane, wave));
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+            *(float4*)(p0 + scat(L::s0(2 * jj))) = make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
+        return;
+    }
     if (REDUCE) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const float pr = fmaf(v[j].x, v[j].x, v[j].y * v[j].y);
+            const uint32_t c = cval(j);
+            s2 += pr;
+            s1 = fmaf((float)c, pr, s1);
+            s0 += c == 0u ? pr : 0.f;
+        }
+        double d0 = s0, d1 = s1, d2 = s2;
         for (int off = 32; off > 0; off >>= 1) {
-            acc0 += __shfl_xor(acc0, off);
-            acc1 += __shfl_xor(acc1, off);
-            acc2 += __shfl_xor(acc2, off);
+            d0 += __shfl_xor(d0, off);
+            d1 += __shfl_xor(d1, off);
+            d2 += __shfl_xor(d2, off);
         }
         if (lane == 0) {
-            red[0][wave] = acc0;
-            red[1][wave] = acc1;
-            red[2][wave] = acc2;
+            red[0][wave] = d0;
+            red[1][wave] = d1;
+            red[2][wave] = d2;
         }
         __syncthreads();
         if (threadIdx.x < 3) {
             double sum = 0.0;
             for (int q = 0; q < (1 << WB); ++q) sum += red[threadIdx.x][q];
-            a.partials[(size_t)blockIdx.x * 3 + threadIdx.x] = sum;
+            partial[threadIdx.x] = sum;
         }
     }
+    if (KIND == SK_MIDDLE || (REDUCE && a.store)) {
+        if (REDUCE) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], a.store_scale);
+        }
+        float2* const p2 = a.psi + base + scat(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) p2[scat(L::s2(j))] = v[j];
+    }
+}
+
+// One sweep over one state: block b handles tile b.
+template <int TB, typename CT, int KIND>
+__global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs a) {
+    sweep_tile<TB, CT, KIND>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
+}
+
+// Instance of work item b in a ragged batch: the largest i with first[i] <= b.
+__device__ __forceinline__ int batch_item(const uint32_t* first, int count, uint32_t b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One sweep step over many states at once (ragged): instance i owns blocks
+// first[i] .. first[i+1]-1, one per tile, with its own arguments.
+template <int TB, typename CT, int KIND>
+__global__ __launch_bounds__(64 << (TB - 11)) void sweep_batch_kernel(const SweepArgs* args, const uint32_t* first,
+                                                                      int count) {
+    const int i = batch_item(first, count, blockIdx.x);
+    const SweepArgs a = args[i];
+    const uint32_t t = blockIdx.x - first[i];
+    sweep_tile<TB, CT, KIND>(a, t, a.partials + 3 * (size_t)t);
 }
 
 // psi[x] <-> psi[N - 1 - x]: undoes an X on every qubit (N >= 4).
@@ -415,7 +399,7 @@ __device__ __forceinline__ void mix16(float2 (&v)[16], int nb, float t) {
 }
 
 template <typename CT>
-__global__ __launch_bounds__(256) void resident_kernel(const ResidentArgs a) {
+__device__ __forceinline__ void resident_body(const ResidentArgs& a) {
     __shared__ float2 s[1 << 14];
     __shared__ double red[3][4];
     const int n = a.n;
@@ -478,7 +462,19 @@ __global__ __launch_bounds__(256) void resident_kernel(const ResidentArgs a) {
     if (tid < 3) a.out[tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
 }
 
-__global__ __launch_bounds__(1024) void final_reduce_kernel(const double* partials, int64_t blocks, double* out) {
+template <typename CT>
+__global__ __launch_bounds__(256) void resident_kernel(const ResidentArgs a) {
+    resident_body<CT>(a);
+}
+
+// Many small instances, one workgroup each.
+template <typename CT>
+__global__ __launch_bounds__(256) void resident_batch_kernel(const ResidentArgs* args) {
+    const ResidentArgs a = args[blockIdx.x];
+    resident_body<CT>(a);
+}
+
+__device__ __forceinline__ void final_reduce_body(const double* partials, int64_t blocks, double* out) {
     __shared__ double red[3][16];
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
     for (int64_t i = threadIdx.x; i < blocks; i += 1024) {
@@ -504,66 +500,74 @@ __global__ __launch_bounds__(1024) void final_reduce_kernel(const double* partia
     }
 }
 
-// Resident workgroups per CU of a kernel, cached after the first query.
-template <typename K>
-int blocks_per_cu(K kernel, int block) {
-    static int cached = 0;
-    if (cached == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1) nb = 1;
-        cached = nb;
-    }
-    return cached;
+__global__ __launch_bounds__(1024) void final_reduce_kernel(const double* partials, int64_t blocks, double* out) {
+    final_reduce_body(partials, blocks, out);
 }
 
-int num_cus() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 256;
-    }
-    return cus;
+// One workgroup per instance i: blocks[i] triples at partials[i] -> outs[i].
+__global__ __launch_bounds__(1024) void final_reduce_batch_kernel(const double* const* partials, const uint32_t* blocks,
+                                                                   double* const* outs) {
+    final_reduce_body(partials[blockIdx.x], blocks[blockIdx.x], outs[blockIdx.x]);
 }
 
 template <int TB, typename CT, int KIND>
-hipError_t launch_kind(const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
-    const int block = 64 << (TB - 11);
-    auto kern = sweep_kernel<TB, CT, KIND>;
-    const uint64_t ntiles = 1ull << a.nw;
-    const uint64_t cap = a.persistent ? (uint64_t)blocks_per_cu(kern, block) * num_cus() : ntiles;
-    const uint32_t grid = (uint32_t)(ntiles < cap ? ntiles : cap);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a);
-    if (grid_out) *grid_out = grid;
+hipError_t launch_kind(const SweepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int TB, typename CT, int KIND>
+hipError_t launch_batch_kind(const SweepArgs* args, const uint32_t* first, int count, uint32_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((sweep_batch_kernel<TB, CT, KIND>), dim3(blocks), dim3(64 << (TB - 11)), 0, s, args, first,
+                       count);
     return hipGetLastError();
 }
 
 template <int TB, typename CT>
-hipError_t launch_tb(int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
+hipError_t launch_tb(int kind, const SweepArgs& a, hipStream_t s) {
     switch (kind) {
-        case SK_FIRST: return launch_kind<TB, CT, SK_FIRST>(a, s, grid_out);
-        case SK_MIDDLE: return launch_kind<TB, CT, SK_MIDDLE>(a, s, grid_out);
-        case SK_BOUNDARY: return launch_kind<TB, CT, SK_BOUNDARY>(a, s, grid_out);
-        case SK_FINAL: return launch_kind<TB, CT, SK_FINAL>(a, s, grid_out);
-        case SK_P0: return launch_kind<TB, CT, SK_P0>(a, s, grid_out);
+        case SK_FIRST: return launch_kind<TB, CT, SK_FIRST>(a, s);
+        case SK_MIDDLE: return launch_kind<TB, CT, SK_MIDDLE>(a, s);
+        case SK_BOUNDARY: return launch_kind<TB, CT, SK_BOUNDARY>(a, s);
+        case SK_FINAL: return launch_kind<TB, CT, SK_FINAL>(a, s);
+        case SK_P0: return launch_kind<TB, CT, SK_P0>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename CT>
+hipError_t launch_batch_ct(int kind, const SweepArgs* args, const uint32_t* first, int count, uint32_t blocks,
+                           hipStream_t s) {
+    switch (kind) {
+        case SK_FIRST: return launch_batch_kind<kBatchTileBits, CT, SK_FIRST>(args, first, count, blocks, s);
+        case SK_MIDDLE: return launch_batch_kind<kBatchTileBits, CT, SK_MIDDLE>(args, first, count, blocks, s);
+        case SK_BOUNDARY: return launch_batch_kind<kBatchTileBits, CT, SK_BOUNDARY>(args, first, count, blocks, s);
+        case SK_FINAL: return launch_batch_kind<kBatchTileBits, CT, SK_FINAL>(args, first, count, blocks, s);
+        case SK_P0: return launch_batch_kind<kBatchTileBits, CT, SK_P0>(args, first, count, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int TB>
-hipError_t launch_tb_dt(int dtype, int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
-    return dtype == 1 ? launch_tb<TB, uint8_t>(kind, a, s, grid_out) : launch_tb<TB, uint16_t>(kind, a, s, grid_out);
+hipError_t launch_tb_dt(int dtype, int kind, const SweepArgs& a, hipStream_t s) {
+    return dtype == 1 ? launch_tb<TB, uint8_t>(kind, a, s) : launch_tb<TB, uint16_t>(kind, a, s);
 }
 
 }  // namespace
 
-hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s, uint32_t* grid_out) {
+hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s) {
     switch (tb) {
-        case 12: return launch_tb_dt<12>(dtype, kind, a, s, grid_out);
-        case 13: return launch_tb_dt<13>(dtype, kind, a, s, grid_out);
-        case 14: return launch_tb_dt<14>(dtype, kind, a, s, grid_out);
+        case 12: return launch_tb_dt<12>(dtype, kind, a, s);
+        case 13: return launch_tb_dt<13>(dtype, kind, a, s);
+        case 14: return launch_tb_dt<14>(dtype, kind, a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_sweep_batch(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
+                              uint32_t blocks, hipStream_t s) {
+    return dtype == 1 ? launch_batch_ct<uint8_t>(kind, args, first, count, blocks, s)
+                      : launch_batch_ct<uint16_t>(kind, args, first, count, blocks, s);
 }
 
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s) {
@@ -580,8 +584,22 @@ hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_resident_batch(int dtype, const ResidentArgs* args, int count, hipStream_t s) {
+    if (dtype == 1)
+        hipLaunchKernelGGL((resident_batch_kernel<uint8_t>), dim3(count), dim3(256), 0, s, args);
+    else
+        hipLaunchKernelGGL((resident_batch_kernel<uint16_t>), dim3(count), dim3(256), 0, s, args);
+    return hipGetLastError();
+}
+
 hipError_t launch_final_reduce(const double* partials, int64_t blocks, double* out, hipStream_t s) {
     hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(1024), 0, s, partials, blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_reduce_batch(const double* const* partials, const uint32_t* blocks, double* const* outs,
+                                     int count, hipStream_t s) {
+    hipLaunchKernelGGL(final_reduce_batch_kernel, dim3(count), dim3(1024), 0, s, partials, blocks, outs);
     return hipGetLastError();
 }
 

@@ -1,0 +1,87 @@
+"""Batched path (many instances per launch) against the single-instance path
+and the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_02852_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2401_02852_amd as q
+    q.load_library()
+    return q
+
+
+def ragged(count, seed, n_lo=3, n_hi=20):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        k = int(rng.integers(1, min(n, 5) + 1))
+        m = int(rng.integers(0, 4 * n))
+        if i % 7 == 3:
+            m = 300 + n  # uint16 costs
+        cl = inst.instance(n, k, m, 1000 * seed + i).reshape(m, k)
+        p = int(rng.integers(0, 6))
+        g, b = rng.uniform(-3, 3, p), rng.uniform(-3, 3, p)
+        out.append((n, k, m, cl, g, b))
+    return out
+
+
+def test_batched_cost_matches_single(q):
+    jobs = ragged(40, 1)
+    costs, sols = q.build_cost_diagonals([j[3] for j in jobs], [j[0] for j in jobs], count_solutions=True)
+    for (n, k, m, cl, g, b), c, s in zip(jobs, costs, sols):
+        ref = oracle.cost(cl, n)
+        assert np.array_equal(c.cpu().numpy().astype(np.int64), ref), (n, k, m)
+        assert s == int((ref == 0).sum())
+
+
+def test_batched_run_matches_single_and_oracle(q):
+    jobs = ragged(48, 2)
+    costs = q.build_cost_diagonals([j[3] for j in jobs], [j[0] for j in jobs])
+    res = q.qaoa_run_batched(costs, [j[0] for j in jobs], [j[2] for j in jobs], [j[4] for j in jobs],
+                             [j[5] for j in jobs])
+    for (n, k, m, cl, g, b), c, r in zip(jobs, costs, res):
+        alone = q.qaoa_run(c, n, m, g, b)
+        assert np.allclose(r, alone, rtol=1e-12, atol=1e-15), (n, m, len(g), r, alone)
+        ref = oracle.qaoa(oracle.cost(cl, n), n, g, b)
+        assert abs(r.p_success - ref[0]) <= 1e-5
+        assert abs(r.expected_cost - ref[1]) <= 1e-5 * max(ref[1], 1e-12) + 1e-9
+        assert abs(r.norm - 1) <= 1e-5
+
+
+def test_batched_states(q):
+    import torch
+    jobs = ragged(12, 3, n_lo=8, n_hi=19)
+    costs = q.build_cost_diagonals([j[3] for j in jobs], [j[0] for j in jobs])
+    states = [torch.empty(1 << j[0], dtype=torch.complex64, device="cuda") for j in jobs]
+    q.qaoa_run_batched(costs, [j[0] for j in jobs], [j[2] for j in jobs], [j[4] for j in jobs],
+                       [j[5] for j in jobs], states=states)
+    for (n, k, m, cl, g, b), c, st in zip(jobs, costs, states):
+        ref = torch.empty_like(st)
+        q.qaoa_run(c, n, m, g, b, state=ref)
+        assert torch.equal(st, ref), n
+
+
+def test_batched_workload_512(q):
+    """The 512-instance ragged batch: every result equals the single-instance
+    path; a sample is checked against the oracle."""
+    batch = inst.batched_workload(count=512)
+    costs = q.build_cost_diagonals([x["clauses"] for x in batch], [x["n"] for x in batch])
+    res = q.qaoa_run_batched(costs, [x["n"] for x in batch], [x["m"] for x in batch],
+                             [x["gammas"] for x in batch], [x["betas"] for x in batch])
+    for x, c, r in zip(batch, costs, res):
+        alone = q.qaoa_run(c, x["n"], x["m"], x["gammas"], x["betas"])
+        assert np.allclose(r, alone, rtol=1e-12, atol=1e-15)
+    for i in range(0, 512, 37):
+        x = batch[i]
+        ref = oracle.qaoa(oracle.cost(x["clauses"], x["n"]), x["n"], x["gammas"], x["betas"])
+        assert abs(res[i].p_success - ref[0]) <= 1e-5
+        assert abs(res[i].expected_cost - ref[1]) <= 1e-5 * ref[1]

@@ -88,3 +88,45 @@ def test_bench_refuses_multiple_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+class _NullCtx:
+    """Context stand-in whose handle is NULL: the library validates the
+    arguments, then rejects the call, so the binding's marshalling runs without
+    a GPU."""
+    handle = ctypes.c_void_p(None)
+
+
+class _FakeTensor:
+    def __init__(self, numel, dtype):
+        self._n, self.dtype = numel, dtype
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def _lib_or_skip():
+    from paper_2401_02852_amd import _binding
+    if not os.path.exists(_binding.library_path()):
+        pytest.skip("libqnae.so not built")
+    return _binding
+
+
+def test_binding_marshalling_without_gpu():
+    import torch
+    b = _lib_or_skip()
+    cl = inst.instance(8, 3, 10, 0)
+    costs = [_FakeTensor(256, torch.uint8), _FakeTensor(512, torch.uint8)]
+    with pytest.raises(b.QNAEError, match="null context"):
+        b.build_cost_diagonals([cl, cl], [8, 9], outs=costs, count_solutions=True, ctx=_NullCtx(), stream=0)
+    with pytest.raises(b.QNAEError, match="null context"):
+        b.qaoa_run_batched(costs, [8, 9], [10, 10], [[0.1, 0.2], []], [[0.3, 0.4], []], ctx=_NullCtx(), stream=0)
+    with pytest.raises(b.QNAEError, match="instance 1"):
+        b.qaoa_run_batched(costs, [8, 9], [10, 300], [[0.1], [0.2]], [[0.3], [0.4]], ctx=_NullCtx(), stream=0)
+    with pytest.raises(b.QNAEError, match="null context"):
+        b.qaoa_run(costs[0], 8, 10, [0.1], [0.2], ctx=_NullCtx(), stream=0)
+    with pytest.raises(b.QNAEError, match="literal"):
+        b.build_cost_diagonal(np.array([[1, 99]], dtype=np.int32), 8, out=costs[0], ctx=_NullCtx(), stream=0)
