@@ -81,6 +81,58 @@ def measured_traffic(stats):
     return tot / launches if launches else None
 
 
+def batched_bench(q, ctx, reps=5, count=512):
+    """512 ragged instances (k in {3, 5}, n in 10..20, p = 5, random angles):
+    instance-layers/s of the batched path and of the plain path (one
+    qnae_build_cost_diagonal + qnae_qaoa_run per instance) on the same GPU."""
+    import torch
+    from paper_2401_02852_amd import instances as inst
+    batch = inst.batched_workload(count=count)
+    ns = [x["n"] for x in batch]
+    ms = [x["m"] for x in batch]
+    cls = [x["clauses"] for x in batch]
+    gs = [x["gammas"] for x in batch]
+    bs = [x["betas"] for x in batch]
+    layers = sum(x["p"] for x in batch)
+    costs = q.build_cost_diagonals(cls, ns, ctx=ctx)
+    q.qaoa_run_batched(costs, ns, ms, gs, bs, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q.build_cost_diagonals(cls, ns, outs=costs, ctx=ctx)
+        q.qaoa_run_batched(costs, ns, ms, gs, bs, ctx=ctx)
+    torch.cuda.synchronize()
+    t_with = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q.qaoa_run_batched(costs, ns, ms, gs, bs, ctx=ctx)
+    torch.cuda.synchronize()
+    t_without = (time.perf_counter() - t0) / reps
+    for i in range(count):  # warm the plain path
+        q.build_cost_diagonal(cls[i], ns[i], out=costs[i], ctx=ctx)
+        q.qaoa_run(costs[i], ns[i], ms[i], gs[i], bs[i], ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(count):
+        q.build_cost_diagonal(cls[i], ns[i], out=costs[i], ctx=ctx)
+        q.qaoa_run(costs[i], ns[i], ms[i], gs[i], bs[i], ctx=ctx)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for i in range(count):
+        q.qaoa_run(costs[i], ns[i], ms[i], gs[i], bs[i], ctx=ctx)
+    torch.cuda.synchronize()
+    t_plain_nc = time.perf_counter() - t0
+    return {"workload": f"{count} random k-NAE-SAT instances, k in {{3,5}}, n in 10..20, p=5, angles U(0,pi)",
+            "instance_layers": layers,
+            "instance_layers_per_s": layers / t_with,
+            "instance_layers_per_s_cost_resident": layers / t_without,
+            "plain_instance_layers_per_s": layers / t_plain,
+            "plain_instance_layers_per_s_cost_resident": layers / t_plain_nc,
+            "speedup_vs_plain": t_plain / t_with,
+            "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +141,7 @@ def main():
     ap.add_argument("--workload", default="nae3_n30_p10")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -164,6 +217,8 @@ def main():
         "layers_only_amp_layer_per_s": (2 ** n) * p / (layer_ms * 1e-3) if layer_ms > 0 else None,
         "result": {"p_success": res.p_success, "expected_cost": res.expected_cost, "norm": res.norm},
     }
+    if not args.no_batched:
+        out["batched"] = batched_bench(q, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)

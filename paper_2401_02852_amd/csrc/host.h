@@ -7,6 +7,7 @@
 
 #include <complex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/qnae.h"
@@ -75,6 +76,10 @@ struct qnae_ctx {
     qnae_host::DevBuf b_blob, b_states, b_partials, b_results;
     qnae_host::HostBuf h_blob, h_results;
     hipEvent_t staging_done = nullptr;  // last async copy out of pinned staging
+    // captured batch launch sequences (hash of shape and argument addresses)
+    bool use_graphs = true;
+    hipStream_t capture_stream = nullptr;
+    std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
     int tile_bits = 13;                 // tile size of the plain sweeps (log2 amplitudes)
     int min_low_run = 4;                // minimum contiguous low run (log2 amplitudes)
     int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes

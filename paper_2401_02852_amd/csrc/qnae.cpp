@@ -25,6 +25,7 @@ int qnae_create(qnae_ctx** out, int device) {
     qnae_ctx* ctx = new qnae_ctx();
     ctx->device = device;
     hipError_t e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = ctx->small.reserve(64);
     if (e == hipSuccess) e = ctx->h_small.reserve(64);
     if (e != hipSuccess) {
@@ -35,6 +36,7 @@ int qnae_create(qnae_ctx** out, int device) {
         const int v = std::atoi(tb);
         if (v >= 12 && v <= 14) ctx->tile_bits = v;
     }
+    if (const char* gr = std::getenv("QNAE_GRAPHS")) ctx->use_graphs = std::atoi(gr) != 0;
     if (const char* pb = std::getenv("QNAE_PAGE_BIT")) {
         const int v = std::atoi(pb);
         if (v >= 4 && v <= 64) ctx->page_bit = v;
@@ -53,6 +55,8 @@ int qnae_destroy(qnae_ctx* ctx) {
     for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results})
         b->release();
     if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto& r : ctx->prof.pending) {
         (void)hipEventDestroy(r.start);
         (void)hipEventDestroy(r.stop);

@@ -85,3 +85,28 @@ def test_batched_workload_512(q):
         ref = oracle.qaoa(oracle.cost(x["clauses"], x["n"]), x["n"], x["gammas"], x["betas"])
         assert abs(res[i].p_success - ref[0]) <= 1e-5
         assert abs(res[i].expected_cost - ref[1]) <= 1e-5 * ref[1]
+
+
+def test_graph_replay_matches_eager(q, monkeypatch):
+    """A batch shape seen again replays a captured launch graph; every replay
+    (with new angles, and eager work in between) equals the eager result."""
+    import torch
+    batch = inst.batched_workload(count=64, seed=5)
+    ns = [x["n"] for x in batch]
+    ms = [x["m"] for x in batch]
+    costs = q.build_cost_diagonals([x["clauses"] for x in batch], ns)
+    monkeypatch.setenv("QNAE_GRAPHS", "0")
+    eager = q.Context()
+    monkeypatch.setenv("QNAE_GRAPHS", "1")
+    graph = q.Context()
+    rng = np.random.default_rng(9)
+    for rep in range(4):
+        g = [rng.uniform(0, np.pi, 5) for _ in batch]
+        b = [rng.uniform(0, np.pi, 5) for _ in batch]
+        ref = q.qaoa_run_batched(costs, ns, ms, g, b, ctx=eager)
+        got = q.qaoa_run_batched(costs, ns, ms, g, b, ctx=graph)
+        assert got == ref, rep
+        q.qaoa_run(costs[rep], ns[rep], ms[rep], g[rep], b[rep], ctx=eager)
+        torch.cuda.synchronize()
+    eager.close()
+    graph.close()
