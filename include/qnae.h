@@ -119,6 +119,29 @@ int qnae_qaoa_run(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype,
                   const double *betas, int32_t p, void *state_dev,
                   qnae_result *out, void *stream);
 
+/* Gradient of F = w_psucc * p_succ + w_energy * E[C] with respect to every
+ * gamma_l and beta_l, by the adjoint (reverse-mode) method written out by
+ * hand: dF/dbeta_l = 2 Im <lam_l|sum_j X_j|psi_l> and
+ * dF/dgamma_l = 2 Im <mu_l|C|phi_l>, with lam_p = W psi_p and
+ * W = diag(w_psucc [C = 0] + w_energy C) (from d<psi|W|psi> = 2 Re <psi|W dpsi>
+ * on the QAOA state of Section 3.3; the objective of Section 3.3's angle
+ * training is the mean success probability).
+ *
+ * The forward pass runs in segments of `checkpoint_every` layers and keeps the
+ * state at each segment end (checkpoint_every = 0 means 4). The reverse pass
+ * applies the inverse layers to lam and psi together and restarts psi from
+ * each checkpoint, so rounding in the uncomputed psi spans at most one segment.
+ * Device memory: ceil(p / checkpoint_every) + 1 states of 2^n complex64 (n >
+ * 13), held by the context.
+ *
+ *   dgammas, dbetas  host, p doubles each (may be NULL when p = 0)
+ *   out              host readout of the forward state (as qnae_qaoa_run)
+ * other arguments as qnae_qaoa_run. Synchronous. Errors: QNAE_EINVAL,
+ * QNAE_ENOMEM, QNAE_EHIP. */
+int qnae_qaoa_grad(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
+                   const double *gammas, const double *betas, int32_t p, double w_psucc, double w_energy,
+                   int32_t checkpoint_every, double *dgammas, double *dbetas, qnae_result *out, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent instances per launch (one GPU, ragged sizes).
  * ------------------------------------------------------------------------- */

@@ -16,6 +16,8 @@ from ._binding import (  # noqa: F401
     default_context,
     library_path,
     load_library,
+    qaoa_grad,
     qaoa_run,
     qaoa_run_batched,
 )
+from .autograd import QAOAFunction  # noqa: F401

@@ -86,9 +86,12 @@ def load_library():
         lib.qnae_build_cost_diagonal_batched.argtypes = [vp, ctypes.POINTER(_CCostJob), ctypes.c_int32, vp]
         lib.qnae_qaoa_run_batched.argtypes = [vp, ctypes.POINTER(_CInstance), ctypes.c_int32,
                                               ctypes.POINTER(_CResult), vp]
+        lib.qnae_qaoa_grad.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _F64P, _F64P,
+                                       ctypes.POINTER(_CResult), vp]
         for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
-                   lib.qnae_qaoa_run_batched):
+                   lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -272,3 +275,30 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, ctx: Optional
     ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))
     return [Result(r.p_success, r.expected_cost, r.norm) for r in res]
+
+
+def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_energy: float = 0.0,
+              checkpoint_every: int = 4, ctx: Optional[Context] = None, stream=None):
+    """Adjoint gradient of w_psucc * p_succ + w_energy * E[C].
+
+    Returns (dgammas, dbetas, Result) with float64 numpy arrays."""
+    g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
+    if g.shape != b.shape or g.ndim != 1:
+        raise ValueError("gammas and betas must be 1-D of equal length")
+    if cost.numel() != (1 << n):
+        raise ValueError(f"cost has {cost.numel()} entries, expected 2^{n}")
+    import torch
+    code = QNAE_U8 if cost.dtype == torch.uint8 else QNAE_U16
+    p = g.shape[0]
+    dg = np.zeros(p, dtype=np.float64)
+    db = np.zeros(p, dtype=np.float64)
+    res = _CResult()
+    ctx = ctx or default_context()
+    _check(load_library().qnae_qaoa_grad(
+        ctx.handle, ctypes.c_void_p(cost.data_ptr()), code, n, m,
+        g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
+        float(w_psucc), float(w_energy), int(checkpoint_every),
+        dg.ctypes.data_as(_F64P) if p else None, db.ctypes.data_as(_F64P) if p else None,
+        ctypes.byref(res), _stream(stream)))
+    return dg, db, Result(res.p_success, res.expected_cost, res.norm)

@@ -1,0 +1,391 @@
+// Reverse pass of the gradient of F = w_psucc p_succ + w_energy E[C] with
+// respect to every gamma_l and beta_l.
+//
+// With psi_l the state after layer l, phi_l the state after its phase,
+// W = diag(w_psucc [C = 0] + w_energy C) and lam_l = (U_{l+1} .. U_p)^dagger W psi_p,
+// d<psi|W|psi>/dtheta = 2 Re <psi|W d psi> gives
+//   dF/dbeta_l  = 2 Im <lam_l | sum_j X_j | psi_l>,
+//   mu_l        = U_B(beta_l)^dagger lam_l,   phi_l = U_B(beta_l)^dagger psi_l,
+//   dF/dgamma_l = 2 Im <mu_l | C | phi_l>,
+//   lam_{l-1}   = U_C(gamma_l)^dagger mu_l,   psi_{l-1} = U_C(gamma_l)^dagger phi_l
+// (U_B and U_C as in Section 2.1 / Section 3.2). A reverse sweep applies the
+// inverse one-qubit factors to lam and psi alike. Because X_j commutes with
+// every one-qubit factor, <lam|X_j|psi> is the same before and after any of
+// them is applied to both states, so the X_j terms of a qubit group are summed
+// inside the sweep that inverts that group. The inverse phase of the layer is
+// fused in the same way as the forward phase.
+#include "tile.h"
+
+namespace qnae {
+namespace {
+
+using namespace tile;
+
+// a' = c a - i s b for both members of the pairs on register bit S.
+template <int S>
+__device__ __forceinline__ void ebfly(float2 (&v)[32], float c, float s) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 a = v[j], b = v[j | (1 << S)];
+        v[j] = make_float2(fmaf(c, a.x, s * b.y), fmaf(c, a.y, -s * b.x));
+        v[j | (1 << S)] = make_float2(fmaf(c, b.x, s * a.y), fmaf(c, b.y, -s * a.x));
+    }
+}
+
+// Im of sum over pairs on register bit S of conj(l_a) p_b + conj(l_b) p_a,
+// i.e. the pairs' share of Im <l|X|p> for that bit.
+template <int S>
+__device__ __forceinline__ float ipair(const float2 (&l)[32], const float2 (&p)[32]) {
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 la = l[j], lb = l[j | (1 << S)], pa = p[j], pb = p[j | (1 << S)];
+        acc = fmaf(la.x, pb.y, acc);
+        acc = fmaf(-la.y, pb.x, acc);
+        acc = fmaf(lb.x, pa.y, acc);
+        acc = fmaf(-lb.y, pa.x, acc);
+    }
+    return acc;
+}
+
+template <int S>
+__device__ __forceinline__ void adj_bit(float2 (&l)[32], float2 (&p)[32], float c, float s, float& acc) {
+    acc += ipair<S>(l, p);
+    ebfly<S>(l, c, s);
+    ebfly<S>(p, c, s);
+}
+
+__device__ __forceinline__ void adj_mix(float2 (&l)[32], float2 (&p)[32], uint32_t sm, float c, float s, float& acc) {
+    if (sm & 1u) adj_bit<0>(l, p, c, s, acc);
+    if (sm & 2u) adj_bit<1>(l, p, c, s, acc);
+    if (sm & 4u) adj_bit<2>(l, p, c, s, acc);
+    if (sm & 8u) adj_bit<3>(l, p, c, s, acc);
+    if (sm & 16u) adj_bit<4>(l, p, c, s, acc);
+}
+
+// Both register arrays from layout FROM to layout TO through one LDS buffer.
+template <int TB, int FROM, int TO>
+__device__ __forceinline__ void xpose2(float2* lds, float2 (&l)[32], float2 (&p)[32], uint32_t lane, uint32_t wave) {
+    __syncthreads();
+    to_lds<TB, FROM>(lds, l, lane, wave);
+    __syncthreads();
+    from_lds<TB, TO>(lds, l, lane, wave);
+    __syncthreads();
+    to_lds<TB, FROM>(lds, p, lane, wave);
+    __syncthreads();
+    from_lds<TB, TO>(lds, p, lane, wave);
+}
+
+template <typename CT, int KIND>
+__global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a) {
+    constexpr int TB = kAdjointTileBits;
+    constexpr int WB = TB - 11;
+    constexpr int NT = 64 << WB;
+    constexpr bool PHASE = KIND == AK_BOUNDARY || KIND == AK_END;
+    constexpr bool POST = KIND == AK_BOUNDARY;
+    constexpr bool LUT_LDS = sizeof(CT) == 1;
+    constexpr int PK = 4 / (int)sizeof(CT);
+    constexpr int NC = PHASE ? 32 / PK : 1;
+    using L = Lay<TB>;
+    __shared__ float2 lds[lds_elems<TB>()];
+    __shared__ float2 lut_s[PHASE && LUT_LDS ? 256 : 1];
+    __shared__ double red[3][1 << WB];
+
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t t = blockIdx.x;
+    const uint32_t ntiles = 1u << a.nw;
+    uint64_t bitval[TB];
+#pragma unroll
+    for (int i = 0; i < TB; ++i) bitval[i] = 1ull << a.pos[i];
+    auto scat = [&](uint32_t e) -> uint64_t {
+        uint64_t x = 0;
+#pragma unroll
+        for (int i = 0; i < TB; ++i)
+            if ((e >> i) & 1u) x |= bitval[i];
+        return x;
+    };
+    uint64_t w = ntiles >= 8 ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
+    uint64_t base = 0;
+    for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull) {
+        if (w & 1ull) base |= m & (~m + 1ull);
+        w >>= 1;
+    }
+
+    uint32_t cvp[NC];
+    if (PHASE) {
+        const CT* const c2 = (const CT*)a.cost + base + scat(L::t2(lane, wave));
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            uint32_t wv = 0u;
+#pragma unroll
+            for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2(PK * i + q))] << (8 * sizeof(CT) * q);
+            cvp[i] = wv;
+        }
+        if (LUT_LDS)
+            for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
+    }
+    const uint32_t lut_last = (uint32_t)a.lut_len - 1u;
+    auto lut = [&](uint32_t cidx) -> float2 { return LUT_LDS ? lut_s[cidx] : a.lut[min(cidx, lut_last)]; };
+    auto cval = [&](int j) -> uint32_t {
+        return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
+    };
+
+    float2 l[32], p[32];
+    {
+        const uint64_t o0 = base + scat(L::t0(lane, wave));
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const uint64_t off = o0 + scat(L::s0(2 * jj));
+            const float4 ql = *(const float4*)(a.lam + off);
+            const float4 qp = *(const float4*)(a.psi + off);
+            l[2 * jj] = make_float2(ql.x, ql.y);
+            l[2 * jj + 1] = make_float2(ql.z, ql.w);
+            p[2 * jj] = make_float2(qp.x, qp.y);
+            p[2 * jj + 1] = make_float2(qp.z, qp.w);
+        }
+    }
+    float acc_pre = 0.f, acc_g = 0.f, acc_post = 0.f;
+    {
+        const uint32_t m = a.pre_mask;
+        adj_mix(l, p, L::sm0(m), a.pre_c, a.pre_s, acc_pre);
+        if (L::sm1(m)) {
+            xpose2<TB, 0, 1>(lds, l, p, lane, wave);
+            adj_mix(l, p, L::sm1(m), a.pre_c, a.pre_s, acc_pre);
+            xpose2<TB, 1, 2>(lds, l, p, lane, wave);
+        } else {
+            xpose2<TB, 0, 2>(lds, l, p, lane, wave);
+        }
+        adj_mix(l, p, L::sm2(m), a.pre_c, a.pre_s, acc_pre);
+    }
+    if (PHASE) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const uint32_t c = cval(j);
+            const float im = fmaf(l[j].x, p[j].y, -l[j].y * p[j].x);
+            acc_g = fmaf((float)c, im, acc_g);
+            const float2 e = lut(c);
+            l[j] = cmul(l[j], e);
+            p[j] = cmul(p[j], e);
+        }
+    }
+    if (POST) {
+        const uint32_t m = a.post_mask;
+        adj_mix(l, p, L::sm2(m), a.post_c, a.post_s, acc_post);
+        if (L::sm1(m)) {
+            xpose2<TB, 2, 1>(lds, l, p, lane, wave);
+            adj_mix(l, p, L::sm1(m), a.post_c, a.post_s, acc_post);
+            xpose2<TB, 1, 0>(lds, l, p, lane, wave);
+        } else {
+            xpose2<TB, 2, 0>(lds, l, p, lane, wave);
+        }
+        adj_mix(l, p, L::sm0(m), a.post_c, a.post_s, acc_post);
+        const uint64_t o0 = base + scat(L::t0(lane, wave));
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const uint64_t off = o0 + scat(L::s0(2 * jj));
+            *(float4*)(a.lam + off) = make_float4(l[2 * jj].x, l[2 * jj].y, l[2 * jj + 1].x, l[2 * jj + 1].y);
+            if (a.store_psi)
+                *(float4*)(a.psi + off) = make_float4(p[2 * jj].x, p[2 * jj].y, p[2 * jj + 1].x, p[2 * jj + 1].y);
+        }
+    } else {
+        const uint64_t o2 = base + scat(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const uint64_t off = o2 + scat(L::s2(j));
+            a.lam[off] = l[j];
+            if (a.store_psi) a.psi[off] = p[j];
+        }
+    }
+    double d0 = acc_pre, d1 = acc_g, d2 = acc_post;
+    for (int off = 32; off > 0; off >>= 1) {
+        d0 += __shfl_xor(d0, off);
+        d1 += __shfl_xor(d1, off);
+        d2 += __shfl_xor(d2, off);
+    }
+    if (lane == 0) {
+        red[0][wave] = d0;
+        red[1][wave] = d1;
+        red[2][wave] = d2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double sum = 0.0;
+        for (int q = 0; q < (1 << WB); ++q) sum += red[threadIdx.x][q];
+        a.partials[3 * (size_t)t + threadIdx.x] = sum;
+    }
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void weight_kernel(const CT* cost, const float2* psi, float2* lam, uint64_t N,
+                                                     float w_psucc, float w_energy) {
+    const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (x >= N) return;
+    const uint32_t c = cost[x];
+    const float w = w_energy * (float)c + (c == 0u ? w_psucc : 0.f);
+    const float2 v = psi[x];
+    lam[x] = make_float2(w * v.x, w * v.y);
+}
+
+// ---------------------------------------------------------------------------
+// Whole gradient for n <= 13 in one workgroup.
+// ---------------------------------------------------------------------------
+
+// Pairs (x, x | 2^j) of bit j over the resident states: first Im<l|X_j|p>
+// (when l != null) then a' = c a - i s b on every state given.
+__device__ __forceinline__ float resident_bit(float2* l, float2* p, uint32_t N, int j, float c, float s) {
+    float acc = 0.f;
+    const uint32_t bit = 1u << j;
+    for (uint32_t task = threadIdx.x; task < N / 2; task += 256) {
+        const uint32_t x = ((task >> j) << (j + 1)) | (task & (bit - 1u));
+        const uint32_t y = x | bit;
+        const float2 pa = p[x], pb = p[y];
+        if (l) {
+            const float2 la = l[x], lb = l[y];
+            acc = fmaf(la.x, pb.y, acc);
+            acc = fmaf(-la.y, pb.x, acc);
+            acc = fmaf(lb.x, pa.y, acc);
+            acc = fmaf(-lb.y, pa.x, acc);
+            l[x] = make_float2(fmaf(c, la.x, s * lb.y), fmaf(c, la.y, -s * lb.x));
+            l[y] = make_float2(fmaf(c, lb.x, s * la.y), fmaf(c, lb.y, -s * la.x));
+        }
+        p[x] = make_float2(fmaf(c, pa.x, s * pb.y), fmaf(c, pa.y, -s * pb.x));
+        p[y] = make_float2(fmaf(c, pb.x, s * pa.y), fmaf(c, pb.y, -s * pa.x));
+    }
+    __syncthreads();
+    return acc;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+template <typename CT>
+__global__ __launch_bounds__(256) void resident_grad_kernel(const ResidentGradArgs a) {
+    __shared__ float2 ls[1 << 13];
+    __shared__ float2 ps[1 << 13];
+    __shared__ double red[4];
+    const int n = a.n;
+    const uint32_t N = 1u << n;
+    const uint32_t tid = threadIdx.x;
+    const CT* cost = (const CT*)a.cost;
+    const uint32_t last = (uint32_t)a.lut_len - 1u;
+    const float amp = __builtin_ldexpf(1.0f, -n) == 0.f ? 0.f : sqrtf(__builtin_ldexpf(1.0f, -n));
+    // forward
+    for (int l = 0; l < a.p; ++l) {
+        const float2* lut = a.luts + (size_t)l * a.lut_len;
+        for (uint32_t x = tid; x < N; x += 256) {
+            const float2 e = lut[min((uint32_t)cost[x], last)];
+            ps[x] = l == 0 ? make_float2(amp * e.x, amp * e.y) : cmul(ps[x], e);
+        }
+        __syncthreads();
+        const float2 cs = a.cs[l];
+        for (int j = 0; j < n; ++j) resident_bit(nullptr, ps, N, j, cs.x, cs.y);
+        if ((l + 1) % a.every == 0 && l + 1 < a.p) {
+            float2* ck = a.ckpt + (size_t)((l + 1) / a.every - 1) * N;
+            for (uint32_t x = tid; x < N; x += 256) ck[x] = ps[x];
+        }
+    }
+    if (a.p == 0)
+        for (uint32_t x = tid; x < N; x += 256) ps[x] = make_float2(amp, 0.f);
+    __syncthreads();
+    // readout and lam = W psi
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (uint32_t x = tid; x < N; x += 256) {
+        const float2 v = ps[x];
+        const uint32_t c = cost[x];
+        const float pr = fmaf(v.x, v.x, v.y * v.y);
+        s2 += pr;
+        s1 += (double)c * pr;
+        s0 += c == 0u ? pr : 0.0;
+        const float w = (float)a.w_energy * (float)c + (c == 0u ? (float)a.w_psucc : 0.f);
+        ls[x] = make_float2(w * v.x, w * v.y);
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (tid == 0) {
+        a.out[0] = s0;
+        a.out[1] = s1;
+        a.out[2] = s2;
+    }
+    __syncthreads();
+    // reverse
+    for (int l = a.p - 1; l >= 0; --l) {
+        const float2 cs = a.cs[l];
+        float accb = 0.f;
+        for (int j = 0; j < n; ++j) accb += resident_bit(ls, ps, N, j, cs.x, -cs.y);
+        const float2* lut = a.luts + (size_t)l * a.lut_len;
+        float accg = 0.f;
+        for (uint32_t x = tid; x < N; x += 256) {
+            const uint32_t c = cost[x];
+            const float2 lv = ls[x], pv = ps[x];
+            accg = fmaf((float)c, fmaf(lv.x, pv.y, -lv.y * pv.x), accg);
+            const float2 e = lut[min(c, last)];
+            const float2 ec = make_float2(e.x, -e.y);
+            ls[x] = cmul(lv, ec);
+            ps[x] = cmul(pv, ec);
+        }
+        const double db = block_sum((double)accb, red);
+        const double dg = block_sum((double)accg, red);
+        if (tid == 0) {
+            a.out[3 + l] = 2.0 * dg;
+            a.out[3 + a.p + l] = 2.0 * db;
+        }
+        if (l % a.every == 0 && l > 0) {
+            const float2* ck = a.ckpt + (size_t)(l / a.every - 1) * N;
+            for (uint32_t x = tid; x < N; x += 256) ps[x] = ck[x];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s) {
+    const dim3 grid(1u << a.nw), block(256);
+    if (dtype == 1) {
+        switch (kind) {
+            case AK_MIDDLE: hipLaunchKernelGGL((adjoint_kernel<uint8_t, AK_MIDDLE>), grid, block, 0, s, a); break;
+            case AK_BOUNDARY: hipLaunchKernelGGL((adjoint_kernel<uint8_t, AK_BOUNDARY>), grid, block, 0, s, a); break;
+            case AK_END: hipLaunchKernelGGL((adjoint_kernel<uint8_t, AK_END>), grid, block, 0, s, a); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (kind) {
+            case AK_MIDDLE: hipLaunchKernelGGL((adjoint_kernel<uint16_t, AK_MIDDLE>), grid, block, 0, s, a); break;
+            case AK_BOUNDARY: hipLaunchKernelGGL((adjoint_kernel<uint16_t, AK_BOUNDARY>), grid, block, 0, s, a); break;
+            case AK_END: hipLaunchKernelGGL((adjoint_kernel<uint16_t, AK_END>), grid, block, 0, s, a); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_weight(int dtype, const void* cost, const float2* psi, float2* lam, int n, double w_psucc,
+                         double w_energy, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    const dim3 grid((uint32_t)((N + 255) / 256)), block(256);
+    if (dtype == 1)
+        hipLaunchKernelGGL(weight_kernel<uint8_t>, grid, block, 0, s, (const uint8_t*)cost, psi, lam, N,
+                           (float)w_psucc, (float)w_energy);
+    else
+        hipLaunchKernelGGL(weight_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)cost, psi, lam, N,
+                           (float)w_psucc, (float)w_energy);
+    return hipGetLastError();
+}
+
+hipError_t launch_resident_grad(int dtype, const ResidentGradArgs& a, hipStream_t s) {
+    if (dtype == 1)
+        hipLaunchKernelGGL(resident_grad_kernel<uint8_t>, dim3(1), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(resident_grad_kernel<uint16_t>, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace qnae

@@ -19,21 +19,6 @@ using qnae::ClauseRec;
 using qnae::MixForm;
 using qnae::SweepArgs;
 
-namespace {
-
-// Bump allocator over a host blob that mirrors a device buffer.
-struct Blob {
-    size_t size = 0;
-    size_t take(size_t bytes, size_t align = 256) {
-        size = (size + align - 1) / align * align;
-        const size_t at = size;
-        size += bytes;
-        return at;
-    }
-};
-
-}  // namespace
-
 extern "C" {
 
 int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, int32_t count, void* stream) {
@@ -256,6 +241,7 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         for (size_t q = 0; q < res_members[g].size(); ++q) {
             const int i = res_members[g][q];
             const Job& J = jobs[i];
+            ra[q].state_in = nullptr;
             ra[q].cost = inst[i].cost_dev;
             ra[q].luts = d_luts + J.lut_at;
             ra[q].forms = d_forms + J.form_at;

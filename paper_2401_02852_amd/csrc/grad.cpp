@@ -1,0 +1,239 @@
+// qnae_qaoa_grad: gradient of w_psucc p_succ + w_energy E[C] by a hand-written
+// adjoint pass (include/qnae.h). See adjoint.hip for the formulas.
+//
+// n <= 13: one workgroup does the forward pass, the readout and the reverse
+// pass with both states in LDS. Larger n: the forward pass runs as sweep
+// segments of `every` layers that each keep their final state (checkpoints);
+// lam = W psi_p; then for each segment from the last, reverse sweeps take lam
+// and that segment's checkpoint (psi, uncomputed in place) through the inverse
+// layers, summing the inner products per tile.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "host.h"
+
+using namespace qnae_host;
+using qnae::MixForm;
+using qnae::SweepArgs;
+
+extern "C" {
+
+int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
+                   const double* gammas, const double* betas, int32_t p, double w_psucc, double w_energy,
+                   int32_t checkpoint_every, double* dgammas, double* dbetas, qnae_result* out, void* stream) {
+    if (int rc = check_run_args(n, m, cost_dtype, cost_dev, gammas, betas, p)) return rc;
+    if (!out) return fail(QNAE_EINVAL, "null result pointer");
+    if (p > 0 && (!dgammas || !dbetas)) return fail(QNAE_EINVAL, "null gradient arrays with p=%d", p);
+    if (checkpoint_every < 0) return fail(QNAE_EINVAL, "checkpoint_every=%d < 0", checkpoint_every);
+    if (!std::isfinite(w_psucc) || !std::isfinite(w_energy)) return fail(QNAE_EINVAL, "non-finite weights");
+    const int every = checkpoint_every > 0 ? checkpoint_every : 4;
+    if (int rc = enter(ctx)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int lut_len = m + 1;
+    const size_t N = (size_t)1 << n;
+
+    if (n <= 13) {
+        // tables: forward phases exp(-i gamma c) (unit), (cos b, sin b)
+        Blob B;
+        const size_t lut_at = B.take(sizeof(float2) * (size_t)(p > 0 ? p : 1) * lut_len);
+        const size_t cs_at = B.take(sizeof(float2) * (size_t)(p > 0 ? p : 1));
+        const size_t out_at = B.take(sizeof(double) * (3 + 2 * (size_t)p));
+        HIP_TRY(ctx->h_blob.reserve(B.size));
+        HIP_TRY(ctx->g_blob.reserve(B.size));
+        char* h = (char*)ctx->h_blob.ptr;
+        char* d = (char*)ctx->g_blob.ptr;
+        float2* lut = (float2*)(h + lut_at);
+        float2* cs = (float2*)(h + cs_at);
+        for (int l = 0; l < p; ++l) {
+            for (int c = 0; c <= m; ++c)
+                lut[(size_t)l * lut_len + c] = make_float2((float)std::cos(gammas[l] * c), (float)-std::sin(gammas[l] * c));
+            cs[l] = make_float2((float)std::cos(betas[l]), (float)std::sin(betas[l]));
+        }
+        const int nck = p > 1 ? (p - 1) / every : 0;
+        HIP_TRY(ctx->g_states.reserve(sizeof(float2) * N * (size_t)(nck > 0 ? nck : 1)));
+        HIP_TRY(hipMemcpyAsync(d, h, out_at, hipMemcpyHostToDevice, s));
+        qnae::ResidentGradArgs a;
+        a.cost = cost_dev;
+        a.luts = (const float2*)(d + lut_at);
+        a.cs = (const float2*)(d + cs_at);
+        a.ckpt = (float2*)ctx->g_states.ptr;
+        a.out = (double*)(d + out_at);
+        a.w_psucc = w_psucc;
+        a.w_energy = w_energy;
+        a.n = n;
+        a.p = p;
+        a.lut_len = lut_len;
+        a.every = every;
+        HIP_TRY(timed(ctx, K_RESIDENT, std::ldexp(3.0 * p, n), s, [&] { return qnae::launch_resident_grad(cost_dtype, a, s); }));
+        HIP_TRY(hipMemcpyAsync(h + out_at, d + out_at, sizeof(double) * (3 + 2 * (size_t)p), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(ctx->staging_done, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double* r = (const double*)(h + out_at);
+        out->p_success = r[0];
+        out->expected_cost = r[1];
+        out->norm = r[2];
+        for (int l = 0; l < p; ++l) {
+            dgammas[l] = r[3 + l];
+            dbetas[l] = r[3 + p + l];
+        }
+        return QNAE_OK;
+    }
+
+    // ---- tiled path ----------------------------------------------------------
+    const int TB = qnae::kAdjointTileBits;
+    const int nseg = p > 0 ? (p + every - 1) / every : 1;
+    const std::vector<Group> groups = make_groups(n, TB, ctx->min_low_run, ctx->page_bit);
+    const uint32_t tiles = 1u << (n - TB);
+    // checkpoints 0 .. nseg-1 (state after each segment), then lam
+    HIP_TRY(ctx->g_states.reserve(sizeof(float2) * N * (size_t)(nseg + 1)));
+    float2* ck = (float2*)ctx->g_states.ptr;
+    float2* lam = ck + N * (size_t)nseg;
+
+    // Host tables for every forward segment and every reverse segment.
+    struct Seg {
+        int a, b;
+        size_t flut_at, blut_at;
+        SweepPlan plan;
+        std::vector<AdjOp> aops;
+        std::complex<double> final_scale;
+    };
+    std::vector<Seg> segs(nseg);
+    const int T = p > 0 ? p : 1;
+    std::vector<float2> ftab((size_t)T * lut_len), btab((size_t)T * lut_len);
+    std::vector<MixForm> forms(T);
+    int total_aops = 0;
+    for (int j = 0; j < nseg; ++j) {
+        Seg& S = segs[j];
+        S.a = j * every;
+        S.b = p > 0 ? std::min(p, S.a + every) : 0;
+        const int L = S.b - S.a;
+        S.flut_at = (size_t)S.a * lut_len;
+        const std::complex<double> first = j == 0 ? std::complex<double>(std::pow(2.0, -0.5 * n), 0.0)
+                                                  : std::complex<double>(1.0, 0.0);
+        S.final_scale = build_tables_from(n, m, gammas + S.a, betas + S.a, L, ftab.data() + S.flut_at,
+                                          forms.data() + S.a, first);
+        plan_sweeps(S.plan, n, m, L, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, true, forms.data() + S.a,
+                    S.final_scale, j > 0);
+        // reverse tables: b-layer i is forward layer b - 1 - i, exp(+i gamma c)
+        S.blut_at = (size_t)S.a * lut_len;
+        for (int i = 0; i < L; ++i) {
+            const double g = gammas[S.b - 1 - i];
+            for (int c = 0; c <= m; ++c)
+                btab[S.blut_at + (size_t)i * lut_len + c] = make_float2((float)std::cos(g * c), (float)std::sin(g * c));
+        }
+        if (L > 0) S.aops = make_adjoint_plan((int)groups.size(), L);
+        total_aops += (int)S.aops.size();
+    }
+    Blob B;
+    const size_t flut_at = B.take(sizeof(float2) * ftab.size());
+    const size_t blut_at = B.take(sizeof(float2) * btab.size());
+    const size_t rp_at = B.take(sizeof(double*) * (total_aops + 1));
+    const size_t rb_at = B.take(sizeof(uint32_t) * (total_aops + 1));
+    const size_t ro_at = B.take(sizeof(double*) * (total_aops + 1));
+    const size_t res_at = B.take(sizeof(double) * 3 * (total_aops + 1));
+    HIP_TRY(ctx->h_blob.reserve(B.size));
+    HIP_TRY(ctx->g_blob.reserve(B.size));
+    HIP_TRY(ctx->g_partials.reserve(sizeof(double) * 3 * tiles * (size_t)(total_aops + 1)));
+    char* h = (char*)ctx->h_blob.ptr;
+    char* d = (char*)ctx->g_blob.ptr;
+    double* parts = (double*)ctx->g_partials.ptr;
+    double* res_dev = (double*)(d + res_at);
+    std::memcpy(h + flut_at, ftab.data(), sizeof(float2) * ftab.size());
+    std::memcpy(h + blut_at, btab.data(), sizeof(float2) * btab.size());
+    {
+        const double** rp = (const double**)(h + rp_at);
+        uint32_t* rb = (uint32_t*)(h + rb_at);
+        double** ro = (double**)(h + ro_at);
+        for (int q = 0; q <= total_aops; ++q) {  // entry total_aops: forward readout
+            rp[q] = parts + 3 * (size_t)tiles * q;
+            rb[q] = tiles;
+            ro[q] = res_dev + 3 * (size_t)q;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(d, h, B.size, hipMemcpyHostToDevice, s));
+    const float2* d_flut = (const float2*)(d + flut_at);
+    const float2* d_blut = (const float2*)(d + blut_at);
+
+    // forward segments
+    double* fwd_parts = parts + 3 * (size_t)tiles * total_aops;
+    for (int j = 0; j < nseg; ++j) {
+        const Seg& S = segs[j];
+        float2* psi = ck + N * (size_t)j;
+        for (size_t q = 0; q < S.plan.ops.size(); ++q) {
+            const Op& op = S.plan.ops[q];
+            SweepArgs a;
+            sweep_args(S.plan, op, psi, cost_dev, d_flut + S.flut_at, fwd_parts, &a);
+            if (q == 0 && j > 0) a.psi_in = ck + N * (size_t)(j - 1);
+            HIP_TRY(timed(ctx, op_profile_kind(op), op_bytes(S.plan, op), s,
+                          [&] { return qnae::launch_sweep(TB, cost_dtype, op.kind, a, s); }));
+        }
+        if (S.plan.p > 0 && S.plan.flips_before[S.plan.p]) HIP_TRY(qnae::launch_reverse(psi, N, s));
+    }
+    // lam = W psi_p
+    float2* psi_p = ck + N * (size_t)(nseg - 1);
+    HIP_TRY(qnae::launch_weight(cost_dtype, cost_dev, psi_p, lam, n, w_psucc, w_energy, s));
+    // reverse segments, last first
+    int q = 0;
+    std::vector<std::pair<int, const AdjOp*>> order;  // (segment, op) in launch order
+    for (int j = nseg - 1; j >= 0; --j) {
+        const Seg& S = segs[j];
+        float2* psi = ck + N * (size_t)j;
+        for (const AdjOp& op : S.aops) {
+            const Group& g = groups[op.group];
+            qnae::AdjointArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.lam = lam;
+            a.psi = psi;
+            a.cost = cost_dev;
+            a.lut = op.phase_layer >= 0 ? d_blut + S.blut_at + (size_t)op.phase_layer * lut_len : nullptr;
+            a.partials = parts + 3 * (size_t)tiles * q;
+            a.n = n;
+            a.nw = n - TB;
+            a.lut_len = lut_len;
+            for (int i = 0; i < TB; ++i) {
+                a.pos[i] = (uint8_t)g.pos[i];
+                a.tile_bits |= 1ull << g.pos[i];
+            }
+            a.wmask = ((1ull << n) - 1ull) & ~a.tile_bits;
+            a.pre_mask = op.pre_layer >= 0 ? g.mask : 0u;
+            a.post_mask = op.post_layer >= 0 ? g.mask : 0u;
+            if (op.pre_layer >= 0) {
+                const double b = betas[S.b - 1 - op.pre_layer];
+                a.pre_c = (float)std::cos(b);
+                a.pre_s = (float)-std::sin(b);
+            }
+            if (op.post_layer >= 0) {
+                const double b = betas[S.b - 1 - op.post_layer];
+                a.post_c = (float)std::cos(b);
+                a.post_s = (float)-std::sin(b);
+            }
+            a.store_psi = op.kind == qnae::AK_END ? 0 : 1;
+            const double bytes = std::ldexp(32.0 - (a.store_psi ? 0.0 : 8.0) + (op.phase_layer >= 0 ? (cost_dtype == QNAE_U8 ? 1.0 : 2.0) : 0.0), n);
+            HIP_TRY(timed(ctx, K_ADJOINT, bytes, s, [&] { return qnae::launch_adjoint(cost_dtype, op.kind, a, s); }));
+            order.emplace_back(j, &op);
+            ++q;
+        }
+    }
+    HIP_TRY(qnae::launch_final_reduce_batch((const double* const*)(d + rp_at), (const uint32_t*)(d + rb_at),
+                                            (double* const*)(d + ro_at), total_aops + 1, s));
+    HIP_TRY(hipMemcpyAsync(h + res_at, d + res_at, sizeof(double) * 3 * (total_aops + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ctx->staging_done, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double* r = (const double*)(h + res_at);
+    for (int l = 0; l < p; ++l) dgammas[l] = dbetas[l] = 0.0;
+    for (int k = 0; k < total_aops; ++k) {
+        const Seg& S = segs[order[k].first];
+        const AdjOp& op = *order[k].second;
+        if (op.pre_layer >= 0) dbetas[S.b - 1 - op.pre_layer] += 2.0 * r[3 * k];
+        if (op.phase_layer >= 0) dgammas[S.b - 1 - op.phase_layer] += 2.0 * r[3 * k + 1];
+        if (op.post_layer >= 0) dbetas[S.b - 1 - op.post_layer] += 2.0 * r[3 * k + 2];
+    }
+    const double sc = std::norm(segs[nseg - 1].final_scale);
+    out->p_success = r[3 * total_aops] * sc;
+    out->expected_cost = r[3 * total_aops + 1] * sc;
+    out->norm = r[3 * total_aops + 2] * sc;
+    return QNAE_OK;
+}
+
+}  // extern "C"

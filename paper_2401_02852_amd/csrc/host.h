@@ -45,7 +45,7 @@ struct HostBuf {
 
 // Event-timed kernel tallies (qnae_profile_*).
 enum { K_COST, K_FIRST, K_MIDDLE, K_BOUNDARY, K_FINAL, K_RESIDENT, K_REDUCE, K_BATCH_COST, K_BATCH_RESIDENT,
-       K_BATCH_SWEEP, K_BATCH_REDUCE, K_KINDS };
+       K_BATCH_SWEEP, K_BATCH_REDUCE, K_ADJOINT, K_KINDS };
 
 struct Profiler {
     struct Rec {
@@ -64,6 +64,17 @@ struct Profiler {
 
 constexpr int kResidentMaxN = 14;
 
+// Bump allocator for a pinned host blob mirrored by a device buffer.
+struct Blob {
+    size_t size = 0;
+    size_t take(size_t bytes, size_t align = 256) {
+        size = (size + align - 1) / align * align;
+        const size_t at = size;
+        size += bytes;
+        return at;
+    }
+};
+
 }  // namespace qnae_host
 
 struct qnae_ctx {
@@ -74,6 +85,8 @@ struct qnae_ctx {
     qnae_host::HostBuf h_luts, h_clauses, h_forms, h_small;
     // batched path: uploaded tables and work lists, states, partial sums, results
     qnae_host::DevBuf b_blob, b_states, b_partials, b_results;
+    // gradient: checkpoints + adjoint state, tables, partial sums
+    qnae_host::DevBuf g_states, g_blob, g_partials;
     qnae_host::HostBuf h_blob, h_results;
     hipEvent_t staging_done = nullptr;  // last async copy out of pinned staging
     // captured batch launch sequences (hash of shape and argument addresses)
@@ -116,6 +129,10 @@ int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k);
 // mixer forms; returns the scalar factor left after the last layer.
 std::complex<double> build_tables(int n, int m, const double* gammas, const double* betas, int p, float2* tables,
                                   qnae::MixForm* forms);
+// The same with the first table scaled by `first` instead of 2^{-n/2} (a run
+// that starts from a given, normalised state uses 1).
+std::complex<double> build_tables_from(int n, int m, const double* gammas, const double* betas, int p,
+                                       float2* tables, qnae::MixForm* forms, std::complex<double> first);
 
 struct Group {
     std::vector<int> pos;  // global bit of each tile bit
@@ -129,7 +146,8 @@ struct Op {
 };
 
 std::vector<Group> make_groups(int n, int TB, int cmin, int page);
-std::vector<Op> make_plan(int ngroups, int p);
+// from_state: the first sweep loads a given state instead of starting from |+>.
+std::vector<Op> make_plan(int ngroups, int p, bool from_state = false);
 
 // A tiled (n > kResidentMaxN) solve: groups, op sequence and per-layer data.
 struct SweepPlan {
@@ -144,7 +162,16 @@ struct SweepPlan {
 
 // Plans a tiled solve; `forms` are the per-layer mixer forms from build_tables.
 void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, bool keep,
-                 const qnae::MixForm* forms, std::complex<double> final_scale);
+                 const qnae::MixForm* forms, std::complex<double> final_scale, bool from_state = false);
+
+// Reverse pass of a gradient over L layers ("b-layers", the last forward
+// layer first): each b-layer inverts the mixer of every group, then the phase.
+struct AdjOp {
+    int group;
+    int kind;                                  // qnae::AdjointKind
+    int pre_layer, phase_layer, post_layer;    // b-layer indices, -1 when unused
+};
+std::vector<AdjOp> make_adjoint_plan(int ngroups, int L);
 // Kernel arguments of one op.
 void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost, const float2* luts, double* partials,
                 qnae::SweepArgs* a);

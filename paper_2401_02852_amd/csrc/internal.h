@@ -67,7 +67,8 @@ enum SweepKind {
 };
 
 struct SweepArgs {
-    float2* psi;
+    float2* psi;           // state written (and read, unless psi_in is set)
+    const float2* psi_in;  // state read by the load (== psi for in-place sweeps)
     const void* cost;
     const float2* lut;     // phase table of this sweep (lut_len entries)
     double* partials;      // 3 doubles per block for readout kinds
@@ -101,6 +102,7 @@ hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s);
 
 // Whole circuit for n <= 14 in one workgroup (state resident in LDS).
 struct ResidentArgs {
+    const float2* state_in;  // optional initial state (true scale); |+> when null
     const void* cost;
     const float2* luts;    // p (or 1 when p = 0) tables of lut_len entries
     const MixForm* forms;  // p entries (device)
@@ -111,6 +113,54 @@ struct ResidentArgs {
 };
 
 hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradient) sweeps: the reverse pass carries the adjoint state lam
+// and the forward state psi together and applies the inverse of each layer to
+// both (psi is uncomputed), with exact butterflies (cos, -sin) so no scalar
+// factor or relabelling is involved. Tiles as in the forward sweeps, TB = 13.
+// ---------------------------------------------------------------------------
+
+enum AdjointKind {
+    AK_MIDDLE = 0,    // inverse mixer of one group (b-layer i)
+    AK_BOUNDARY = 1,  // inverse mixer (i), inverse phase (i), inverse mixer (i + 1) of one group
+    AK_END = 2,       // inverse mixer (i), inverse phase (i): last op of a reverse segment
+};
+
+struct AdjointArgs {
+    float2* lam;
+    float2* psi;
+    const void* cost;
+    const float2* lut;     // exp(+i gamma c), c = 0 .. lut_len - 1
+    double* partials;      // 3 per tile: Im<lam|X|psi> (pre group), Im<lam|C|psi>, Im<lam|X|psi> (post group)
+    int32_t n, nw, lut_len;
+    uint64_t tile_bits, wmask;
+    uint8_t pos[16];
+    uint32_t pre_mask, post_mask;
+    float pre_c, pre_s, post_c, post_s;  // butterfly a' = c a - i s b
+    int32_t store_psi;
+};
+
+constexpr int kAdjointTileBits = 13;
+hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s);
+
+// lam(x) = (w_psucc [C(x) = 0] + w_energy C(x)) psi(x), x in [0, 2^n).
+hipError_t launch_weight(int dtype, const void* cost, const float2* psi, float2* lam, int n, double w_psucc,
+                         double w_energy, hipStream_t s);
+
+// Whole gradient for n <= 13 in one workgroup (lam and psi resident in LDS):
+// forward with exact butterflies (checkpoints of psi every `every` layers in
+// ckpt), readout, then the reverse pass with psi refreshed at checkpoints.
+struct ResidentGradArgs {
+    const void* cost;
+    const float2* luts;    // p forward tables exp(-i gamma_l c)
+    const float2* cs;      // p (cos beta_l, sin beta_l)
+    float2* ckpt;          // (p - 1) / every states of 2^n
+    double* out;           // 3 readout sums, then dgamma[p], then dbeta[p]
+    double w_psucc, w_energy;
+    int32_t n, p, lut_len, every;
+};
+hipError_t launch_resident_grad(int dtype, const ResidentGradArgs& a, hipStream_t s);
 hipError_t launch_resident_batch(int dtype, const ResidentArgs* args, int count, hipStream_t s);
 
 // Sum of 3-double block partials into out[3], FP64.

@@ -50,7 +50,8 @@ int qnae_destroy(qnae_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->state, &ctx->partials, &ctx->luts, &ctx->clauses, &ctx->forms, &ctx->small, &ctx->b_blob,
-                      &ctx->b_states, &ctx->b_partials, &ctx->b_results})
+                      &ctx->b_states, &ctx->b_partials, &ctx->b_results, &ctx->g_states, &ctx->g_blob,
+                      &ctx->g_partials})
         b->release();
     for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results})
         b->release();
@@ -127,6 +128,7 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
         HIP_TRY(ctx->forms.reserve(sizeof(MixForm) * (size_t)T));
         if (p > 0) HIP_TRY(hipMemcpyAsync(ctx->forms.ptr, forms, sizeof(MixForm) * p, hipMemcpyHostToDevice, s));
         qnae::ResidentArgs a;
+        a.state_in = nullptr;
         a.cost = cost_dev;
         a.luts = (const float2*)ctx->luts.ptr;
         a.forms = (const MixForm*)ctx->forms.ptr;

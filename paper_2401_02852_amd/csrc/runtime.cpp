@@ -45,7 +45,12 @@ Layer mixer_form(double beta, int n) {
 // amplitude of |+>, for layer 0). Returns the factor left after the last layer.
 std::complex<double> build_tables(int n, int m, const double* gammas, const double* betas, int p,
                                   float2* tables, MixForm* forms) {
-    std::complex<double> prev(std::pow(2.0, -0.5 * n), 0.0);
+    return build_tables_from(n, m, gammas, betas, p, tables, forms, std::complex<double>(std::pow(2.0, -0.5 * n), 0.0));
+}
+
+std::complex<double> build_tables_from(int n, int m, const double* gammas, const double* betas, int p,
+                                       float2* tables, MixForm* forms, std::complex<double> first) {
+    std::complex<double> prev = first;
     const int T = p > 0 ? p : 1;
     for (int l = 0; l < T; ++l) {
         const double g = p > 0 ? gammas[l] : 0.0;
@@ -113,7 +118,7 @@ void HostBuf::release() {
 const char* Profiler::name(int k) {
     static const char* names[K_KINDS] = {"cost", "sweep_first", "sweep_middle", "sweep_boundary", "sweep_final",
                                          "resident", "final_reduce", "batch_cost", "batch_resident", "batch_sweep",
-                                         "batch_reduce"};
+                                         "batch_reduce", "adjoint"};
     return names[k];
 }
 
@@ -270,14 +275,16 @@ std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
 // every layer after the first costs (number of groups - 1) sweeps. The first
 // sweep starts from the phase table (no load) and the last one only reads the
 // state for the readout unless the final state is kept.
-std::vector<Op> make_plan(int ngroups, int p) {
+std::vector<Op> make_plan(int ngroups, int p, bool from_state) {
     using namespace qnae;
     std::vector<Op> ops;
     if (p == 0) {
         ops.push_back({0, SK_P0, -1, -1, 0});
         return ops;
     }
-    ops.push_back({0, SK_FIRST, -1, 0, 0});
+    // from a given state: load, phase 0, mix group 0 (a boundary sweep with
+    // nothing to mix before the phase)
+    ops.push_back(from_state ? Op{0, SK_BOUNDARY, -1, 0, 0} : Op{0, SK_FIRST, -1, 0, 0});
     std::vector<int> pending;  // groups not yet mixed for layer l
     for (int g = 1; g < ngroups; ++g) pending.push_back(g);
     for (int l = 0;; ++l) {
@@ -305,8 +312,31 @@ std::vector<Op> make_plan(int ngroups, int p) {
     }
 }
 
+std::vector<AdjOp> make_adjoint_plan(int ngroups, int L) {
+    using namespace qnae;
+    std::vector<AdjOp> ops;
+    std::vector<int> pending;
+    for (int g = 0; g < ngroups; ++g) pending.push_back(g);
+    for (int i = 0; i < L; ++i) {
+        int last = pending.back();
+        for (int g : pending)
+            if (g != 0) last = g;
+        for (int g : pending)
+            if (g != last) ops.push_back({g, AK_MIDDLE, i, -1, -1});
+        if (i == L - 1) {
+            ops.push_back({last, AK_END, i, i, -1});
+            break;
+        }
+        ops.push_back({last, AK_BOUNDARY, i, i, i + 1});
+        pending.clear();
+        for (int g = 0; g < ngroups; ++g)
+            if (g != last) pending.push_back(g);
+    }
+    return ops;
+}
+
 void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, bool keep,
-                 const qnae::MixForm* forms, std::complex<double> final_scale) {
+                 const qnae::MixForm* forms, std::complex<double> final_scale, bool from_state) {
     P.n = n;
     P.m = m;
     P.p = p;
@@ -315,7 +345,7 @@ void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin,
     P.lut_len = m + 1;
     P.keep = keep;
     P.groups = make_groups(n, TB, cmin, page);
-    P.ops = make_plan((int)P.groups.size(), p);
+    P.ops = make_plan((int)P.groups.size(), p, from_state);
     P.forms.assign(forms, forms + p);
     P.flips_before.assign(p + 1, 0);
     for (int l = 0; l < p; ++l) P.flips_before[l + 1] = P.flips_before[l] ^ forms[l].flip;
@@ -327,6 +357,7 @@ void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost,
     const Group& g = P.groups[op.group];
     std::memset(a, 0, sizeof *a);
     a->psi = psi;
+    a->psi_in = psi;
     a->cost = cost;
     a->lut = op.lut_layer >= 0 ? luts + (size_t)op.lut_layer * P.lut_len : nullptr;
     a->partials = partials;

@@ -1,0 +1,162 @@
+// Device helpers shared by the sweep and adjoint kernels: complex product,
+// register butterflies, the three register layouts of a tile and the LDS
+// transposes between them. See sweep.hip for the tiling scheme.
+#pragma once
+
+#include "internal.h"
+
+namespace qnae {
+namespace tile {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// Butterfly on register bit S of a register array of size NE:
+// own' = own - i t partner for both members of each pair.
+template <int NE, int S>
+__device__ __forceinline__ void bfly(float2 (&v)[NE], float t) {
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        if (j & (1 << S)) continue;
+        const float2 a = v[j], b = v[j | (1 << S)];
+        v[j] = make_float2(fmaf(t, b.y, a.x), fmaf(-t, b.x, a.y));
+        v[j | (1 << S)] = make_float2(fmaf(t, a.y, b.x), fmaf(-t, a.x, b.y));
+    }
+}
+
+__device__ __forceinline__ void mix32(float2 (&v)[32], uint32_t sm, float t) {
+    if (sm & 1u) bfly<32, 0>(v, t);
+    if (sm & 2u) bfly<32, 1>(v, t);
+    if (sm & 4u) bfly<32, 2>(v, t);
+    if (sm & 8u) bfly<32, 3>(v, t);
+    if (sm & 16u) bfly<32, 4>(v, t);
+}
+
+// Bit positions of layout L2 (tile bits held by slots, lanes and waves). For
+// TB <= 13 the slots also hold tile bits 4 and 5, so a group whose low tile
+// bits are an unmixed run of 4 (a high-qubit tile) mixes everything in L0 and
+// L2 and skips L1.
+template <int TB>
+struct L2Map;
+template <>
+struct L2Map<14> {
+    static constexpr int slot[5] = {6, 11, 12, 13, 7};
+    static constexpr int lane[6] = {0, 1, 2, 3, 4, 5};
+    static constexpr int wave[3] = {8, 9, 10};
+};
+template <>
+struct L2Map<13> {
+    static constexpr int slot[5] = {6, 11, 12, 4, 5};
+    static constexpr int lane[6] = {0, 1, 2, 3, 7, 8};
+    static constexpr int wave[2] = {9, 10};
+};
+template <>
+struct L2Map<12> {
+    static constexpr int slot[5] = {6, 11, 4, 5, 7};
+    static constexpr int lane[6] = {0, 1, 2, 3, 8, 9};
+    static constexpr int wave[1] = {10};
+};
+
+// Tile-local element index of register slot j in each layout, split into a
+// thread part and a slot part with disjoint bits (e = t | s).
+//   L0  slots = e{0, 7, 8, 9, 10}, lanes = e{1..6},  waves = e{11..}
+//   L1  slots = e{1..5},           lanes = e{0, 6..10}, waves = e{11..}
+//   L2  see L2Map
+// Round ownership: L0 mixes tile bits {0, 7..10}; L1 mixes {1..5}; L2 mixes
+// {6, 11..}, and also {4, 5} when L1 has nothing else to do (TB <= 13).
+template <int TB>
+struct Lay {
+    static constexpr int WB = TB - 11;  // wave bits
+    using M = L2Map<TB>;
+    static constexpr bool L2_HAS_45 = TB <= 13;
+    __device__ static __forceinline__ uint32_t t0(uint32_t lane, uint32_t wave) { return (lane << 1) | (wave << 11); }
+    __device__ static __forceinline__ constexpr uint32_t s0(int j) { return (uint32_t)(j & 1) | ((uint32_t)(j >> 1) << 7); }
+    __device__ static __forceinline__ uint32_t t1(uint32_t lane, uint32_t wave) {
+        return (lane & 1u) | ((lane >> 1) << 6) | (wave << 11);
+    }
+    __device__ static __forceinline__ constexpr uint32_t s1(int j) { return (uint32_t)j << 1; }
+    __device__ static __forceinline__ uint32_t t2(uint32_t lane, uint32_t wave) {
+        uint32_t e = 0u;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) e |= ((lane >> i) & 1u) << M::lane[i];
+#pragma unroll
+        for (int i = 0; i < WB; ++i) e |= ((wave >> i) & 1u) << M::wave[i];
+        return e;
+    }
+    __device__ static __forceinline__ constexpr uint32_t s2(int j) {
+        uint32_t e = 0u;
+        for (int i = 0; i < 5; ++i) e |= (uint32_t)((j >> i) & 1) << M::slot[i];
+        return e;
+    }
+    // Does L1 mix tile bits 4 and 5 for mask m?
+    __device__ static __forceinline__ bool r1_takes_45(uint32_t m) { return !L2_HAS_45 || (m & 0xeu) != 0u; }
+    // Slot masks of the tile bits each round mixes.
+    __device__ static __forceinline__ uint32_t sm0(uint32_t m) { return (m & 1u) | (((m >> 7) & 15u) << 1); }
+    __device__ static __forceinline__ uint32_t sm1(uint32_t m) {
+        return r1_takes_45(m) ? (m >> 1) & 31u : (m >> 1) & 7u;
+    }
+    __device__ static __forceinline__ uint32_t sm2(uint32_t m) {
+        const bool with45 = !r1_takes_45(m);
+        uint32_t sm = 0u;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const int eb = M::slot[i];
+            const bool own = eb == 6 || eb >= 11 || (with45 && (eb == 4 || eb == 5));
+            if (own && ((m >> eb) & 1u)) sm |= 1u << i;
+        }
+        return sm;
+    }
+};
+
+// LDS position of tile element e: two padding slots after every 64 elements.
+// Any 16 consecutive lanes then hit 16 distinct 8-byte bank pairs in all three
+// layouts, and because the map is additive over disjoint bit sets of e, an
+// address is a per-thread base plus a compile-time constant per slot.
+__device__ __forceinline__ constexpr uint32_t phys(uint32_t e) { return e + 2u * (e >> 6); }
+template <int TB>
+constexpr uint32_t lds_elems() { return phys((1u << TB) - 1u) + 1u; }
+
+template <int TB, int LAYOUT>
+__device__ __forceinline__ void to_lds(float2* lds, const float2 (&v)[32], uint32_t lane, uint32_t wave) {
+    using L = Lay<TB>;
+    if (LAYOUT == 0) {
+        float2* const p = lds + phys(L::t0(lane, wave));
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+            *(float4*)(p + phys(L::s0(2 * jj))) = make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
+    } else if (LAYOUT == 1) {
+        float2* const p = lds + phys(L::t1(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) p[phys(L::s1(j))] = v[j];
+    } else {
+        float2* const p = lds + phys(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) p[phys(L::s2(j))] = v[j];
+    }
+}
+
+template <int TB, int LAYOUT>
+__device__ __forceinline__ void from_lds(const float2* lds, float2 (&v)[32], uint32_t lane, uint32_t wave) {
+    using L = Lay<TB>;
+    if (LAYOUT == 0) {
+        const float2* const p = lds + phys(L::t0(lane, wave));
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const float4 q = *(const float4*)(p + phys(L::s0(2 * jj)));
+            v[2 * jj] = make_float2(q.x, q.y);
+            v[2 * jj + 1] = make_float2(q.z, q.w);
+        }
+    } else if (LAYOUT == 1) {
+        const float2* const p = lds + phys(L::t1(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = p[phys(L::s1(j))];
+    } else {
+        const float2* const p = lds + phys(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = p[phys(L::s2(j))];
+    }
+}
+
+}  // namespace tile
+}  // namespace qnae
