@@ -133,6 +133,87 @@ def batched_bench(q, ctx, reps=5, count=512):
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
 
 
+def serving_bench(q, ctx, count=2000, warm=100, rate=200.0):
+    """Poisson request trace (n 14..26, p 2..20, k in {3, 5}) through the
+    continuous-batching server and through the plain path one request at a
+    time in arrival order (FIFO), at the trace's rate and at saturation (every
+    arrival at t = 0). Latency is arrival to result in host memory; the first
+    `warm` requests are excluded from the statistics."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_2401_02852_amd import instances as inst
+    trace = inst.serving_workload(count=count, rate=rate)
+    layers = sum(r["p"] for r in trace[warm:])
+    pct = lambda a, x: float(np.percentile(np.asarray(a), x)) * 1e3
+
+    def served(saturate):
+        lat = [0.0] * count
+        with q.Server(pool_bytes=64 << 30, max_slots=256, ctx=ctx) as srv:
+            tickets = [None] * count
+            lag = [0.0] * count
+            ready = threading.Semaphore(0)
+
+            def submitter():
+                t0 = time.perf_counter()
+                for i, r in enumerate(trace):
+                    at = 0.0 if saturate else r["arrival_s"]
+                    d = at - (time.perf_counter() - t0)
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[i] = srv.submit(r["clauses"], r["n"], r["gammas"], r["betas"])
+                    lag[i] = max(0.0, time.perf_counter() - t0 - at)
+                    ready.release()
+            th = threading.Thread(target=submitter)
+            th.start()
+            t_first = None
+            for i in range(count):
+                ready.acquire()
+                _, l = srv.wait(tickets[i])
+                lat[i] = l + lag[i]
+                if i == warm - 1:
+                    t_first = time.perf_counter()
+            t_end = time.perf_counter()
+            th.join()
+            st = srv.stats()
+        return lat[warm:], t_end - t_first, st
+
+    def plain(saturate):
+        cost = {}
+        lat = []
+        t0 = time.perf_counter()
+        t_first = None
+        for i, r in enumerate(trace):
+            at = 0.0 if saturate else r["arrival_s"]
+            d = at - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            key = (r["n"], r["m"] > 255)
+            if key not in cost:
+                cost[key] = torch.empty(1 << r["n"], dtype=torch.uint16 if key[1] else torch.uint8, device="cuda")
+            q.build_cost_diagonal(r["clauses"], r["n"], out=cost[key], ctx=ctx)
+            q.qaoa_run(cost[key], r["n"], r["m"], r["gammas"], r["betas"], ctx=ctx)  # result on the host
+            if i >= warm:
+                lat.append(time.perf_counter() - t0 - at)
+            if i == warm - 1:
+                t_first = time.perf_counter()
+        return lat, time.perf_counter() - t_first
+
+    out = {"workload": f"{count} Poisson requests at {rate:g}/s (first {warm} warm-up), k in {{3,5}}, "
+                       "n in 14..26, p in 2..20, angles U(0,pi)",
+           "instance_layers": layers}
+    for mode, sat in (("rate", False), ("saturation", True)):
+        lat, wall, st = served(sat)
+        torch.cuda.synchronize()
+        plat, pwall = plain(sat)
+        out[mode] = {"served": {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "req_per_s": (count - warm) / wall,
+                                "instance_layers_per_s": layers / wall, "ticks": st["ticks"],
+                                "launches": st["launches"], "peak_pool_GiB": st["peak_pool_bytes"] / 2 ** 30},
+                     "plain_fifo": {"p50_ms": pct(plat, 50), "p99_ms": pct(plat, 99),
+                                    "req_per_s": (count - warm) / pwall, "instance_layers_per_s": layers / pwall}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +223,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -219,6 +302,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_bench(q, ctx)
+    if not args.no_serving:
+        out["serving"] = serving_bench(q, ctx, count=args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)

@@ -181,6 +181,53 @@ typedef struct {
 int qnae_qaoa_run_batched(qnae_ctx *ctx, const qnae_instance *inst, int32_t count, qnae_result *out,
                           void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of solve requests on one GPU.
+ *
+ * A server owns a device pool (one allocation, split by a buddy allocator)
+ * and a scheduler thread. Requests wait in a FIFO queue and are admitted,
+ * oldest first, while a slot is free and the pool can hold the request's
+ * state (2^n * 8 bytes when n > 14), cost diagonal (2^n bytes, or 2^n * 2 when
+ * m > 255) and tables. Every scheduler tick builds the cost diagonals of newly
+ * admitted requests, runs small requests (n <= 14) to completion and advances
+ * every other active request by one sweep, all requests sharing the same
+ * launches; requests that finish are read out and their memory is freed, so
+ * later arrivals join while earlier ones are still on the GPU. A request's
+ * result equals qnae_qaoa_run on the same instance up to FP32 rounding order.
+ * ------------------------------------------------------------------------- */
+
+typedef struct qnae_server qnae_server;
+
+/* pool_bytes: device memory for states, costs and tables (rounded down to a
+ * power of two, at least 1 MiB); max_slots: requests on the GPU at once
+ * (1 .. 65536). The server runs on the context's device and its own stream.
+ * Errors: QNAE_EINVAL, QNAE_ENOMEM, QNAE_EHIP. */
+int qnae_server_create(qnae_ctx *ctx, uint64_t pool_bytes, int32_t max_slots, qnae_server **out);
+
+/* Queues one request (clauses, gammas and betas are copied before return;
+ * literals as for qnae_build_cost_diagonal; 1 <= n <= QNAE_MAX_N). *ticket identifies
+ * it for qnae_server_wait. Errors: QNAE_EINVAL (bad request, or one that can
+ * never fit the pool), QNAE_EBUSY (queue of 1 << 20 requests full). */
+int qnae_server_submit(qnae_server *server, const int32_t *clauses, int32_t m, int32_t n, int32_t k,
+                       const double *gammas, const double *betas, int32_t p, uint64_t *ticket);
+
+/* Waits for a request. timeout_ms < 0 waits without limit, 0 polls. On
+ * success fills *out and, if latency_s is not NULL, the seconds from submit to
+ * completion, and forgets the ticket. Errors: QNAE_ETIMEDOUT (not done yet;
+ * the ticket stays valid), QNAE_EINVAL (unknown ticket), QNAE_EHIP (the
+ * request failed on the device). */
+int qnae_server_wait(qnae_server *server, uint64_t ticket, int32_t timeout_ms, qnae_result *out,
+                     double *latency_s);
+
+/* Counters: completed requests, scheduler ticks, kernel launches, peak pool
+ * bytes in use, requests waiting and active now. Any pointer may be NULL. */
+int qnae_server_stats(qnae_server *server, uint64_t *completed, uint64_t *ticks, uint64_t *launches,
+                      uint64_t *peak_pool_bytes, uint64_t *queued, uint64_t *active);
+
+/* Finishes every request already submitted, stops the scheduler and frees the
+ * pool. Results not yet collected are lost. NULL is a no-op. */
+int qnae_server_destroy(qnae_server *server);
+
 /* Kernel timing with HIP events, for measurement. While enabled, the context
  * records an event pair around every kernel it launches, on the stream the
  * kernel runs on, and tallies per kernel kind the number of launches, the

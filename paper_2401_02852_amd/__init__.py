@@ -11,6 +11,7 @@ from ._binding import (  # noqa: F401
     QNAEError,
     Context,
     Result,
+    Server,
     build_cost_diagonal,
     build_cost_diagonals,
     default_context,

@@ -89,9 +89,18 @@ def load_library():
         lib.qnae_qaoa_grad.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _F64P, _F64P,
                                        ctypes.POINTER(_CResult), vp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.qnae_server_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(vp)]
+        lib.qnae_server_submit.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
+                                           ctypes.c_int32, u64p]
+        lib.qnae_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(_CResult),
+                                         ctypes.POINTER(ctypes.c_double)]
+        lib.qnae_server_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, u64p]
+        lib.qnae_server_destroy.argtypes = [vp]
         for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
-                   lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad):
+                   lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
+                   lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -302,3 +311,61 @@ def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_en
         dg.ctypes.data_as(_F64P) if p else None, db.ctypes.data_as(_F64P) if p else None,
         ctypes.byref(res), _stream(stream)))
     return dg, db, Result(res.p_success, res.expected_cost, res.norm)
+
+
+class Server:
+    """Continuous-batching solve server (qnae_server_*): submit instances,
+    collect results; requests share GPU launches while they are active."""
+
+    def __init__(self, pool_bytes: int = 64 << 30, max_slots: int = 256, ctx: Optional[Context] = None):
+        self._ctx = ctx or default_context()
+        h = ctypes.c_void_p()
+        _check(load_library().qnae_server_create(self._ctx.handle, int(pool_bytes), int(max_slots), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, clauses, n: int, gammas, betas) -> int:
+        cl = np.ascontiguousarray(np.asarray(clauses, dtype=np.int32))
+        if cl.ndim != 2:
+            raise ValueError("clauses must be an [m, k] literal array")
+        m, k = cl.shape
+        g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
+        b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
+        if g.shape != b.shape or g.ndim != 1:
+            raise ValueError("gammas and betas must be 1-D of equal length")
+        t = ctypes.c_uint64(0)
+        p = g.shape[0]
+        _check(load_library().qnae_server_submit(
+            self._h, cl.ctypes.data_as(_I32P) if m else None, m, int(n), max(k, 1),
+            g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p, ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(Result, latency seconds from submit to completion)."""
+        res = _CResult()
+        lat = ctypes.c_double(0.0)
+        _check(load_library().qnae_server_wait(self._h, int(ticket), int(timeout_ms), ctypes.byref(res),
+                                               ctypes.byref(lat)))
+        return Result(res.p_success, res.expected_cost, res.norm), float(lat.value)
+
+    def stats(self) -> dict:
+        v = [ctypes.c_uint64(0) for _ in range(6)]
+        _check(load_library().qnae_server_stats(self._h, *[ctypes.byref(x) for x in v]))
+        keys = ["completed", "ticks", "launches", "peak_pool_bytes", "queued", "active"]
+        return {k: int(x.value) for k, x in zip(keys, v)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().qnae_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

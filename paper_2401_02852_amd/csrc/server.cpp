@@ -1,0 +1,553 @@
+// Serving (include/qnae.h, qnae_server_*): continuous batching of QAOA solve
+// requests on one GPU, driven by a host scheduler thread.
+//
+// Memory: one device pool split by a buddy allocator (every state is a power
+// of two of 8-byte amplitudes, so blocks do not fragment into odd sizes).
+// Each active request holds a cost block, an aux block (phase tables, tile
+// partial sums, result) and, when n > 14, a state block.
+//
+// Tick: admit queued requests (FIFO) while a slot is free and the pool can
+// hold them; build the new cost diagonals (one batched launch); run new small
+// requests whole (one batched resident launch); advance every large request
+// by one sweep (one batched launch per sweep kind and cost type); read out
+// requests whose plan ended (one batched reduce), copy their results to the
+// host, free their blocks and wake their waiters.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <thread>
+#include <unordered_map>
+
+#include "host.h"
+
+using namespace qnae_host;
+using qnae::ClauseRec;
+using qnae::MixForm;
+using qnae::SweepArgs;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Buddy allocator over [0, 2^max_order) in blocks of 2^order bytes.
+class Buddy {
+   public:
+    static constexpr int kMinOrder = 12;
+    explicit Buddy(int max_order) : max_order_(max_order), free_(max_order + 1) { free_[max_order].insert(0); }
+    static int order_for(uint64_t bytes) {
+        int o = kMinOrder;
+        while ((1ull << o) < bytes) ++o;
+        return o;
+    }
+    bool alloc(int order, uint64_t* off) {
+        int o = order;
+        while (o <= max_order_ && free_[o].empty()) ++o;
+        if (o > max_order_) return false;
+        uint64_t at = *free_[o].begin();
+        free_[o].erase(free_[o].begin());
+        while (o > order) {  // split, keep the lower half
+            --o;
+            free_[o].insert(at + (1ull << o));
+        }
+        used_ += 1ull << order;
+        peak_ = std::max(peak_, used_);
+        *off = at;
+        return true;
+    }
+    void release(uint64_t at, int order) {
+        used_ -= 1ull << order;
+        while (order < max_order_) {
+            const uint64_t buddy = at ^ (1ull << order);
+            auto it = free_[order].find(buddy);
+            if (it == free_[order].end()) break;
+            free_[order].erase(it);
+            at = std::min(at, buddy);
+            ++order;
+        }
+        free_[order].insert(at);
+    }
+    uint64_t peak() const { return peak_; }
+
+   private:
+    int max_order_;
+    std::vector<std::set<uint64_t>> free_;
+    uint64_t used_ = 0, peak_ = 0;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    int n = 0, m = 0, k = 0, p = 0, dtype = QNAE_U8;
+    std::vector<int32_t> clauses;
+    std::vector<double> gammas, betas;
+    double t_submit = 0, t_done = 0;
+    enum { QUEUED, ACTIVE, DONE, FAILED } state = QUEUED;
+    qnae_result result{};
+    // active
+    bool resident = false;
+    uint64_t state_off = 0, cost_off = 0, aux_off = 0;
+    int state_order = -1, cost_order = -1, aux_order = -1;
+    size_t lut_off = 0, form_off = 0, part_off = 0, res_off = 0;  // inside the aux block
+    uint32_t tiles = 0;
+    SweepPlan plan;
+    std::complex<double> final_scale;
+    size_t next_op = 0;
+    bool cost_built = false;
+};
+
+uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct qnae_server {
+    qnae_ctx* ctx = nullptr;
+    int device = 0;
+    int max_slots = 1;
+    hipStream_t stream = nullptr;
+    char* pool = nullptr;
+    uint64_t pool_bytes = 0;
+    std::unique_ptr<Buddy> buddy;
+    DevBuf d_blob;
+    HostBuf h_blob;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::vector<Request*> active;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int error = QNAE_OK;
+    std::string error_msg;
+    uint64_t completed = 0, ticks = 0, launches = 0;
+    std::thread worker;
+
+    // Footprint blocks of a request; false if it can never fit the pool.
+    bool plan_blocks(Request& r, int* so, int* co, int* ao) const {
+        const uint64_t N = 1ull << r.n;
+        *so = r.resident ? -1 : Buddy::order_for(N * 8);
+        *co = Buddy::order_for(N * (r.dtype == QNAE_U8 ? 1 : 2));
+        const int T = r.p > 0 ? r.p : 1;
+        const uint64_t aux = round_up(sizeof(float2) * (uint64_t)T * (r.m + 1), 256) + round_up(sizeof(MixForm) * T, 256) +
+                             round_up(sizeof(double) * 3 * (uint64_t)(r.tiles ? r.tiles : 1), 256) + 256;
+        *ao = Buddy::order_for(aux);
+        uint64_t total = (1ull << *co) + (1ull << *ao) + (*so >= 0 ? 1ull << *so : 0);
+        return total <= pool_bytes && *co <= 63;
+    }
+    void release(Request& r) {
+        if (r.state_order >= 0) buddy->release(r.state_off, r.state_order);
+        if (r.cost_order >= 0) buddy->release(r.cost_off, r.cost_order);
+        if (r.aux_order >= 0) buddy->release(r.aux_off, r.aux_order);
+        r.state_order = r.cost_order = r.aux_order = -1;
+    }
+    int tick(std::vector<Request*>& admitted);
+    void run();
+};
+
+namespace {
+
+int fail_server(qnae_server* S, int code) {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->error = code;
+    S->error_msg = last_error();
+    return code;
+}
+
+}  // namespace
+
+// One scheduler tick over the requests admitted now and the active ones.
+int qnae_server::tick(std::vector<Request*>& admitted) {
+    hipStream_t s = stream;
+    // Host side of new requests: tables, clause records, plans.
+    Blob B;
+    struct NewCost {
+        Request* r;
+        size_t rec_at;
+        int nrec;
+    };
+    std::vector<NewCost> costs;
+    std::vector<std::vector<ClauseRec>> recs(admitted.size());
+    std::vector<std::vector<float2>> tabs(admitted.size());
+    std::vector<std::vector<MixForm>> forms(admitted.size());
+    for (size_t i = 0; i < admitted.size(); ++i) {
+        Request& r = *admitted[i];
+        recs[i].resize((size_t)std::max(r.m, 1));
+        const int nrec = make_clause_records(r.clauses.data(), r.m, r.k, recs[i].data());
+        recs[i].resize((size_t)nrec);
+        costs.push_back({&r, B.take(sizeof(ClauseRec) * (size_t)std::max(nrec, 1)), nrec});
+        const int T = r.p > 0 ? r.p : 1;
+        tabs[i].resize((size_t)T * (r.m + 1));
+        forms[i].resize((size_t)T);
+        r.final_scale = build_tables(r.n, r.m, r.gammas.data(), r.betas.data(), r.p, tabs[i].data(), forms[i].data());
+        if (!r.resident)
+            plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, qnae::kBatchTileBits, ctx->min_low_run, ctx->page_bit, false,
+                        forms[i].data(), r.final_scale);
+    }
+    // Cost launch arguments per cost type.
+    std::vector<Request*> cgroups[2];
+    for (auto& c : costs) cgroups[c.r->dtype == QNAE_U16 ? 1 : 0].push_back(c.r);
+    size_t cargs_at[2], cfirst_at[2];
+    for (int g = 0; g < 2; ++g) {
+        cargs_at[g] = B.take(sizeof(qnae::CostArgs) * cgroups[g].size());
+        cfirst_at[g] = B.take(sizeof(uint32_t) * (cgroups[g].size() + 1));
+    }
+    // Resident launches (new small requests run whole this tick).
+    std::vector<Request*> res[2];
+    for (Request* r : admitted)
+        if (r->resident) res[r->dtype == QNAE_U16 ? 1 : 0].push_back(r);
+    size_t res_at[2];
+    for (int g = 0; g < 2; ++g) res_at[g] = B.take(sizeof(qnae::ResidentArgs) * res[g].size());
+    // Sweep launches: every active large request does its next op.
+    struct Launch {
+        int kind, dtype;
+        std::vector<Request*> members;
+        size_t args_at, first_at;
+        uint32_t blocks;
+    };
+    std::map<std::pair<int, int>, Launch> sweeps;
+    std::vector<Request*> finishing;
+    for (Request* r : active) {
+        if (r->resident) continue;
+        const Op& op = r->plan.ops[r->next_op];
+        Launch& L = sweeps[{op.kind, r->dtype}];
+        L.kind = op.kind;
+        L.dtype = r->dtype;
+        L.members.push_back(r);
+        if (r->next_op + 1 == r->plan.ops.size()) finishing.push_back(r);
+    }
+    for (auto& kv : sweeps) {
+        kv.second.args_at = B.take(sizeof(SweepArgs) * kv.second.members.size());
+        kv.second.first_at = B.take(sizeof(uint32_t) * (kv.second.members.size() + 1));
+    }
+    const size_t rp_at = B.take(sizeof(double*) * finishing.size());
+    const size_t rb_at = B.take(sizeof(uint32_t) * finishing.size());
+    const size_t ro_at = B.take(sizeof(double*) * finishing.size());
+    if (B.size == 0) return QNAE_OK;
+    HIP_TRY(h_blob.reserve(B.size));
+    HIP_TRY(d_blob.reserve(B.size));
+    char* h = (char*)h_blob.ptr;
+    char* d = (char*)d_blob.ptr;
+    // Per-request uploads into their own aux blocks, then the blob.
+    for (size_t i = 0; i < admitted.size(); ++i) {
+        Request& r = *admitted[i];
+        char* aux = pool + r.aux_off;
+        HIP_TRY(hipMemcpyAsync(aux + r.lut_off, tabs[i].data(), sizeof(float2) * tabs[i].size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(aux + r.form_off, forms[i].data(), sizeof(MixForm) * forms[i].size(),
+                               hipMemcpyHostToDevice, s));
+        std::memcpy(h + costs[i].rec_at, recs[i].data(), sizeof(ClauseRec) * recs[i].size());
+    }
+    uint32_t cblocks[2] = {0, 0};
+    int cmax[2] = {0, 0};
+    {
+        std::unordered_map<Request*, size_t> rec_at;
+        for (auto& c : costs) rec_at[c.r] = c.rec_at;
+        std::unordered_map<Request*, int> nrec;
+        for (auto& c : costs) nrec[c.r] = c.nrec;
+        for (int g = 0; g < 2; ++g) {
+            qnae::CostArgs* args = (qnae::CostArgs*)(h + cargs_at[g]);
+            uint32_t* first = (uint32_t*)(h + cfirst_at[g]);
+            for (size_t q = 0; q < cgroups[g].size(); ++q) {
+                Request& r = *cgroups[g][q];
+                args[q].clauses = (const ClauseRec*)(d + rec_at[&r]);
+                args[q].num_clauses = nrec[&r];
+                args[q].n = r.n;
+                args[q].cost = pool + r.cost_off;
+                args[q].zeros = nullptr;
+                first[q] = cblocks[g];
+                const uint64_t threads = r.n >= 5 ? (1ull << (r.n - 5)) : 1ull;
+                cblocks[g] += (uint32_t)((threads + 255) / 256);
+                cmax[g] = std::max(cmax[g], nrec[&r]);
+            }
+            first[cgroups[g].size()] = cblocks[g];
+        }
+    }
+    for (int g = 0; g < 2; ++g) {
+        qnae::ResidentArgs* ra = (qnae::ResidentArgs*)(h + res_at[g]);
+        for (size_t q = 0; q < res[g].size(); ++q) {
+            Request& r = *res[g][q];
+            char* aux = pool + r.aux_off;
+            ra[q].state_in = nullptr;
+            ra[q].cost = pool + r.cost_off;
+            ra[q].luts = (const float2*)(aux + r.lut_off);
+            ra[q].forms = (const MixForm*)(aux + r.form_off);
+            ra[q].state_out = nullptr;
+            ra[q].out = (double*)(aux + r.res_off);
+            ra[q].store_scale = make_float2(1.f, 0.f);
+            ra[q].n = r.n;
+            ra[q].p = r.p;
+            ra[q].lut_len = r.m + 1;
+        }
+    }
+    for (auto& kv : sweeps) {
+        Launch& L = kv.second;
+        SweepArgs* args = (SweepArgs*)(h + L.args_at);
+        uint32_t* first = (uint32_t*)(h + L.first_at);
+        L.blocks = 0;
+        for (size_t q = 0; q < L.members.size(); ++q) {
+            Request& r = *L.members[q];
+            char* aux = pool + r.aux_off;
+            sweep_args(r.plan, r.plan.ops[r.next_op], (float2*)(pool + r.state_off), pool + r.cost_off,
+                       (const float2*)(aux + r.lut_off), (double*)(aux + r.part_off), &args[q]);
+            first[q] = L.blocks;
+            L.blocks += r.tiles;
+        }
+        first[L.members.size()] = L.blocks;
+    }
+    {
+        const double** rp = (const double**)(h + rp_at);
+        uint32_t* rb = (uint32_t*)(h + rb_at);
+        double** ro = (double**)(h + ro_at);
+        for (size_t q = 0; q < finishing.size(); ++q) {
+            Request& r = *finishing[q];
+            char* aux = pool + r.aux_off;
+            rp[q] = (const double*)(aux + r.part_off);
+            rb[q] = r.tiles;
+            ro[q] = (double*)(aux + r.res_off);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(d, h, B.size, hipMemcpyHostToDevice, s));
+    for (int g = 0; g < 2; ++g) {
+        if (cgroups[g].empty()) continue;
+        HIP_TRY(qnae::launch_cost_batch((const qnae::CostArgs*)(d + cargs_at[g]), (const uint32_t*)(d + cfirst_at[g]),
+                                        (int)cgroups[g].size(), cblocks[g], g ? QNAE_U16 : QNAE_U8, cmax[g], false, s));
+        ++launches;
+    }
+    for (int g = 0; g < 2; ++g) {
+        if (res[g].empty()) continue;
+        HIP_TRY(qnae::launch_resident_batch(g ? QNAE_U16 : QNAE_U8, (const qnae::ResidentArgs*)(d + res_at[g]),
+                                            (int)res[g].size(), s));
+        ++launches;
+    }
+    for (auto& kv : sweeps) {
+        const Launch& L = kv.second;
+        HIP_TRY(qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
+                                         (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, s));
+        ++launches;
+    }
+    if (!finishing.empty()) {
+        HIP_TRY(qnae::launch_final_reduce_batch((const double* const*)(d + rp_at), (const uint32_t*)(d + rb_at),
+                                                (double* const*)(d + ro_at), (int)finishing.size(), s));
+        ++launches;
+    }
+    // Results of every request that ends this tick.
+    std::vector<Request*> done;
+    for (int g = 0; g < 2; ++g)
+        for (Request* r : res[g]) done.push_back(r);
+    for (Request* r : finishing) done.push_back(r);
+    std::vector<double> hres(3 * done.size());
+    for (size_t q = 0; q < done.size(); ++q)
+        HIP_TRY(hipMemcpyAsync(&hres[3 * q], pool + done[q]->aux_off + done[q]->res_off, 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double t = now_s();
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (Request* r : active)
+            if (!r->resident) ++r->next_op;
+        for (size_t q = 0; q < done.size(); ++q) {
+            Request& r = *done[q];
+            const double sc = std::norm(r.final_scale);
+            r.result.p_success = hres[3 * q] * sc;
+            r.result.expected_cost = hres[3 * q + 1] * sc;
+            r.result.norm = hres[3 * q + 2] * sc;
+            r.t_done = t;
+            r.state = Request::DONE;
+            release(r);
+            ++completed;
+        }
+        active.erase(std::remove_if(active.begin(), active.end(), [](Request* r) { return r->state == Request::DONE; }),
+                     active.end());
+        ++ticks;
+    }
+    cv_done.notify_all();
+    return QNAE_OK;
+}
+
+void qnae_server::run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Request*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            if (queue.empty() && active.empty() && stop) return;
+            // FIFO admission while a slot and the pool allow it
+            while (!queue.empty() && (int)active.size() < max_slots) {
+                Request& r = *queue.front();
+                int so, co, ao;
+                plan_blocks(r, &so, &co, &ao);
+                uint64_t soff = 0, coff = 0, aoff = 0;
+                if (!buddy->alloc(co, &coff)) break;
+                if (!buddy->alloc(ao, &aoff)) {
+                    buddy->release(coff, co);
+                    break;
+                }
+                if (so >= 0 && !buddy->alloc(so, &soff)) {
+                    buddy->release(coff, co);
+                    buddy->release(aoff, ao);
+                    break;
+                }
+                r.cost_off = coff;
+                r.cost_order = co;
+                r.aux_off = aoff;
+                r.aux_order = ao;
+                r.state_off = soff;
+                r.state_order = so;
+                const int T = r.p > 0 ? r.p : 1;
+                r.lut_off = 0;
+                r.form_off = round_up(sizeof(float2) * (uint64_t)T * (r.m + 1), 256);
+                r.part_off = r.form_off + round_up(sizeof(MixForm) * T, 256);
+                r.res_off = r.part_off + round_up(sizeof(double) * 3 * (uint64_t)(r.tiles ? r.tiles : 1), 256);
+                r.state = Request::ACTIVE;
+                queue.pop_front();
+                active.push_back(&r);
+                admitted.push_back(&r);
+            }
+        }
+        const int rc = tick(admitted);
+        if (rc != QNAE_OK) {
+            fail_server(this, rc);
+            std::lock_guard<std::mutex> g(mu);
+            for (Request* r : active) {
+                r->state = Request::FAILED;
+                release(*r);
+            }
+            active.clear();
+            for (Request* r : queue) r->state = Request::FAILED;
+            queue.clear();
+            cv_done.notify_all();
+            return;
+        }
+    }
+}
+
+extern "C" {
+
+int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qnae_server** out) {
+    if (!out) return fail(QNAE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!ctx) return fail(QNAE_EINVAL, "null context");
+    if (max_slots < 1 || max_slots > 65536) return fail(QNAE_EINVAL, "max_slots=%d outside [1, 65536]", max_slots);
+    if (pool_bytes < (1ull << 20)) return fail(QNAE_EINVAL, "pool_bytes=%llu below 1 MiB", (unsigned long long)pool_bytes);
+    int order = 63;
+    while ((1ull << order) > pool_bytes) --order;
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::unique_ptr<qnae_server> S(new qnae_server());
+    S->ctx = ctx;
+    S->device = ctx->device;
+    S->max_slots = max_slots;
+    S->pool_bytes = 1ull << order;
+    HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+    hipError_t e = hipMalloc((void**)&S->pool, S->pool_bytes);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(S->stream);
+        return fail(QNAE_ENOMEM, "server pool of %llu bytes: %s", (unsigned long long)S->pool_bytes, hipGetErrorString(e));
+    }
+    S->buddy.reset(new Buddy(order));
+    qnae_server* raw = S.release();
+    raw->worker = std::thread([raw] { raw->run(); });
+    *out = raw;
+    return QNAE_OK;
+}
+
+int qnae_server_submit(qnae_server* S, const int32_t* clauses, int32_t m, int32_t n, int32_t k, const double* gammas,
+                       const double* betas, int32_t p, uint64_t* ticket) {
+    if (!S || !ticket) return fail(QNAE_EINVAL, "null argument");
+    const int dtype = m <= 255 ? QNAE_U8 : QNAE_U16;
+    if (int rc = check_cost_args(n, m, dtype)) return rc;
+    if (int rc = check_literals(clauses, m, n, k)) return rc;
+    if (p < 0 || p > 100000) return fail(QNAE_EINVAL, "p=%d outside [0, 100000]", p);
+    if (p > 0 && (!gammas || !betas)) return fail(QNAE_EINVAL, "null angle arrays with p=%d", p);
+    for (int l = 0; l < p; ++l)
+        if (!std::isfinite(gammas[l]) || !std::isfinite(betas[l]))
+            return fail(QNAE_EINVAL, "non-finite angle at layer %d", l);
+    std::unique_ptr<Request> r(new Request());
+    r->n = n;
+    r->m = m;
+    r->k = k;
+    r->p = p;
+    r->dtype = dtype;
+    r->clauses.assign(clauses, clauses + (size_t)m * k);
+    if (p > 0) {
+        r->gammas.assign(gammas, gammas + p);
+        r->betas.assign(betas, betas + p);
+    }
+    r->resident = n <= kResidentMaxN;
+    r->tiles = r->resident ? 0u : 1u << (n - qnae::kBatchTileBits);
+    int so, co, ao;
+    if (!S->plan_blocks(*r, &so, &co, &ao))
+        return fail(QNAE_EINVAL, "request with n=%d does not fit a pool of %llu bytes", n,
+                    (unsigned long long)S->pool_bytes);
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->error != QNAE_OK) return fail(S->error, "server failed: %s", S->error_msg.c_str());
+    if (S->stop) return fail(QNAE_EINVAL, "server is shutting down");
+    if (S->queue.size() >= (1u << 20)) return fail(QNAE_EBUSY, "request queue full");
+    r->ticket = S->next_ticket++;
+    r->t_submit = now_s();
+    *ticket = r->ticket;
+    S->queue.push_back(r.get());
+    S->all.emplace(r->ticket, std::move(r));
+    S->cv_work.notify_one();
+    return QNAE_OK;
+}
+
+int qnae_server_wait(qnae_server* S, uint64_t ticket, int32_t timeout_ms, qnae_result* out, double* latency_s) {
+    if (!S || !out) return fail(QNAE_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(QNAE_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    auto ready = [&] { return r->state == Request::DONE || r->state == Request::FAILED; };
+    if (timeout_ms < 0) S->cv_done.wait(lk, ready);
+    else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+        return fail(QNAE_ETIMEDOUT, "ticket %llu not done", (unsigned long long)ticket);
+    if (r->state == Request::FAILED) {
+        const std::string msg = S->error_msg;
+        S->all.erase(it);
+        return fail(QNAE_EHIP, "request failed: %s", msg.c_str());
+    }
+    *out = r->result;
+    if (latency_s) *latency_s = r->t_done - r->t_submit;
+    S->all.erase(it);
+    return QNAE_OK;
+}
+
+int qnae_server_stats(qnae_server* S, uint64_t* completed, uint64_t* ticks, uint64_t* launches,
+                      uint64_t* peak_pool_bytes, uint64_t* queued, uint64_t* active) {
+    if (!S) return fail(QNAE_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(S->mu);
+    if (completed) *completed = S->completed;
+    if (ticks) *ticks = S->ticks;
+    if (launches) *launches = S->launches;
+    if (peak_pool_bytes) *peak_pool_bytes = S->buddy->peak();
+    if (queued) *queued = S->queue.size();
+    if (active) *active = S->active.size();
+    return QNAE_OK;
+}
+
+int qnae_server_destroy(qnae_server* S) {
+    if (!S) return QNAE_OK;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    (void)hipSetDevice(S->device);
+    (void)hipStreamSynchronize(S->stream);
+    (void)hipFree(S->pool);
+    S->d_blob.release();
+    S->h_blob.release();
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return QNAE_OK;
+}
+
+}  // extern "C"

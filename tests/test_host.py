@@ -130,3 +130,12 @@ def test_binding_marshalling_without_gpu():
         b.qaoa_run(costs[0], 8, 10, [0.1], [0.2], ctx=_NullCtx(), stream=0)
     with pytest.raises(b.QNAEError, match="literal"):
         b.build_cost_diagonal(np.array([[1, 99]], dtype=np.int32), 8, out=costs[0], ctx=_NullCtx(), stream=0)
+
+
+def test_server_binding_without_gpu():
+    b = _lib_or_skip()
+    with pytest.raises(b.QNAEError, match="null context"):
+        b.Server(pool_bytes=1 << 30, max_slots=4, ctx=_NullCtx())
+    lib = b.load_library()
+    assert lib.qnae_server_submit(None, None, 0, 4, 1, None, None, 0, None) == -1
+    assert lib.qnae_server_destroy(None) == 0
