@@ -3,19 +3,21 @@
 //
 // Memory: one device pool split by a buddy allocator (every state is a power
 // of two of 8-byte amplitudes, so blocks do not fragment into odd sizes).
-// Each active request holds a cost block, an aux block (phase tables, tile
-// partial sums, result) and, when n > 14, a state block.
+// Each active request holds a cost block; a large one (n > 14) also holds a
+// state block and an aux block (phase tables, mixer forms, tile partial sums).
 //
 // Tick: admit queued requests (FIFO) while a slot is free and the pool can
-// hold them; build the new cost diagonals (one batched launch); run new small
-// requests whole (one batched resident launch); advance every large request
-// by one sweep (one batched launch per sweep kind and cost type); read out
-// requests whose plan ended (one batched reduce), copy their results to the
-// host, free their blocks and wake their waiters.
+// hold them; upload everything new in one pinned copy; build the new cost
+// diagonals (one batched launch); run new small requests whole (one batched
+// resident launch); advance the large requests by one or more rounds of one
+// sweep each (one batched launch per round, sweep kind and cost type); read
+// out requests whose plan ended (one batched reduce), copy all results back
+// in one copy, free their blocks and wake their waiters.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -95,7 +97,7 @@ struct Request {
     bool resident = false;
     uint64_t state_off = 0, cost_off = 0, aux_off = 0;
     int state_order = -1, cost_order = -1, aux_order = -1;
-    size_t lut_off = 0, form_off = 0, part_off = 0, res_off = 0;  // inside the aux block
+    size_t form_off = 0, part_off = 0;  // inside the aux block (tables at 0)
     uint32_t tiles = 0;
     SweepPlan plan;
     std::complex<double> final_scale;
@@ -127,19 +129,23 @@ struct qnae_server {
     int error = QNAE_OK;
     std::string error_msg;
     uint64_t completed = 0, ticks = 0, launches = 0;
+    double tick_bytes = 2e9;  // state traffic per tick, about 0.4 ms of HBM time
     std::thread worker;
 
     // Footprint blocks of a request; false if it can never fit the pool.
+    // Footprint blocks of a request (-1: none); false if it can never fit.
+    // Large requests: state, cost, aux = [tables | forms | tile partials].
+    // Small (resident) requests: cost only; their tables stay in the upload.
     bool plan_blocks(Request& r, int* so, int* co, int* ao) const {
         const uint64_t N = 1ull << r.n;
-        *so = r.resident ? -1 : Buddy::order_for(N * 8);
-        *co = Buddy::order_for(N * (r.dtype == QNAE_U8 ? 1 : 2));
         const int T = r.p > 0 ? r.p : 1;
-        const uint64_t aux = round_up(sizeof(float2) * (uint64_t)T * (r.m + 1), 256) + round_up(sizeof(MixForm) * T, 256) +
-                             round_up(sizeof(double) * 3 * (uint64_t)(r.tiles ? r.tiles : 1), 256) + 256;
-        *ao = Buddy::order_for(aux);
-        uint64_t total = (1ull << *co) + (1ull << *ao) + (*so >= 0 ? 1ull << *so : 0);
-        return total <= pool_bytes && *co <= 63;
+        r.form_off = round_up(sizeof(float2) * (uint64_t)T * (r.m + 1), 256);
+        r.part_off = r.form_off + round_up(sizeof(MixForm) * T, 256);
+        *co = Buddy::order_for(N * (r.dtype == QNAE_U8 ? 1 : 2));
+        *so = r.resident ? -1 : Buddy::order_for(N * 8);
+        *ao = r.resident ? -1 : Buddy::order_for(r.part_off + sizeof(double) * 3 * (uint64_t)r.tiles);
+        const uint64_t total = (1ull << *co) + (*ao >= 0 ? 1ull << *ao : 0) + (*so >= 0 ? 1ull << *so : 0);
+        return total <= pool_bytes;
     }
     void release(Request& r) {
         if (r.state_order >= 0) buddy->release(r.state_off, r.state_order);
@@ -162,157 +168,180 @@ int fail_server(qnae_server* S, int code) {
 
 }  // namespace
 
-// One scheduler tick over the requests admitted now and the active ones.
+// One scheduler tick over the requests admitted now and the active ones. A
+// tick runs several rounds (each round advances every unfinished large
+// request by one sweep) while the rounds' state traffic stays within
+// tick_bytes, so that a lightly loaded server does not pay one host
+// round trip per sweep, and a heavily loaded one still admits new requests
+// often.
 int qnae_server::tick(std::vector<Request*>& admitted) {
     hipStream_t s = stream;
-    // Host side of new requests: tables, clause records, plans.
     Blob B;
-    struct NewCost {
+    // Host side of new requests: clause records, tables, plans. Tables go
+    // through the upload blob; large requests copy them on into their aux
+    // block, small ones read them there.
+    struct New {
         Request* r;
-        size_t rec_at;
+        size_t rec_at, tab_at;
         int nrec;
+        std::vector<ClauseRec> recs;
+        std::vector<float2> tabs;
+        std::vector<MixForm> forms;
     };
-    std::vector<NewCost> costs;
-    std::vector<std::vector<ClauseRec>> recs(admitted.size());
-    std::vector<std::vector<float2>> tabs(admitted.size());
-    std::vector<std::vector<MixForm>> forms(admitted.size());
+    std::vector<New> nw(admitted.size());
     for (size_t i = 0; i < admitted.size(); ++i) {
         Request& r = *admitted[i];
-        recs[i].resize((size_t)std::max(r.m, 1));
-        const int nrec = make_clause_records(r.clauses.data(), r.m, r.k, recs[i].data());
-        recs[i].resize((size_t)nrec);
-        costs.push_back({&r, B.take(sizeof(ClauseRec) * (size_t)std::max(nrec, 1)), nrec});
+        New& w = nw[i];
+        w.r = &r;
+        w.recs.resize((size_t)std::max(r.m, 1));
+        w.nrec = make_clause_records(r.clauses.data(), r.m, r.k, w.recs.data());
+        w.rec_at = B.take(sizeof(ClauseRec) * (size_t)std::max(w.nrec, 1));
         const int T = r.p > 0 ? r.p : 1;
-        tabs[i].resize((size_t)T * (r.m + 1));
-        forms[i].resize((size_t)T);
-        r.final_scale = build_tables(r.n, r.m, r.gammas.data(), r.betas.data(), r.p, tabs[i].data(), forms[i].data());
+        w.tabs.resize((size_t)T * (r.m + 1));
+        w.forms.resize((size_t)T);
+        r.final_scale = build_tables(r.n, r.m, r.gammas.data(), r.betas.data(), r.p, w.tabs.data(), w.forms.data());
+        w.tab_at = B.take(r.part_off);  // same layout as the aux block: tables, then forms
         if (!r.resident)
             plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, qnae::kBatchTileBits, ctx->min_low_run, ctx->page_bit, false,
-                        forms[i].data(), r.final_scale);
+                        w.forms.data(), r.final_scale);
     }
-    // Cost launch arguments per cost type.
-    std::vector<Request*> cgroups[2];
-    for (auto& c : costs) cgroups[c.r->dtype == QNAE_U16 ? 1 : 0].push_back(c.r);
+    // Cost launches per cost type.
+    std::vector<New*> cgroups[2];
+    for (auto& w : nw) cgroups[w.r->dtype == QNAE_U16 ? 1 : 0].push_back(&w);
     size_t cargs_at[2], cfirst_at[2];
     for (int g = 0; g < 2; ++g) {
         cargs_at[g] = B.take(sizeof(qnae::CostArgs) * cgroups[g].size());
         cfirst_at[g] = B.take(sizeof(uint32_t) * (cgroups[g].size() + 1));
     }
-    // Resident launches (new small requests run whole this tick).
-    std::vector<Request*> res[2];
-    for (Request* r : admitted)
-        if (r->resident) res[r->dtype == QNAE_U16 ? 1 : 0].push_back(r);
+    // Resident launches: new small requests run whole this tick.
+    std::vector<New*> res[2];
+    for (auto& w : nw)
+        if (w.r->resident) res[w.r->dtype == QNAE_U16 ? 1 : 0].push_back(&w);
     size_t res_at[2];
     for (int g = 0; g < 2; ++g) res_at[g] = B.take(sizeof(qnae::ResidentArgs) * res[g].size());
-    // Sweep launches: every active large request does its next op.
+    // Rounds of sweeps over the large requests.
+    std::vector<Request*> large;
+    size_t most = 0;
+    double round_bytes = 0;
+    for (Request* r : active)
+        if (!r->resident) {
+            large.push_back(r);
+            most = std::max(most, r->plan.ops.size() - r->next_op);
+            round_bytes += 17.0 * (double)(1ull << r->n);
+        }
+    size_t rounds = most;
+    if (round_bytes > 0) rounds = std::min(rounds, std::max<size_t>(1, (size_t)(tick_bytes / round_bytes)));
     struct Launch {
         int kind, dtype;
         std::vector<Request*> members;
         size_t args_at, first_at;
         uint32_t blocks;
     };
-    std::map<std::pair<int, int>, Launch> sweeps;
+    std::vector<std::map<std::pair<int, int>, Launch>> sweeps(rounds);
     std::vector<Request*> finishing;
-    for (Request* r : active) {
-        if (r->resident) continue;
-        const Op& op = r->plan.ops[r->next_op];
-        Launch& L = sweeps[{op.kind, r->dtype}];
-        L.kind = op.kind;
-        L.dtype = r->dtype;
-        L.members.push_back(r);
-        if (r->next_op + 1 == r->plan.ops.size()) finishing.push_back(r);
+    for (Request* r : large) {
+        for (size_t k = 0; k < rounds && r->next_op + k < r->plan.ops.size(); ++k) {
+            const Op& op = r->plan.ops[r->next_op + k];
+            Launch& L = sweeps[k][{op.kind, r->dtype}];
+            L.kind = op.kind;
+            L.dtype = r->dtype;
+            L.members.push_back(r);
+        }
+        if (r->next_op + rounds >= r->plan.ops.size()) finishing.push_back(r);
     }
-    for (auto& kv : sweeps) {
-        kv.second.args_at = B.take(sizeof(SweepArgs) * kv.second.members.size());
-        kv.second.first_at = B.take(sizeof(uint32_t) * (kv.second.members.size() + 1));
-    }
+    for (auto& round : sweeps)
+        for (auto& kv : round) {
+            kv.second.args_at = B.take(sizeof(SweepArgs) * kv.second.members.size());
+            kv.second.first_at = B.take(sizeof(uint32_t) * (kv.second.members.size() + 1));
+        }
     const size_t rp_at = B.take(sizeof(double*) * finishing.size());
     const size_t rb_at = B.take(sizeof(uint32_t) * finishing.size());
     const size_t ro_at = B.take(sizeof(double*) * finishing.size());
-    if (B.size == 0) return QNAE_OK;
+    // Results of every request that ends this tick, gathered for one copy back.
+    std::vector<Request*> done;
+    for (int g = 0; g < 2; ++g)
+        for (New* w : res[g]) done.push_back(w->r);
+    for (Request* r : finishing) done.push_back(r);
+    const size_t out_at = B.take(sizeof(double) * 3 * std::max<size_t>(done.size(), 1));
+    if (admitted.empty() && large.empty()) return QNAE_OK;
     HIP_TRY(h_blob.reserve(B.size));
     HIP_TRY(d_blob.reserve(B.size));
     char* h = (char*)h_blob.ptr;
     char* d = (char*)d_blob.ptr;
-    // Per-request uploads into their own aux blocks, then the blob.
-    for (size_t i = 0; i < admitted.size(); ++i) {
-        Request& r = *admitted[i];
-        char* aux = pool + r.aux_off;
-        HIP_TRY(hipMemcpyAsync(aux + r.lut_off, tabs[i].data(), sizeof(float2) * tabs[i].size(), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(aux + r.form_off, forms[i].data(), sizeof(MixForm) * forms[i].size(),
-                               hipMemcpyHostToDevice, s));
-        std::memcpy(h + costs[i].rec_at, recs[i].data(), sizeof(ClauseRec) * recs[i].size());
+    std::unordered_map<Request*, double*> out_of;
+    for (size_t q = 0; q < done.size(); ++q) out_of[done[q]] = (double*)(d + out_at) + 3 * q;
+    for (auto& w : nw) {
+        std::memcpy(h + w.rec_at, w.recs.data(), sizeof(ClauseRec) * (size_t)w.nrec);
+        std::memcpy(h + w.tab_at, w.tabs.data(), sizeof(float2) * w.tabs.size());
+        std::memcpy(h + w.tab_at + w.r->form_off, w.forms.data(), sizeof(MixForm) * w.forms.size());
     }
     uint32_t cblocks[2] = {0, 0};
     int cmax[2] = {0, 0};
-    {
-        std::unordered_map<Request*, size_t> rec_at;
-        for (auto& c : costs) rec_at[c.r] = c.rec_at;
-        std::unordered_map<Request*, int> nrec;
-        for (auto& c : costs) nrec[c.r] = c.nrec;
-        for (int g = 0; g < 2; ++g) {
-            qnae::CostArgs* args = (qnae::CostArgs*)(h + cargs_at[g]);
-            uint32_t* first = (uint32_t*)(h + cfirst_at[g]);
-            for (size_t q = 0; q < cgroups[g].size(); ++q) {
-                Request& r = *cgroups[g][q];
-                args[q].clauses = (const ClauseRec*)(d + rec_at[&r]);
-                args[q].num_clauses = nrec[&r];
-                args[q].n = r.n;
-                args[q].cost = pool + r.cost_off;
-                args[q].zeros = nullptr;
-                first[q] = cblocks[g];
-                const uint64_t threads = r.n >= 5 ? (1ull << (r.n - 5)) : 1ull;
-                cblocks[g] += (uint32_t)((threads + 255) / 256);
-                cmax[g] = std::max(cmax[g], nrec[&r]);
-            }
-            first[cgroups[g].size()] = cblocks[g];
+    for (int g = 0; g < 2; ++g) {
+        qnae::CostArgs* args = (qnae::CostArgs*)(h + cargs_at[g]);
+        uint32_t* first = (uint32_t*)(h + cfirst_at[g]);
+        for (size_t q = 0; q < cgroups[g].size(); ++q) {
+            const New& w = *cgroups[g][q];
+            args[q].clauses = (const ClauseRec*)(d + w.rec_at);
+            args[q].num_clauses = w.nrec;
+            args[q].n = w.r->n;
+            args[q].cost = pool + w.r->cost_off;
+            args[q].zeros = nullptr;
+            first[q] = cblocks[g];
+            const uint64_t threads = w.r->n >= 5 ? (1ull << (w.r->n - 5)) : 1ull;
+            cblocks[g] += (uint32_t)((threads + 255) / 256);
+            cmax[g] = std::max(cmax[g], w.nrec);
         }
+        first[cgroups[g].size()] = cblocks[g];
     }
     for (int g = 0; g < 2; ++g) {
         qnae::ResidentArgs* ra = (qnae::ResidentArgs*)(h + res_at[g]);
         for (size_t q = 0; q < res[g].size(); ++q) {
-            Request& r = *res[g][q];
-            char* aux = pool + r.aux_off;
+            const New& w = *res[g][q];
+            const Request& r = *w.r;
             ra[q].state_in = nullptr;
             ra[q].cost = pool + r.cost_off;
-            ra[q].luts = (const float2*)(aux + r.lut_off);
-            ra[q].forms = (const MixForm*)(aux + r.form_off);
+            ra[q].luts = (const float2*)(d + w.tab_at);
+            ra[q].forms = (const MixForm*)(d + w.tab_at + r.form_off);
             ra[q].state_out = nullptr;
-            ra[q].out = (double*)(aux + r.res_off);
+            ra[q].out = out_of[w.r];
             ra[q].store_scale = make_float2(1.f, 0.f);
             ra[q].n = r.n;
             ra[q].p = r.p;
             ra[q].lut_len = r.m + 1;
         }
     }
-    for (auto& kv : sweeps) {
-        Launch& L = kv.second;
-        SweepArgs* args = (SweepArgs*)(h + L.args_at);
-        uint32_t* first = (uint32_t*)(h + L.first_at);
-        L.blocks = 0;
-        for (size_t q = 0; q < L.members.size(); ++q) {
-            Request& r = *L.members[q];
-            char* aux = pool + r.aux_off;
-            sweep_args(r.plan, r.plan.ops[r.next_op], (float2*)(pool + r.state_off), pool + r.cost_off,
-                       (const float2*)(aux + r.lut_off), (double*)(aux + r.part_off), &args[q]);
-            first[q] = L.blocks;
-            L.blocks += r.tiles;
+    for (size_t k = 0; k < rounds; ++k)
+        for (auto& kv : sweeps[k]) {
+            Launch& L = kv.second;
+            SweepArgs* args = (SweepArgs*)(h + L.args_at);
+            uint32_t* first = (uint32_t*)(h + L.first_at);
+            L.blocks = 0;
+            for (size_t q = 0; q < L.members.size(); ++q) {
+                Request& r = *L.members[q];
+                char* aux = pool + r.aux_off;
+                sweep_args(r.plan, r.plan.ops[r.next_op + k], (float2*)(pool + r.state_off), pool + r.cost_off,
+                           (const float2*)aux, (double*)(aux + r.part_off), &args[q]);
+                first[q] = L.blocks;
+                L.blocks += r.tiles;
+            }
+            first[L.members.size()] = L.blocks;
         }
-        first[L.members.size()] = L.blocks;
-    }
     {
         const double** rp = (const double**)(h + rp_at);
         uint32_t* rb = (uint32_t*)(h + rb_at);
         double** ro = (double**)(h + ro_at);
         for (size_t q = 0; q < finishing.size(); ++q) {
             Request& r = *finishing[q];
-            char* aux = pool + r.aux_off;
-            rp[q] = (const double*)(aux + r.part_off);
+            rp[q] = (const double*)(pool + r.aux_off + r.part_off);
             rb[q] = r.tiles;
-            ro[q] = (double*)(aux + r.res_off);
+            ro[q] = out_of[&r];
         }
     }
     HIP_TRY(hipMemcpyAsync(d, h, B.size, hipMemcpyHostToDevice, s));
+    for (auto& w : nw)
+        if (!w.r->resident)
+            HIP_TRY(hipMemcpyAsync(pool + w.r->aux_off, d + w.tab_at, w.r->part_off, hipMemcpyDeviceToDevice, s));
     for (int g = 0; g < 2; ++g) {
         if (cgroups[g].empty()) continue;
         HIP_TRY(qnae::launch_cost_batch((const qnae::CostArgs*)(d + cargs_at[g]), (const uint32_t*)(d + cfirst_at[g]),
@@ -325,32 +354,26 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
                                             (int)res[g].size(), s));
         ++launches;
     }
-    for (auto& kv : sweeps) {
-        const Launch& L = kv.second;
-        HIP_TRY(qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
-                                         (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, s));
-        ++launches;
-    }
+    for (size_t k = 0; k < rounds; ++k)
+        for (auto& kv : sweeps[k]) {
+            const Launch& L = kv.second;
+            HIP_TRY(qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
+                                             (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, s));
+            ++launches;
+        }
     if (!finishing.empty()) {
         HIP_TRY(qnae::launch_final_reduce_batch((const double* const*)(d + rp_at), (const uint32_t*)(d + rb_at),
                                                 (double* const*)(d + ro_at), (int)finishing.size(), s));
         ++launches;
     }
-    // Results of every request that ends this tick.
-    std::vector<Request*> done;
-    for (int g = 0; g < 2; ++g)
-        for (Request* r : res[g]) done.push_back(r);
-    for (Request* r : finishing) done.push_back(r);
-    std::vector<double> hres(3 * done.size());
-    for (size_t q = 0; q < done.size(); ++q)
-        HIP_TRY(hipMemcpyAsync(&hres[3 * q], pool + done[q]->aux_off + done[q]->res_off, 3 * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
+    if (!done.empty())
+        HIP_TRY(hipMemcpyAsync(h + out_at, d + out_at, sizeof(double) * 3 * done.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const double t = now_s();
+    const double* hres = (const double*)(h + out_at);
     {
         std::lock_guard<std::mutex> g(mu);
-        for (Request* r : active)
-            if (!r->resident) ++r->next_op;
+        for (Request* r : large) r->next_op = std::min(r->plan.ops.size(), r->next_op + rounds);
         for (size_t q = 0; q < done.size(); ++q) {
             Request& r = *done[q];
             const double sc = std::norm(r.final_scale);
@@ -384,14 +407,15 @@ void qnae_server::run() {
                 int so, co, ao;
                 plan_blocks(r, &so, &co, &ao);
                 uint64_t soff = 0, coff = 0, aoff = 0;
-                if (!buddy->alloc(co, &coff)) break;
-                if (!buddy->alloc(ao, &aoff)) {
-                    buddy->release(coff, co);
+                // largest block first: the state, then the cost, then the aux
+                if (so >= 0 && !buddy->alloc(so, &soff)) break;
+                if (!buddy->alloc(co, &coff)) {
+                    if (so >= 0) buddy->release(soff, so);
                     break;
                 }
-                if (so >= 0 && !buddy->alloc(so, &soff)) {
+                if (ao >= 0 && !buddy->alloc(ao, &aoff)) {
+                    if (so >= 0) buddy->release(soff, so);
                     buddy->release(coff, co);
-                    buddy->release(aoff, ao);
                     break;
                 }
                 r.cost_off = coff;
@@ -400,11 +424,6 @@ void qnae_server::run() {
                 r.aux_order = ao;
                 r.state_off = soff;
                 r.state_order = so;
-                const int T = r.p > 0 ? r.p : 1;
-                r.lut_off = 0;
-                r.form_off = round_up(sizeof(float2) * (uint64_t)T * (r.m + 1), 256);
-                r.part_off = r.form_off + round_up(sizeof(MixForm) * T, 256);
-                r.res_off = r.part_off + round_up(sizeof(double) * 3 * (uint64_t)(r.tiles ? r.tiles : 1), 256);
                 r.state = Request::ACTIVE;
                 queue.pop_front();
                 active.push_back(&r);
@@ -444,6 +463,7 @@ int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qn
     S->device = ctx->device;
     S->max_slots = max_slots;
     S->pool_bytes = 1ull << order;
+    if (const char* e = std::getenv("QNAE_SERVER_TICK_BYTES")) S->tick_bytes = std::max(1.0, std::atof(e));
     HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
     hipError_t e = hipMalloc((void**)&S->pool, S->pool_bytes);
     if (e != hipSuccess) {

@@ -48,8 +48,12 @@ def close(a, b):
     return np.allclose(tuple(a), tuple(b), rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("slots", [1, 5, 64])
-def test_server_results_equal_single_path(q, slots):
+@pytest.mark.parametrize("slots,tick_bytes", [(1, None), (5, None), (64, None), (7, "1"), (64, "3e7")])
+def test_server_results_equal_single_path(q, slots, tick_bytes, monkeypatch):
+    """tick_bytes 1: one sweep round per scheduler tick; 3e7: a few rounds;
+    default: every round of a lightly loaded server in one tick."""
+    if tick_bytes:
+        monkeypatch.setenv("QNAE_SERVER_TICK_BYTES", tick_bytes)
     reqs = requests(40, slots)
     with q.Server(pool_bytes=1 << 28, max_slots=slots) as s:
         tickets = [s.submit(r[3], r[0], r[4], r[5]) for r in reqs]
