@@ -133,6 +133,47 @@ def batched_bench(q, ctx, reps=5, count=512):
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
 
 
+def grad_bench(q, ctx, reps=10, adam_steps=200):
+    """Differentiation workload: n = 22, m = 46, p = 12 from the linear ramp
+    (beta negated), checkpoints every 4 layers. Time of one adjoint gradient
+    against one forward run, then Adam (lr 0.01) maximising p_succ through
+    QAOAFunction; parity of the gradient is the test suite's job."""
+    import torch
+    rec, cl, g0, b0 = load_workload("nae3_n22_p12")
+    n, m, p = rec["n"], rec["m"], rec["p"]
+    b0 = -b0
+    cost = q.build_cost_diagonal(cl, n, ctx=ctx)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_fwd = timed(lambda: q.qaoa_run(cost, n, m, g0, b0, ctx=ctx))
+    t_grad = timed(lambda: q.qaoa_grad(cost, n, m, g0, b0, w_psucc=1.0, w_energy=0.0, checkpoint_every=4, ctx=ctx))
+    g = torch.tensor(g0, dtype=torch.float64, requires_grad=True)
+    b = torch.tensor(b0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([g, b], lr=0.01)
+    start = None
+    t0 = time.perf_counter()
+    for _ in range(adam_steps):
+        opt.zero_grad()
+        ps, e = q.QAOAFunction.apply(g, b, cost, n, m, 4, ctx)
+        (-ps).backward()
+        opt.step()
+        start = ps.item() if start is None else start
+    dt = time.perf_counter() - t0
+    return {"workload": f"n={n} m={m} p={p} 3-NAE-SAT (seed {rec['seed']}), linear ramp start, checkpoint every 4",
+            "forward_ms": t_fwd * 1e3, "grad_ms": t_grad * 1e3, "grad_over_forward": t_grad / t_fwd,
+            "adam_steps": adam_steps, "adam_steps_per_s": adam_steps / dt,
+            "p_success_start": start, "p_success_end": ps.item(), "expected_cost_end": e.item()}
+
+
 def serving_bench(q, ctx, count=2000, warm=100, rate=200.0):
     """Poisson request trace (n 14..26, p 2..20, k in {3, 5}) through the
     continuous-batching server and through the plain path one request at a
@@ -224,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
@@ -250,6 +293,8 @@ def main():
     n, m, p = rec["n"], rec["m"], rec["p"]
     ctx = q.Context(0)
     cost = torch.empty(1 << n, dtype=torch.uint8 if m <= 255 else torch.uint16, device="cuda")
+    shape = {} if args.no_autotune else ctx.autotune(n, "u8" if m <= 255 else "u16", reps=3)
+    shape = shape or ctx.get_tune(n, "u8" if m <= 255 else "u16")
 
     def step():
         q.build_cost_diagonal(cl, n, out=cost, ctx=ctx)
@@ -290,7 +335,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "k": rec["k"], "m": m, "p": p,
                    "angles": "linear ramp", "seed": rec["seed"], "state": "complex64",
-                   "cost": "uint8" if m <= 255 else "uint16"},
+                   "cost": "uint8" if m <= 255 else "uint16",
+                   "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit")},
+                   "autotuned": not args.no_autotune},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(stats),
                      "launches": sw_launches, "avg_launch_ms": sw_ms / max(sw_launches, 1),
@@ -302,6 +349,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_bench(q, ctx)
+    if not args.no_grad:
+        out["gradient"] = grad_bench(q, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(q, ctx, count=args.serving_requests)
     if not args.no_cpu_baseline:

@@ -228,6 +228,38 @@ int qnae_server_stats(qnae_server *server, uint64_t *completed, uint64_t *ticks,
  * pool. Results not yet collected are lost. NULL is a no-op. */
 int qnae_server_destroy(qnae_server *server);
 
+/* Tile shape of the sweep path (qnae_qaoa_run for n > 14). The mixer of one
+ * layer is n butterfly passes over the state (appendix A.4); the library
+ * fuses them into sweeps, each applying the passes of a group of index bits
+ * to tiles of 2^tile_bits amplitudes held on chip. Every tile starts with a
+ * contiguous run of 2^low_run_bits amplitudes; index bits from page_bit up
+ * are spread over the groups so that a tile touches few memory pages
+ * (page_bit 64: no spreading). The fastest shape depends on n and is found by
+ * timing, not by formula. */
+typedef struct {
+    int32_t tile_bits;    /* 12, 13 or 14 */
+    int32_t low_run_bits; /* 4 .. 6 */
+    int32_t page_bit;     /* 4 .. 64 */
+    double ms_per_layer;  /* measured by qnae_autotune; ignored by qnae_set_tune */
+} qnae_tune;
+
+/* Times every candidate shape (tile_bits 12..14 x low_run_bits 4..5 x
+ * page_bit 18 or 64) on `reps` two-layer runs of an n-qubit state in the
+ * context's scratch memory, on `stream`, keeps the fastest for later
+ * qnae_qaoa_run calls at this n and cost type on this context, and writes it
+ * to *out. Needs 2^n * (8 + cost bytes) of device memory. For n <= 14 the
+ * whole circuit runs in one workgroup and there is nothing to tune: *out is
+ * all zeros. Synchronous. Errors: QNAE_EINVAL (n outside [1, QNAE_MAX_N], bad
+ * cost_dtype, reps outside [1, 1000], null out), QNAE_ENOMEM, QNAE_EHIP. */
+int qnae_autotune(qnae_ctx *ctx, int32_t n, int32_t cost_dtype, int32_t reps, qnae_tune *out, void *stream);
+
+/* Sets (tune != NULL) or clears (NULL) the shape used at n and cost_dtype,
+ * e.g. from a saved autotune result. qnae_get_tune writes the shape in use:
+ * the tuned one if set, else the default (ms_per_layer 0). Errors:
+ * QNAE_EINVAL (n outside [15, QNAE_MAX_N], bad cost_dtype or shape). */
+int qnae_set_tune(qnae_ctx *ctx, int32_t n, int32_t cost_dtype, const qnae_tune *tune);
+int qnae_get_tune(qnae_ctx *ctx, int32_t n, int32_t cost_dtype, qnae_tune *out);
+
 /* Kernel timing with HIP events, for measurement. While enabled, the context
  * records an event pair around every kernel it launches, on the stream the
  * kernel runs on, and tallies per kernel kind the number of launches, the

@@ -46,6 +46,11 @@ class _CInstance(ctypes.Structure):
                 ("betas", ctypes.POINTER(ctypes.c_double)), ("state_dev", ctypes.c_void_p)]
 
 
+class _CTune(ctypes.Structure):
+    _fields_ = [("tile_bits", ctypes.c_int32), ("low_run_bits", ctypes.c_int32), ("page_bit", ctypes.c_int32),
+                ("ms_per_layer", ctypes.c_double)]
+
+
 class _CKernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -90,6 +95,10 @@ def load_library():
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _F64P, _F64P,
                                        ctypes.POINTER(_CResult), vp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
+        tp = ctypes.POINTER(_CTune)
+        lib.qnae_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, tp, vp]
+        lib.qnae_set_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, tp]
+        lib.qnae_get_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, tp]
         lib.qnae_server_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(vp)]
         lib.qnae_server_submit.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
                                            ctypes.c_int32, u64p]
@@ -100,7 +109,8 @@ def load_library():
         for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
-                   lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy):
+                   lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
+                   lib.qnae_set_tune, lib.qnae_get_tune):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -150,6 +160,28 @@ class Context:
         return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].bytes))
                 for i in range(min(cnt.value, 16))}
 
+    def autotune(self, n: int, cost_dtype: str = "u8", reps: int = 3, stream=None) -> dict:
+        """Time the sweep tile shapes at n (scratch memory, two-layer runs)
+        and keep the fastest for this context; returns it ({} for n <= 14)."""
+        t = _CTune()
+        _check(load_library().qnae_autotune(self.handle, int(n), _dtype_code(cost_dtype), int(reps), ctypes.byref(t),
+                                            _stream(stream)))
+        return _tune_dict(t) if t.tile_bits else {}
+
+    def set_tune(self, n: int, tune: Optional[dict], cost_dtype: str = "u8"):
+        """Use `tune` ({tile_bits, low_run_bits, page_bit}) at n; None restores the default."""
+        t = None
+        if tune is not None:
+            t = _CTune(int(tune["tile_bits"]), int(tune["low_run_bits"]), int(tune["page_bit"]),
+                       float(tune.get("ms_per_layer", 0.0)))
+        _check(load_library().qnae_set_tune(self.handle, int(n), _dtype_code(cost_dtype),
+                                            ctypes.byref(t) if t is not None else None))
+
+    def get_tune(self, n: int, cost_dtype: str = "u8") -> dict:
+        t = _CTune()
+        _check(load_library().qnae_get_tune(self.handle, int(n), _dtype_code(cost_dtype), ctypes.byref(t)))
+        return _tune_dict(t)
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             load_library().qnae_destroy(self._h)
@@ -160,6 +192,18 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def _dtype_code(name) -> int:
+    codes = {"u8": QNAE_U8, "uint8": QNAE_U8, "u16": QNAE_U16, "uint16": QNAE_U16}
+    if name not in codes:
+        raise ValueError(f"cost dtype {name!r} is not u8/u16")
+    return codes[name]
+
+
+def _tune_dict(t) -> dict:
+    return {"tile_bits": int(t.tile_bits), "low_run_bits": int(t.low_run_bits), "page_bit": int(t.page_bit),
+            "ms_per_layer": float(t.ms_per_layer)}
 
 
 _default = {}

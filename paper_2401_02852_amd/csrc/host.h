@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -93,6 +94,9 @@ struct qnae_ctx {
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;
     std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
+    // sweep tile shapes chosen per (n, cost type), by qnae_autotune or qnae_set_tune
+    std::map<std::pair<int, int>, qnae_tune> tunes;
+    qnae_host::DevBuf tune_cost;
     int tile_bits = 13;                 // tile size of the plain sweeps (log2 amplitudes)
     int min_low_run = 4;                // minimum contiguous low run (log2 amplitudes)
     int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes
@@ -103,6 +107,9 @@ namespace qnae_host {
 // Makes the context's device current and waits until pinned staging is free.
 int enter(qnae_ctx* ctx);
 int check_cost_args(int32_t n, int32_t m, int32_t dtype);
+// Sweep tile shape at (n, cost type): the tuned one if set, else the context defaults.
+qnae_tune tune_for(const qnae_ctx* ctx, int n, int dtype);
+
 int check_run_args(int32_t n, int32_t m, int32_t dtype, const void* cost, const double* gammas, const double* betas,
                    int32_t p);
 

@@ -51,7 +51,7 @@ int qnae_destroy(qnae_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->state, &ctx->partials, &ctx->luts, &ctx->clauses, &ctx->forms, &ctx->small, &ctx->b_blob,
                       &ctx->b_states, &ctx->b_partials, &ctx->b_results, &ctx->g_states, &ctx->g_blob,
-                      &ctx->g_partials})
+                      &ctx->g_partials, &ctx->tune_cost})
         b->release();
     for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results})
         b->release();
@@ -141,7 +141,8 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
         const double rb = std::ldexp((double)(cost_dtype == QNAE_U8 ? 1 : 2) * T + (keep ? 8.0 : 0.0), n);
         HIP_TRY(timed(ctx, K_RESIDENT, rb, s, [&] { return qnae::launch_resident(cost_dtype, a, s); }));
     } else {
-        const int TB = ctx->tile_bits;
+        const qnae_tune tune = tune_for(ctx, n, cost_dtype);
+        const int TB = tune.tile_bits;
         float2* psi = (float2*)state_dev;
         if (!psi) {
             HIP_TRY(ctx->state.reserve(sizeof(float2) << n));
@@ -150,7 +151,7 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
         const int64_t blocks = 1ll << (n - TB);
         HIP_TRY(ctx->partials.reserve(sizeof(double) * 3 * (size_t)blocks));
         SweepPlan P;
-        plan_sweeps(P, n, m, p, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, keep, forms, final_scale);
+        plan_sweeps(P, n, m, p, cost_dtype, TB, tune.low_run_bits, tune.page_bit, keep, forms, final_scale);
         for (const Op& op : P.ops) {
             SweepArgs a;
             sweep_args(P, op, psi, cost_dev, (const float2*)ctx->luts.ptr, (double*)ctx->partials.ptr, &a);

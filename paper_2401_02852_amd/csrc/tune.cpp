@@ -1,0 +1,126 @@
+// Sweep tile-shape autotuning (include/qnae.h, qnae_autotune / qnae_set_tune /
+// qnae_get_tune). A candidate is timed on two-layer runs of the real sweep
+// kernels over scratch memory: cost diagonal all zero, phase tables of 64
+// entries, angles away from the special values, so every sweep kind of a
+// p >= 2 plan runs (first, middle, boundary, final).
+#include <algorithm>
+#include <cmath>
+
+#include "host.h"
+
+using namespace qnae_host;
+using qnae::MixForm;
+using qnae::SweepArgs;
+
+namespace qnae_host {
+
+qnae_tune tune_for(const qnae_ctx* ctx, int n, int dtype) {
+    auto it = ctx->tunes.find({n, dtype});
+    if (it != ctx->tunes.end()) return it->second;
+    return qnae_tune{ctx->tile_bits, ctx->min_low_run, ctx->page_bit, 0.0};
+}
+
+}  // namespace qnae_host
+
+namespace {
+
+int check_shape(const qnae_tune& t) {
+    if (t.tile_bits < 12 || t.tile_bits > 14) return fail(QNAE_EINVAL, "tile_bits=%d outside [12, 14]", t.tile_bits);
+    if (t.low_run_bits < 4 || t.low_run_bits > 6)
+        return fail(QNAE_EINVAL, "low_run_bits=%d outside [4, 6]", t.low_run_bits);
+    if (t.page_bit < 4 || t.page_bit > 64) return fail(QNAE_EINVAL, "page_bit=%d outside [4, 64]", t.page_bit);
+    return QNAE_OK;
+}
+
+int check_tune_target(int32_t n, int32_t dtype, int32_t lo) {
+    if (n < lo || n > QNAE_MAX_N) return fail(QNAE_EINVAL, "n=%d outside [%d, %d]", n, lo, QNAE_MAX_N);
+    if (dtype != QNAE_U8 && dtype != QNAE_U16) return fail(QNAE_EINVAL, "cost_dtype=%d is not QNAE_U8/QNAE_U16", dtype);
+    return QNAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qnae_tune* out, void* stream) {
+    if (int rc = check_tune_target(n, cost_dtype, 1)) return rc;
+    if (reps < 1 || reps > 1000) return fail(QNAE_EINVAL, "reps=%d outside [1, 1000]", reps);
+    if (!out) return fail(QNAE_EINVAL, "null output pointer");
+    if (int rc = enter(ctx)) return rc;
+    *out = qnae_tune{0, 0, 0, 0.0};
+    if (n <= kResidentMaxN) return QNAE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int p = 2, m = 63, lut_len = m + 1;
+    const double gammas[p] = {0.4, 0.7}, betas[p] = {0.3, 0.2};
+    HIP_TRY(ctx->h_luts.reserve(sizeof(float2) * p * lut_len));
+    HIP_TRY(ctx->h_forms.reserve(sizeof(MixForm) * p));
+    float2* tables = (float2*)ctx->h_luts.ptr;
+    MixForm* forms = (MixForm*)ctx->h_forms.ptr;
+    const std::complex<double> final_scale = build_tables(n, m, gammas, betas, p, tables, forms);
+    HIP_TRY(ctx->luts.reserve(sizeof(float2) * p * lut_len));
+    HIP_TRY(hipMemcpyAsync(ctx->luts.ptr, tables, sizeof(float2) * p * lut_len, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx->state.reserve(sizeof(float2) << n));
+    const size_t cbytes = (size_t)(cost_dtype == QNAE_U8 ? 1 : 2) << n;
+    HIP_TRY(ctx->tune_cost.reserve(cbytes));
+    HIP_TRY(hipMemsetAsync(ctx->tune_cost.ptr, 0, cbytes, s));
+    HIP_TRY(ctx->partials.reserve(sizeof(double) * 3 * ((size_t)1 << (n - 12))));
+    HIP_TRY(hipEventRecord(ctx->staging_done, s));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    HIP_TRY(hipEventCreate(&ev[0]));
+    if (hipError_t e = hipEventCreate(&ev[1])) {
+        (void)hipEventDestroy(ev[0]);
+        return fail(QNAE_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    auto run = [&](const SweepPlan& P, int TB) -> hipError_t {
+        for (const Op& op : P.ops) {
+            SweepArgs a;
+            sweep_args(P, op, (float2*)ctx->state.ptr, ctx->tune_cost.ptr, (const float2*)ctx->luts.ptr,
+                       (double*)ctx->partials.ptr, &a);
+            if (hipError_t e = qnae::launch_sweep(TB, cost_dtype, op.kind, a, s)) return e;
+        }
+        return hipSuccess;
+    };
+    qnae_tune best{0, 0, 0, 1e300};
+    hipError_t err = hipSuccess;
+    for (int TB = 12; TB <= 14 && !err; ++TB)
+        for (int low = 4; low <= 5 && !err; ++low)
+            for (int page : {18, 64}) {
+                SweepPlan P;
+                plan_sweeps(P, n, m, p, cost_dtype, TB, low, page, false, forms, final_scale);
+                if ((err = run(P, TB))) break;  // warm-up
+                if ((err = hipEventRecord(ev[0], s))) break;
+                for (int r = 0; r < reps && !err; ++r) err = run(P, TB);
+                if (err || (err = hipEventRecord(ev[1], s)) || (err = hipEventSynchronize(ev[1]))) break;
+                float ms = 0.f;
+                if ((err = hipEventElapsedTime(&ms, ev[0], ev[1]))) break;
+                const double per_layer = ms / (double)(reps * p);
+                if (per_layer < best.ms_per_layer) best = qnae_tune{TB, low, page, per_layer};
+            }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (err) return fail(QNAE_EHIP, "autotune: %s", hipGetErrorString(err));
+    ctx->tunes[{n, cost_dtype}] = best;
+    *out = best;
+    return QNAE_OK;
+}
+
+int qnae_set_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, const qnae_tune* tune) {
+    if (!ctx) return fail(QNAE_EINVAL, "null context");
+    if (int rc = check_tune_target(n, cost_dtype, kResidentMaxN + 1)) return rc;
+    if (!tune) {
+        ctx->tunes.erase({n, cost_dtype});
+        return QNAE_OK;
+    }
+    if (int rc = check_shape(*tune)) return rc;
+    ctx->tunes[{n, cost_dtype}] = qnae_tune{tune->tile_bits, tune->low_run_bits, tune->page_bit, tune->ms_per_layer};
+    return QNAE_OK;
+}
+
+int qnae_get_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, qnae_tune* out) {
+    if (!ctx || !out) return fail(QNAE_EINVAL, "null argument");
+    if (int rc = check_tune_target(n, cost_dtype, kResidentMaxN + 1)) return rc;
+    *out = tune_for(ctx, n, cost_dtype);
+    return QNAE_OK;
+}
+
+}  // extern "C"

@@ -139,3 +139,15 @@ def test_server_binding_without_gpu():
     lib = b.load_library()
     assert lib.qnae_server_submit(None, None, 0, 4, 1, None, None, 0, None) == -1
     assert lib.qnae_server_destroy(None) == 0
+
+
+def test_tune_binding_without_gpu():
+    b = _lib_or_skip()
+    lib = b.load_library()
+    t = b._CTune(13, 4, 18, 0.0)
+    assert lib.qnae_set_tune(None, 20, 1, ctypes.byref(t)) == -1
+    assert b"null context" in lib.qnae_last_error(None)
+    assert lib.qnae_autotune(None, 20, 1, 0, ctypes.byref(t), None) == -1
+    assert b"reps=0" in lib.qnae_last_error(None)
+    assert lib.qnae_autotune(None, 40, 1, 1, ctypes.byref(t), None) == -1
+    assert b"n=40" in lib.qnae_last_error(None)
