@@ -52,9 +52,15 @@ def _load():
     lib.oracle_qaoa.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P, _F64P, _F64P]
     lib.oracle_qaoa_grad.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _F64P, _F64P,
                                      ctypes.c_double, ctypes.c_double, _F64P, _F64P, _F64P]
+    lib.oracle_cost_pred.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, ctypes.c_int, _I32P]
+    lib.oracle_cost_at_pred.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, ctypes.c_int, _U64P,
+                                        ctypes.c_int64, _I32P]
+    lib.oracle_count_solutions_pred.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, ctypes.c_int,
+                                                _U64P]
     lib.oracle_num_threads.argtypes = []
     for fn in (lib.oracle_cost, lib.oracle_cost_at, lib.oracle_count_solutions, lib.oracle_state,
-               lib.oracle_qaoa, lib.oracle_qaoa_grad, lib.oracle_num_threads):
+               lib.oracle_qaoa, lib.oracle_qaoa_grad, lib.oracle_num_threads, lib.oracle_cost_pred,
+               lib.oracle_cost_at_pred, lib.oracle_count_solutions_pred):
         fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -78,33 +84,43 @@ def _instance(clauses, n):
     return np.ascontiguousarray(cl), m, max(k, 1)
 
 
-def cost(clauses, n: int) -> np.ndarray:
-    """C(x) for all x in [0, 2^n) as int32 (Section 3.2, eq. knaesatobj)."""
+PREDICATES = {"nae": 0, "sat": 1}
+
+
+def _pred(predicate: str) -> int:
+    if predicate not in PREDICATES:
+        raise ValueError(f"predicate {predicate!r} is not 'nae' or 'sat'")
+    return PREDICATES[predicate]
+
+
+def cost(clauses, n: int, predicate: str = "nae") -> np.ndarray:
+    """C(x) for all x in [0, 2^n) as int32: NAE-violated clauses (Section 3.2,
+    eq. knaesatobj) or, with predicate "sat", SAT-violated ones (Section 2.2)."""
     cl, m, k = _instance(clauses, n)
     out = np.empty(1 << n, dtype=np.int32)
-    rc = _load().oracle_cost(n, m, k, cl.ctypes.data_as(_I32P), out.ctypes.data_as(_I32P))
+    rc = _load().oracle_cost_pred(n, m, k, cl.ctypes.data_as(_I32P), _pred(predicate), out.ctypes.data_as(_I32P))
     if rc:
         raise ValueError("oracle_cost: invalid instance")
     return out
 
 
-def cost_at(clauses, n: int, xs) -> np.ndarray:
+def cost_at(clauses, n: int, xs, predicate: str = "nae") -> np.ndarray:
     """C(x) at the given basis states (int32)."""
     cl, m, k = _instance(clauses, n)
     x = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
     out = np.empty(x.shape[0], dtype=np.int32)
-    rc = _load().oracle_cost_at(n, m, k, cl.ctypes.data_as(_I32P), x.ctypes.data_as(_U64P),
-                                x.shape[0], out.ctypes.data_as(_I32P))
+    rc = _load().oracle_cost_at_pred(n, m, k, cl.ctypes.data_as(_I32P), _pred(predicate),
+                                     x.ctypes.data_as(_U64P), x.shape[0], out.ctypes.data_as(_I32P))
     if rc:
         raise ValueError("oracle_cost_at: invalid arguments")
     return out
 
 
-def count_solutions(clauses, n: int) -> int:
+def count_solutions(clauses, n: int, predicate: str = "nae") -> int:
     """#{x : C(x) = 0}."""
     cl, m, k = _instance(clauses, n)
     c = ctypes.c_uint64(0)
-    rc = _load().oracle_count_solutions(n, m, k, cl.ctypes.data_as(_I32P), ctypes.byref(c))
+    rc = _load().oracle_count_solutions_pred(n, m, k, cl.ctypes.data_as(_I32P), _pred(predicate), ctypes.byref(c))
     if rc:
         raise ValueError("oracle_count_solutions: invalid instance")
     return int(c.value)

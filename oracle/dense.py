@@ -54,6 +54,30 @@ def walsh_cost(clauses, n: int) -> np.ndarray:
     return total
 
 
+def walsh_cost_sat(clauses, n: int) -> np.ndarray:
+    """Diagonal of the k-SAT cost from Pauli-Z products (Appendix A.2): an
+    OR-clause is violated when every literal is false, so its Hamiltonian is
+    H_{not sigma} = 2^-k prod_j (I - s_j Z_j)
+      = 2^-k sum_{S subset of [k]} (-1)^{|S|} prod_{j in S} s_j Z_{v_j},
+    with s as in walsh_cost (odd orders kept: no global-flip symmetry)."""
+    cl = np.asarray(clauses, dtype=np.int64)
+    z = z_values(n)
+    total = np.zeros(1 << n)
+    for clause in cl:
+        k = len(clause)
+        s = np.where(clause > 0, -1.0, 1.0)
+        v = np.abs(clause) - 1
+        term = np.zeros(1 << n)
+        for size in range(0, k + 1):
+            for S in itertools.combinations(range(k), size):
+                prod = np.full(1 << n, (-1.0) ** size)
+                for j in S:
+                    prod = prod * s[j] * z[v[j]]
+                term += prod
+        total += term * 2.0 ** (-k)
+    return total
+
+
 def mixer_hamiltonian(n: int) -> np.ndarray:
     """H_B = sum_j X_j as a dense 2^n x 2^n matrix (Appendix A.3). Qubit j is
     bit j of the basis index, so X_j is the Kronecker product with X in the

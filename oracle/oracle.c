@@ -1,6 +1,7 @@
 /*
  * Plain FP64 CPU oracle for depth-p QAOA on random k-NAE-SAT
- * (Elkadi & Bondesan, "Quantum Approximate Optimisation for Not-All-Equal SAT").
+ * (Elkadi & Bondesan, "Quantum Approximate Optimisation for Not-All-Equal SAT"),
+ * with the plain k-SAT clause predicate beside the NAE one.
  *
  * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
  * baseline leg of the benchmark may load or call this library. The GPU
@@ -53,6 +54,19 @@ static int clause_violated(uint64_t x, const int32_t *clause, int k) {
     return n_true == 0 || n_true == k;
 }
 
+/* k-SAT (Section 2.2): an OR-clause is satisfied when any of its literals is
+ * true, so it is violated exactly when every literal is false. */
+static int sat_clause_violated(uint64_t x, const int32_t *clause, int k) {
+    for (int j = 0; j < k; j++)
+        if (literal_value(x, clause[j])) return 0;
+    return 1;
+}
+
+/* Clause predicate: 0 = NAE (the paper's problem), 1 = k-SAT. */
+static int violated(int pred, uint64_t x, const int32_t *clause, int k) {
+    return pred ? sat_clause_violated(x, clause, k) : clause_violated(x, clause, k);
+}
+
 static int check_instance(int n, int m, int k, const int32_t *lits) {
     if (n < 1 || n > 40 || m < 0 || k < 1) return -1;
     if (m > 0 && lits == NULL) return -1;
@@ -63,50 +77,65 @@ static int check_instance(int n, int m, int k, const int32_t *lits) {
     return 0;
 }
 
-/* Cost diagonal C(x) = number of NAE-violated clauses (Section 3.2,
- * eq. knaesatobj), for every x in [0, 2^n). */
-int oracle_cost(int n, int m, int k, const int32_t *lits, int32_t *cost) {
-    if (check_instance(n, m, k, lits) || cost == NULL) return -1;
+/* Cost diagonal C(x) = number of violated clauses for every x in [0, 2^n):
+ * NAE-violated (pred 0; Section 3.2, eq. knaesatobj) or SAT-violated
+ * (pred 1; Section 2.2). */
+int oracle_cost_pred(int n, int m, int k, const int32_t *lits, int pred, int32_t *cost) {
+    if (check_instance(n, m, k, lits) || cost == NULL || pred < 0 || pred > 1) return -1;
     int64_t N = (int64_t)1 << n;
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < N; x++) {
         int32_t c = 0;
-        for (int i = 0; i < m; i++) c += clause_violated((uint64_t)x, lits + (int64_t)i * k, k);
+        for (int i = 0; i < m; i++) c += violated(pred, (uint64_t)x, lits + (int64_t)i * k, k);
         cost[x] = c;
     }
     return 0;
 }
 
-/* C(x) at the given basis states only (same definition as oracle_cost). */
-int oracle_cost_at(int n, int m, int k, const int32_t *lits, const uint64_t *xs,
-                   int64_t count, int32_t *cost) {
-    if (check_instance(n, m, k, lits) || xs == NULL || cost == NULL || count < 0) return -1;
+int oracle_cost(int n, int m, int k, const int32_t *lits, int32_t *cost) {
+    return oracle_cost_pred(n, m, k, lits, 0, cost);
+}
+
+/* C(x) at the given basis states only (same definition as oracle_cost_pred). */
+int oracle_cost_at_pred(int n, int m, int k, const int32_t *lits, int pred, const uint64_t *xs,
+                        int64_t count, int32_t *cost) {
+    if (check_instance(n, m, k, lits) || xs == NULL || cost == NULL || count < 0 || pred < 0 || pred > 1)
+        return -1;
     for (int64_t q = 0; q < count; q++)
         if (n < 64 && (xs[q] >> n) != 0) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < count; q++) {
         int32_t c = 0;
-        for (int i = 0; i < m; i++) c += clause_violated(xs[q], lits + (int64_t)i * k, k);
+        for (int i = 0; i < m; i++) c += violated(pred, xs[q], lits + (int64_t)i * k, k);
         cost[q] = c;
     }
     return 0;
 }
 
-/* Number of NAE solutions, #{x : C(x) = 0}, without storing C. Used to keep
+int oracle_cost_at(int n, int m, int k, const int32_t *lits, const uint64_t *xs, int64_t count,
+                   int32_t *cost) {
+    return oracle_cost_at_pred(n, m, k, lits, 0, xs, count, cost);
+}
+
+/* Number of solutions, #{x : C(x) = 0}, without storing C. Used to keep
  * only satisfiable instances (Section 3.3: evaluation sets are satisfiable). */
-int oracle_count_solutions(int n, int m, int k, const int32_t *lits, uint64_t *count) {
-    if (check_instance(n, m, k, lits) || count == NULL) return -1;
+int oracle_count_solutions_pred(int n, int m, int k, const int32_t *lits, int pred, uint64_t *count) {
+    if (check_instance(n, m, k, lits) || count == NULL || pred < 0 || pred > 1) return -1;
     int64_t N = (int64_t)1 << n;
     uint64_t total = 0;
 #pragma omp parallel for schedule(static) reduction(+ : total)
     for (int64_t x = 0; x < N; x++) {
         int sat = 1;
         for (int i = 0; i < m && sat; i++)
-            if (clause_violated((uint64_t)x, lits + (int64_t)i * k, k)) sat = 0;
+            if (violated(pred, (uint64_t)x, lits + (int64_t)i * k, k)) sat = 0;
         total += (uint64_t)sat;
     }
     *count = total;
     return 0;
+}
+
+int oracle_count_solutions(int n, int m, int k, const int32_t *lits, uint64_t *count) {
+    return oracle_count_solutions_pred(n, m, k, lits, 0, count);
 }
 
 /* ------------------------------------------------------------------ */

@@ -151,6 +151,73 @@ def test_nae_equals_sat_of_x_and_complement():
 
 
 # ---------------------------------------------------------------------------
+# k-SAT predicate (Section 2.2: an OR-clause is violated iff all literals are
+# false)
+# ---------------------------------------------------------------------------
+
+def brute_cost_sat(clauses, n):
+    out = []
+    for x in range(1 << n):
+        c = 0
+        for cl in clauses:
+            if not any(((x >> (abs(l) - 1)) & 1) == (1 if l > 0 else 0) for l in cl):
+                c += 1
+        out.append(c)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sat_cost_brute_force_and_walsh(seed):
+    rng = np.random.default_rng(50 + seed)
+    n = int(rng.integers(2, 9))
+    k = int(rng.integers(1, min(n, 5) + 1))
+    m = int(rng.integers(0, 4 * n))
+    cl = rand_instance(n, k, m, 70 + seed).reshape(m, k)
+    c = oracle.cost(cl, n, "sat")
+    assert np.array_equal(c, brute_cost_sat(cl, n))
+    assert np.array_equal(c, dense.walsh_cost_sat(cl, n).round().astype(np.int64))
+    assert oracle.count_solutions(cl, n, "sat") == int((c == 0).sum())
+    xs = np.arange(0, 1 << n, 3, dtype=np.uint64)
+    assert np.array_equal(oracle.cost_at(cl, n, xs, "sat"), c[xs.astype(np.int64)])
+
+
+def test_sat_repeated_variables():
+    """x OR NOT x is never violated; a repeated same-sign literal acts once."""
+    cl = np.array([[1, -1, 2], [3, 3, -4], [-2, -2, -2]], dtype=np.int32)
+    c = oracle.cost(cl, 4, "sat")
+    assert np.array_equal(c, brute_cost_sat(cl, 4))
+    assert np.array_equal(c, dense.walsh_cost_sat(cl, 4).round().astype(np.int64))
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_sat_cost_sum_and_nae_decomposition(k):
+    """Each k-SAT clause with distinct variables is violated on 2^{n-k}
+    assignments, so sum_x C = m 2^{n-k}; and a clause is NAE-violated exactly
+    when it is SAT-violated at x or at NOT x (Appendix A.5), never both, so
+    C_NAE(x) = C_SAT(x) + C_SAT(NOT x)."""
+    n = 11
+    cl = rand_instance(n, k, 3 * n, 900 + k)
+    sat = oracle.cost(cl, n, "sat")
+    assert int(sat.sum()) == 3 * n * 2 ** (n - k)
+    x = np.arange(1 << n)
+    assert np.array_equal(oracle.cost(cl, n), sat + sat[x ^ ((1 << n) - 1)])
+
+
+def test_sat_qaoa_matches_dense():
+    """The QAOA oracle on a cost without the global-flip symmetry."""
+    n, p = 6, 3
+    cl = rand_instance(n, 3, 14, 4)
+    c = oracle.cost(cl, n, "sat")
+    x = np.arange(1 << n)
+    assert not np.array_equal(c, c[x ^ ((1 << n) - 1)])
+    rng = np.random.default_rng(8)
+    g, b = rng.uniform(-2, 2, p), rng.uniform(-2, 2, p)
+    assert np.allclose(oracle.qaoa(c, n, g, b), dense.qaoa(c, n, g, b), rtol=0, atol=1e-12)
+    psi = oracle.state(c, n, g, b)
+    assert np.allclose(psi, dense.qaoa_state(c, n, g, b), rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
 # P8: dense matrix exponential at small n
 # ---------------------------------------------------------------------------
 
