@@ -96,6 +96,18 @@ int qnae_build_cost_diagonal(qnae_ctx *ctx, const int32_t *clauses, int32_t m,
                              int32_t cost_dtype, uint64_t *num_solutions,
                              void *stream);
 
+/* Clause predicates: NAE (the paper's problem) and plain k-SAT, where an
+ * OR-clause is violated exactly when every literal is false (Section 2.2). */
+enum { QNAE_PRED_NAE = 0, QNAE_PRED_SAT = 1 };
+
+/* qnae_build_cost_diagonal with the clause predicate chosen: C(x) = number of
+ * clauses violated at x under `predicate`. Same arguments, results and
+ * errors, plus QNAE_EINVAL for an unknown predicate. A k-SAT clause holding
+ * a variable with both signs is never violated. */
+int qnae_build_cost_diagonal_pred(qnae_ctx *ctx, const int32_t *clauses, int32_t m, int32_t n, int32_t k,
+                                  int32_t predicate, void *cost_dev, int32_t cost_dtype,
+                                  uint64_t *num_solutions, void *stream);
+
 /* Run depth-p QAOA from |+> on the cost diagonal and read out p_succ, E[C]
  * and the norm (Section 3.3; Definition of the success probability).
  *
@@ -146,13 +158,14 @@ int qnae_qaoa_grad(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype, int3
  * Batches: many independent instances per launch (one GPU, ragged sizes).
  * ------------------------------------------------------------------------- */
 
-/* One cost diagonal of a batch: the arguments of qnae_build_cost_diagonal. */
+/* One cost diagonal of a batch: the arguments of qnae_build_cost_diagonal_pred. */
 typedef struct {
     const int32_t *clauses;   /* host, m * k literals (NULL when m = 0) */
     int32_t m, n, k;
     void *cost_dev;           /* caller-owned device buffer, 2^n of cost_dtype */
     int32_t cost_dtype;       /* QNAE_U8 (m <= 255) or QNAE_U16 */
     uint64_t *num_solutions;  /* optional host pointer (the call then waits) */
+    int32_t predicate;        /* QNAE_PRED_NAE (0) or QNAE_PRED_SAT */
 } qnae_cost_job;
 
 /* Builds `count` cost diagonals (same definition as qnae_build_cost_diagonal)

@@ -13,6 +13,7 @@ _LIB_NAME = "libqnae.so"
 
 QNAE_U8 = 1
 QNAE_U16 = 2
+PREDICATES = {"nae": 0, "sat": 1}  # QNAE_PRED_NAE, QNAE_PRED_SAT
 _STATUS = {0: "QNAE_OK", -1: "QNAE_EINVAL", -2: "QNAE_ENOMEM", -3: "QNAE_EHIP",
            -4: "QNAE_EBUSY", -5: "QNAE_ETIMEDOUT"}
 
@@ -37,7 +38,7 @@ class _CResult(ctypes.Structure):
 class _CCostJob(ctypes.Structure):
     _fields_ = [("clauses", ctypes.POINTER(ctypes.c_int32)), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32),
-                ("num_solutions", ctypes.POINTER(ctypes.c_uint64))]
+                ("num_solutions", ctypes.POINTER(ctypes.c_uint64)), ("predicate", ctypes.c_int32)]
 
 
 class _CInstance(ctypes.Structure):
@@ -83,6 +84,9 @@ def load_library():
         lib.qnae_last_error.restype = ctypes.c_char_p
         lib.qnae_build_cost_diagonal.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                  vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), vp]
+        lib.qnae_build_cost_diagonal_pred.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                      ctypes.c_int32, vp, ctypes.c_int32,
+                                                      ctypes.POINTER(ctypes.c_uint64), vp]
         lib.qnae_qaoa_run.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
                                       ctypes.c_int32, vp, ctypes.POINTER(_CResult), vp]
         lib.qnae_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -107,6 +111,7 @@ def load_library():
         lib.qnae_server_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, u64p]
         lib.qnae_server_destroy.argtypes = [vp]
         for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
+                   lib.qnae_build_cost_diagonal_pred,
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
@@ -222,10 +227,17 @@ def cost_dtype_for(m: int):
     return torch.uint8 if m <= 255 else torch.uint16
 
 
-def build_cost_diagonal(clauses, n: int, *, out=None, count_solutions: bool = False,
+def _pred_code(predicate) -> int:
+    if predicate not in PREDICATES:
+        raise ValueError(f"predicate {predicate!r} is not 'nae' or 'sat'")
+    return PREDICATES[predicate]
+
+
+def build_cost_diagonal(clauses, n: int, *, out=None, count_solutions: bool = False, predicate: str = "nae",
                         ctx: Optional[Context] = None, stream=None):
     """C(x) for x in [0, 2^n) on the current device, uint8 when m <= 255 else
-    uint16. ``clauses`` is an [m, k] int array of DIMACS-style literals.
+    uint16. ``clauses`` is an [m, k] int array of DIMACS-style literals;
+    ``predicate`` "nae" (the paper's problem) or "sat" (plain k-SAT).
     Returns the tensor, or (tensor, #solutions) with count_solutions."""
     import torch
     cl = np.ascontiguousarray(np.asarray(clauses, dtype=np.int32))
@@ -238,8 +250,8 @@ def build_cost_diagonal(clauses, n: int, *, out=None, count_solutions: bool = Fa
     code = QNAE_U8 if out.dtype == torch.uint8 else QNAE_U16
     ctx = ctx or default_context()
     sols = ctypes.c_uint64(0)
-    _check(load_library().qnae_build_cost_diagonal(
-        ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1),
+    _check(load_library().qnae_build_cost_diagonal_pred(
+        ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1), _pred_code(predicate),
         ctypes.c_void_p(out.data_ptr()), code,
         ctypes.byref(sols) if count_solutions else None, _stream(stream)))
     return (out, int(sols.value)) if count_solutions else out
@@ -271,11 +283,12 @@ def qaoa_run(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[C
     return Result(res.p_success, res.expected_cost, res.norm)
 
 
-def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = False,
+def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = False, predicate="nae",
                          ctx: Optional[Context] = None, stream=None):
     """Batched build_cost_diagonal: one tensor per (clauses, n) pair, built
-    with one launch per cost type. Returns the list of tensors, or
-    (tensors, solution counts) with count_solutions."""
+    with one launch per cost type. ``predicate`` is one name for all or a list
+    of names. Returns the list of tensors, or (tensors, solution counts) with
+    count_solutions."""
     import torch
     arrs = [np.ascontiguousarray(np.asarray(c, dtype=np.int32)) for c in clause_sets]
     if len(arrs) != len(ns):
@@ -284,6 +297,9 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
         outs = [torch.empty(1 << n, dtype=cost_dtype_for(a.shape[0]), device="cuda") for a, n in zip(arrs, ns)]
     jobs = (_CCostJob * len(arrs))()
     sols = [ctypes.c_uint64(0) for _ in arrs]
+    preds = [predicate] * len(arrs) if isinstance(predicate, str) else list(predicate)
+    if len(preds) != len(arrs):
+        raise ValueError("predicate list and clause_sets differ in length")
     for i, (a, n, o) in enumerate(zip(arrs, ns, outs)):
         if a.ndim != 2:
             raise ValueError("clauses must be [m, k] literal arrays")
@@ -293,6 +309,7 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
         jobs[i].cost_dev = o.data_ptr()
         jobs[i].cost_dtype = QNAE_U8 if o.dtype == torch.uint8 else QNAE_U16
         jobs[i].num_solutions = ctypes.pointer(sols[i]) if count_solutions else None
+        jobs[i].predicate = _pred_code(preds[i])
     ctx = ctx or default_context()
     _check(load_library().qnae_build_cost_diagonal_batched(ctx.handle, jobs, len(arrs), _stream(stream)))
     return (outs, [int(v.value) for v in sols]) if count_solutions else outs

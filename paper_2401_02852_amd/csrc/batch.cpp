@@ -28,6 +28,8 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
         int rc = check_cost_args(j.n, j.m, j.cost_dtype);
         if (!rc && !j.cost_dev) rc = fail(QNAE_EINVAL, "null cost_dev");
         if (!rc) rc = check_literals(j.clauses, j.m, j.n, j.k);
+        if (!rc && j.predicate != QNAE_PRED_NAE && j.predicate != QNAE_PRED_SAT)
+            rc = fail(QNAE_EINVAL, "predicate=%d is not QNAE_PRED_NAE/QNAE_PRED_SAT", j.predicate);
         if (rc) return fail(rc, "job %d: %s", i, std::string(last_error()).c_str());
     }
     if (count == 0) return QNAE_OK;
@@ -57,7 +59,7 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
     size_t at = 0;
     for (int i = 0; i < count; ++i) {
         rec_off[i] = at;
-        nrec[i] = make_clause_records(jobs[i].clauses, jobs[i].m, jobs[i].k, recs + at);
+        nrec[i] = make_clause_records(jobs[i].clauses, jobs[i].m, jobs[i].k, recs + at, jobs[i].predicate);
         at += (size_t)nrec[i];
     }
     std::memset(h + zero_at, 0, sizeof(unsigned long long) * count);

@@ -8,15 +8,16 @@
 namespace qnae {
 
 // ---------------------------------------------------------------------------
-// Cost diagonal (NAE-violated clause count per basis state)
+// Cost diagonal (violated clause count per basis state)
 // ---------------------------------------------------------------------------
 
 // One clause after host normalisation. With M = the set of variables the
 // clause touches and P = the variables whose literal is negated, the clause is
 // violated at x exactly when ((x ^ P) & M) is 0 (all literals false) or M (all
-// true). The low 5 bits are folded into two 32-bit tables over the position j
-// of x inside an aligned run of 32 states: zero_tab bit j says
-// ((j ^ P) & M & 31) == 0, full_tab bit j says it equals M & 31.
+// true; NAE) or only when it is 0 (k-SAT: full_tab is empty). The low 5 bits
+// are folded into two 32-bit tables over the position j of x inside an aligned
+// run of 32 states: zero_tab bit j says ((j ^ P) & M & 31) == 0, full_tab bit
+// j says it equals M & 31.
 struct ClauseRec {
     uint32_t mask_hi_lo, mask_hi_hi;  // M with bits 0..4 cleared (low / high word)
     uint32_t pat_lo, pat_hi;          // P

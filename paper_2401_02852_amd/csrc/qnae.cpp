@@ -69,6 +69,15 @@ int qnae_destroy(qnae_ctx* ctx) {
 
 int qnae_build_cost_diagonal(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k, void* cost_dev,
                              int32_t cost_dtype, uint64_t* num_solutions, void* stream) {
+    return qnae_build_cost_diagonal_pred(ctx, clauses, m, n, k, QNAE_PRED_NAE, cost_dev, cost_dtype, num_solutions,
+                                         stream);
+}
+
+int qnae_build_cost_diagonal_pred(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k,
+                                  int32_t predicate, void* cost_dev, int32_t cost_dtype, uint64_t* num_solutions,
+                                  void* stream) {
+    if (predicate != QNAE_PRED_NAE && predicate != QNAE_PRED_SAT)
+        return fail(QNAE_EINVAL, "predicate=%d is not QNAE_PRED_NAE/QNAE_PRED_SAT", predicate);
     if (int rc = check_cost_args(n, m, cost_dtype)) return rc;
     if (!cost_dev) return fail(QNAE_EINVAL, "null cost_dev");
     if (int rc = check_literals(clauses, m, n, k)) return rc;
@@ -77,7 +86,7 @@ int qnae_build_cost_diagonal(qnae_ctx* ctx, const int32_t* clauses, int32_t m, i
 
     HIP_TRY(ctx->h_clauses.reserve(sizeof(ClauseRec) * (size_t)(m > 0 ? m : 1)));
     ClauseRec* recs = (ClauseRec*)ctx->h_clauses.ptr;
-    const int nrec = make_clause_records(clauses, m, k, recs);
+    const int nrec = make_clause_records(clauses, m, k, recs, predicate);
     HIP_TRY(ctx->clauses.reserve(sizeof(ClauseRec) * (size_t)(nrec > 0 ? nrec : 1)));
     if (nrec > 0)
         HIP_TRY(hipMemcpyAsync(ctx->clauses.ptr, recs, sizeof(ClauseRec) * nrec, hipMemcpyHostToDevice, s));

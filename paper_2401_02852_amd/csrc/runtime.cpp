@@ -171,7 +171,10 @@ int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k) {
     return QNAE_OK;
 }
 
-int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* recs) {
+// Clause records for the cost kernel; clauses that can never be violated (a
+// variable with both signs: one literal is always true and one false) are
+// dropped. k-SAT clauses only get the all-false table (Section 2.2).
+int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* recs, int predicate) {
     int nrec = 0;
     for (int i = 0; i < m; ++i) {
         uint64_t mask = 0, pat = 0;
@@ -200,7 +203,7 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
         for (uint32_t j = 0; j < 32; ++j) {
             const uint32_t y = (j ^ lp) & lm;
             if (y == 0u) r.zero_tab |= 1u << j;
-            if (y == lm) r.full_tab |= 1u << j;
+            if (y == lm && predicate == QNAE_PRED_NAE) r.full_tab |= 1u << j;
         }
         recs[nrec++] = r;
     }

@@ -1,0 +1,96 @@
+"""k-SAT clause predicate (Section 2.2: an OR-clause is violated iff every
+literal is false) on the GPU: cost diagonals bit-exact against the oracle,
+and QAOA on costs without the global-flip symmetry against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_02852_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2401_02852_amd as q
+    q.load_library()
+    return q
+
+
+@pytest.mark.parametrize("n,k,m", [(1, 1, 3), (3, 2, 5), (5, 3, 9), (9, 1, 12), (12, 3, 40), (17, 5, 90),
+                                   (20, 4, 200), (14, 3, 300)])
+def test_sat_cost_bit_exact(q, n, k, m):
+    cl = inst.instance(n, k, m, 7 * n + k).reshape(m, k)
+    c, sols = q.build_cost_diagonal(cl, n, count_solutions=True, predicate="sat")
+    ref = oracle.cost(cl, n, "sat")
+    assert np.array_equal(c.cpu().numpy().astype(np.int64), ref)
+    assert sols == int((ref == 0).sum())
+
+
+def test_sat_cost_repeated_variables(q):
+    cl = np.array([[1, -1, 2], [3, 3, -4], [2, 4, 4], [5, 6, 7], [-8, -8, -8]], dtype=np.int32)
+    c = q.build_cost_diagonal(cl, 8, predicate="sat")
+    assert np.array_equal(c.cpu().numpy().astype(np.int64), oracle.cost(cl, 8, "sat"))
+
+
+@pytest.mark.parametrize("n", [30, 33])
+def test_sat_cost_full_size_sampled(q, n):
+    """Sampled states (and the top of the index range) against the oracle;
+    sum_x C = m 2^(n-k) over the whole diagonal."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < (1 << n) + (1 << 30):
+        pytest.skip("not enough device memory")
+    k, m = 3, 63
+    cl = inst.instance(n, k, m, 3)
+    c = q.build_cost_diagonal(cl, n, predicate="sat")
+    rng = np.random.default_rng(n)
+    xs = np.concatenate([rng.integers(0, 1 << n, 4000, dtype=np.uint64),
+                         np.arange((1 << n) - 64, 1 << n, dtype=np.uint64)])
+    got = c[torch.from_numpy(xs.astype(np.int64)).cuda()].cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, oracle.cost_at(cl, n, xs, "sat"))
+    total = int(c.view(-1, 1 << 20).sum(dim=1, dtype=torch.int64).sum().item())
+    assert total == m * 2 ** (n - k)
+    del c
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [6, 13, 16, 21])
+@pytest.mark.parametrize("p", [1, 2, 5])
+def test_sat_qaoa_matches_oracle(q, n, p):
+    """Angles in (0, pi) make both butterfly forms occur, so the flipped
+    layout reads the cost at complemented indices: with a cost that is not
+    symmetric under the flip, any slip there changes the result."""
+    m = 4 * n
+    cl = inst.instance(n, 3, m, 11 * n + p)
+    rng = np.random.default_rng(n + p)
+    g, b = rng.uniform(0, np.pi, p), rng.uniform(0, np.pi, p)
+    c = q.build_cost_diagonal(cl, n, predicate="sat")
+    got = q.qaoa_run(c, n, m, g, b)
+    ref = oracle.qaoa(oracle.cost(cl, n, "sat"), n, g, b)
+    assert abs(got.p_success - ref[0]) <= 1e-5
+    assert abs(got.expected_cost - ref[1]) <= 1e-5 * ref[1]
+    assert abs(got.norm - 1) <= 1e-5
+    import torch
+    st = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    q.qaoa_run(c, n, m, g, b, state=st)
+    psi = oracle.state(oracle.cost(cl, n, "sat"), n, g, b)
+    assert np.max(np.abs(st.cpu().numpy() - psi)) <= 1e-5
+
+
+def test_sat_batched_mixed_predicates(q):
+    rng = np.random.default_rng(4)
+    jobs = []
+    for i in range(24):
+        n = int(rng.integers(3, 19))
+        k = int(rng.integers(1, min(n, 5) + 1))
+        m = int(rng.integers(0, 5 * n))
+        jobs.append((inst.instance(n, k, m, 400 + i).reshape(m, k), n, "sat" if i % 2 else "nae"))
+    costs, sols = q.build_cost_diagonals([j[0] for j in jobs], [j[1] for j in jobs], count_solutions=True,
+                                         predicate=[j[2] for j in jobs])
+    for (cl, n, pred), c, s in zip(jobs, costs, sols):
+        ref = oracle.cost(cl, n, pred)
+        assert np.array_equal(c.cpu().numpy().astype(np.int64), ref), (n, pred)
+        assert s == int((ref == 0).sum())

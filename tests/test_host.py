@@ -130,6 +130,15 @@ def test_binding_marshalling_without_gpu():
         b.qaoa_run(costs[0], 8, 10, [0.1], [0.2], ctx=_NullCtx(), stream=0)
     with pytest.raises(b.QNAEError, match="literal"):
         b.build_cost_diagonal(np.array([[1, 99]], dtype=np.int32), 8, out=costs[0], ctx=_NullCtx(), stream=0)
+    with pytest.raises(b.QNAEError, match="null context"):
+        b.build_cost_diagonal(cl, 8, out=costs[0], predicate="sat", ctx=_NullCtx(), stream=0)
+    with pytest.raises(b.QNAEError, match="null context"):
+        b.build_cost_diagonals([cl, cl], [8, 9], outs=costs, predicate=["sat", "nae"], ctx=_NullCtx(), stream=0)
+    with pytest.raises(ValueError, match="predicate"):
+        b.build_cost_diagonal(cl, 8, out=costs[0], predicate="xor", ctx=_NullCtx(), stream=0)
+    lib = b.load_library()
+    assert lib.qnae_build_cost_diagonal_pred(None, None, 0, 5, 3, 7, None, 1, None, None) == -1
+    assert b"predicate=7" in lib.qnae_last_error(None)
 
 
 def test_server_binding_without_gpu():
