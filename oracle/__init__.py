@@ -57,10 +57,11 @@ def _load():
                                         ctypes.c_int64, _I32P]
     lib.oracle_count_solutions_pred.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, ctypes.c_int,
                                                 _U64P]
+    lib.oracle_sample.argtypes = [ctypes.c_int, _F64P, _F64P, ctypes.c_int64, _U64P]
     lib.oracle_num_threads.argtypes = []
     for fn in (lib.oracle_cost, lib.oracle_cost_at, lib.oracle_count_solutions, lib.oracle_state,
                lib.oracle_qaoa, lib.oracle_qaoa_grad, lib.oracle_num_threads, lib.oracle_cost_pred,
-               lib.oracle_cost_at_pred, lib.oracle_count_solutions_pred):
+               lib.oracle_cost_at_pred, lib.oracle_count_solutions_pred, lib.oracle_sample):
         fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -143,6 +144,29 @@ def state(cost_arr, n: int, gammas, betas) -> np.ndarray:
     if rc:
         raise ValueError("oracle_state: invalid arguments")
     return psi.view(np.complex128)
+
+
+def sample(psi, n: int, uniforms) -> np.ndarray:
+    """Bitstrings drawn from |psi|^2 / norm by the inverse cumulative
+    distribution in index order, one per uniform in [0, 1) (uint64)."""
+    st = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    if st.shape != (1 << n,):
+        raise ValueError("psi must have 2^n entries")
+    u, up = _f64(np.atleast_1d(np.asarray(uniforms, dtype=np.float64)))
+    out = np.empty(u.shape[0], dtype=np.uint64)
+    rc = _load().oracle_sample(n, st.view(np.float64).ctypes.data_as(_F64P), up, u.shape[0],
+                               out.ctypes.data_as(_U64P))
+    if rc:
+        raise ValueError("oracle_sample: invalid arguments (uniforms must lie in [0, 1))")
+    return out
+
+
+def running_time(samples, cost_arr) -> int:
+    """Instance running time (Section 4.2): the number of bitstrings drawn
+    until the first satisfying one (C = 0); 0 if none of them satisfies."""
+    c = np.asarray(cost_arr)[np.asarray(samples, dtype=np.int64)]
+    hit = np.flatnonzero(c == 0)
+    return int(hit[0]) + 1 if hit.size else 0
 
 
 def qaoa(cost_arr, n: int, gammas, betas):

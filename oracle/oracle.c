@@ -277,6 +277,43 @@ int oracle_qaoa(int n, const int32_t *cost, int p, const double *gammas,
 }
 
 /* ------------------------------------------------------------------ */
+/* Sampling bitstrings from the final state                           */
+/* ------------------------------------------------------------------ */
+
+/* Draws count bitstrings from |psi(x)|^2 / sum_y |psi(y)|^2 (the outcome
+ * distribution of measuring the final state, Section 4.2, instance running
+ * time) by inverting the cumulative distribution in index order: sample q
+ * is the smallest x whose cumulative mass exceeds u[q] times the total.
+ * The uniforms u[q] in [0, 1) are inputs. psi is interleaved (re, im). */
+int oracle_sample(int n, const double *psi, const double *u, int64_t count, uint64_t *out) {
+    if (n < 1 || n > 40 || psi == NULL || count < 0 || (count > 0 && (u == NULL || out == NULL))) return -1;
+    int64_t N = (int64_t)1 << n;
+    double *cum = (double *)malloc(sizeof(double) * (size_t)N);
+    if (cum == NULL) return -1;
+    double run = 0.0;
+    for (int64_t x = 0; x < N; x++) {
+        run += psi[2 * x] * psi[2 * x] + psi[2 * x + 1] * psi[2 * x + 1];
+        cum[x] = run;
+    }
+    for (int64_t q = 0; q < count; q++) {
+        if (!(u[q] >= 0.0 && u[q] < 1.0)) {
+            free(cum);
+            return -1;
+        }
+        double target = u[q] * run;
+        int64_t lo = 0, hi = N - 1; /* smallest x with cum[x] > target */
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (cum[mid] > target) hi = mid;
+            else lo = mid + 1;
+        }
+        out[q] = (uint64_t)lo;
+    }
+    free(cum);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Gradient by the adjoint method with stored states                  */
 /* ------------------------------------------------------------------ */
 

@@ -444,3 +444,76 @@ def test_gradient_matches_dense_finite_differences():
             return 0.3 * ps + en
         assert abs((F(g + e, b) - F(g - e, b)) / (2 * h) - dg[i]) < 1e-7
         assert abs((F(g, b + e) - F(g, b - e)) / (2 * h) - db[i]) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Sampling bitstrings from the final state (Section 4.2: instance running time)
+# ---------------------------------------------------------------------------
+
+def brute_sample(psi, u):
+    """Walk the outcomes in index order until the running mass passes u times
+    the total (plain Python)."""
+    probs = [abs(complex(a)) ** 2 for a in psi]
+    total = sum(probs)
+    out = []
+    for uu in u:
+        acc = 0.0
+        for x, pr in enumerate(probs):
+            acc += pr
+            if acc > uu * total:
+                out.append(x)
+                break
+    return out
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sample_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = 5
+    cl = rand_instance(n, 3, 8, seed)
+    psi = oracle.state(oracle.cost(cl, n), n, rng.uniform(0, 3, 2), rng.uniform(0, 3, 2))
+    u = rng.random(300)
+    assert list(oracle.sample(psi, n, u)) == brute_sample(psi, u)
+
+
+def test_sample_uniform_state_closed_form():
+    """|+> (p = 0): every outcome has mass 2^-n, so x = floor(u 2^n) away from
+    the cell boundaries."""
+    n = 16
+    psi = oracle.state(np.zeros(1 << n, dtype=np.int32), n, [], [])
+    rng = np.random.default_rng(1)
+    u = rng.random(5000)
+    frac = u * 2 ** n - np.floor(u * 2 ** n)
+    u = u[(frac > 1e-6) & (frac < 1 - 1e-6)]
+    assert np.array_equal(oracle.sample(psi, n, u), np.floor(u * 2 ** n).astype(np.uint64))
+
+
+def test_sample_skips_zero_mass_and_normalises():
+    psi = np.array([0, 0.6, 0, 0, 0.8j, 0, 0, 0], dtype=np.complex128) * 3.0  # norm 9
+    s = oracle.sample(psi, 3, [0.0, 0.3599, 0.3601, 0.999999])
+    assert list(s) == [1, 1, 4, 4]
+
+
+def test_sample_frequencies_and_running_time():
+    """Empirical frequencies match |psi|^2 (within 5 standard errors) and the
+    mean running time matches the geometric mean 1/p_succ."""
+    n, p = 6, 2
+    cl = rand_instance(n, 3, 10, 3)
+    c = oracle.cost(cl, n)
+    g, b = [0.7, 0.4], [-0.5, -0.3]
+    psi = oracle.state(c, n, g, b)
+    prob = np.abs(psi) ** 2
+    rng = np.random.default_rng(5)
+    S = 400_000
+    s = oracle.sample(psi, n, rng.random(S)).astype(np.int64)
+    freq = np.bincount(s, minlength=1 << n) / S
+    se = np.sqrt(prob * (1 - prob) / S)
+    assert np.all(np.abs(freq - prob) <= 5 * se + 1e-12)
+    ps = oracle.qaoa(c, n, g, b)[0]
+    hits = np.flatnonzero(c[s] == 0)
+    runs = np.diff(np.concatenate([[-1], hits]))  # i.i.d. running times
+    assert oracle.running_time(s, c) == runs[0]
+    assert oracle.running_time(s[hits[0] + 1:], c) == runs[1]
+    assert oracle.running_time(s[c[s] > 0], c) == 0
+    mean = np.mean(runs)
+    assert abs(mean - 1 / ps) <= 5 * np.sqrt((1 - ps) / ps ** 2 / len(runs)), (mean, 1 / ps)
