@@ -133,6 +133,61 @@ def batched_bench(q, ctx, reps=5, count=512):
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
 
 
+def sampling_bench(q, ctx, draws=100_000, ensemble=200):
+    """Drawing bitstrings from the final state (Section 4.2). (1) Draws from
+    the n = 30 workload's state (ramp with beta negated): draws/s and the
+    tile-mass pass over the 8 GiB state. (2) Running times over an ensemble of
+    satisfiable 3-NAE-SAT instances (n = 16, m = 34, p = 8, same ramp): median
+    running time against 1/mean(p_succ)."""
+    import numpy as np
+    import torch
+    from paper_2401_02852_amd import instances as inst
+    rec, cl, g, b = load_workload("nae3_n30_p10")
+    n, m = rec["n"], rec["m"]
+    cost = q.build_cost_diagonal(cl, n, ctx=ctx)
+    st = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    res = q.qaoa_run(cost, n, m, g, -b, state=st, ctx=ctx)
+    u = np.random.default_rng(0).random(draws)
+    q.sample(st, n, u[:1000], cost=cost, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, costs = q.sample(st, n, u, cost=cost, ctx=ctx)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    q.sample(st, n, [], ctx=ctx)  # the two prefix passes alone
+    dt0 = time.perf_counter() - t0
+    del st, cost
+    torch.cuda.empty_cache()
+    out = {"workload": f"n={n} m={m} p=10 (seed {rec['seed']}), ramp with beta negated; {draws} draws",
+           "draws_per_s": draws / dt, "ms": dt * 1e3, "prefix_pass_ms": dt0 * 1e3,
+           "prefix_pass_GBps": 8 * 2 ** n / dt0 / 1e9,
+           "share_satisfying": float((costs == 0).mean()), "p_success": res.p_success}
+    # ensemble running times
+    nn, pp = 16, 8
+    mm = inst.clause_count(nn, 2.1)
+    gg, bb = inst.ramp_angles(pp)
+    rng = np.random.default_rng(1)
+    runs, succ, seed = [], [], 0
+    st = torch.empty(1 << nn, dtype=torch.complex64, device="cuda")
+    t0 = time.perf_counter()
+    while len(runs) < ensemble:
+        c, sols = q.build_cost_diagonal(inst.instance(nn, 3, mm, seed), nn, count_solutions=True, ctx=ctx)
+        seed += 1
+        if sols == 0:
+            continue
+        r = q.qaoa_run(c, nn, mm, gg, -bb, state=st, ctx=ctx)
+        rt, drawn = 0, 0
+        while rt == 0 and drawn < 1 << 22:
+            _, sc = q.sample(st, nn, rng.random(4096), cost=c, ctx=ctx)
+            rt = q.running_time(sc)
+            rt, drawn = (drawn + rt, drawn) if rt else (0, drawn + 4096)
+        runs.append(rt)
+        succ.append(r.p_success)
+    out["ensemble"] = {"instances": ensemble, "n": nn, "m": mm, "p": pp, "median_running_time": float(np.median(runs)),
+                       "inverse_mean_p_success": 1.0 / float(np.mean(succ)), "seconds": time.perf_counter() - t0}
+    return out
+
+
 def grad_bench(q, ctx, reps=10, adam_steps=200):
     """Differentiation workload: n = 22, m = 46, p = 12 from the linear ramp
     (beta negated), checkpoints every 4 layers. Time of one adjoint gradient
@@ -266,6 +321,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -351,6 +407,8 @@ def main():
         out["batched"] = batched_bench(q, ctx)
     if not args.no_grad:
         out["gradient"] = grad_bench(q, ctx)
+    if not args.no_sampling:
+        out["sampling"] = sampling_bench(q, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(q, ctx, count=args.serving_requests)
     if not args.no_cpu_baseline:

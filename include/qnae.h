@@ -241,6 +241,28 @@ int qnae_server_stats(qnae_server *server, uint64_t *completed, uint64_t *ticks,
  * pool. Results not yet collected are lost. NULL is a no-op. */
 int qnae_server_destroy(qnae_server *server);
 
+/* Draws `count` bitstrings from the outcome distribution |psi(x)|^2 / norm of
+ * a state, as measuring the final QAOA state does (Section 4.2: the instance
+ * running time is the number of draws until one satisfies the instance). The
+ * draw for uniforms[q] is the smallest x whose cumulative mass, in index
+ * order, exceeds uniforms[q] times the total: FP32 |psi|^2 summed in FP64
+ * per tile of 4096 amplitudes, prefix sums over tiles; a uniform within about
+ * 1e-7 of a cumulative boundary may therefore land on the neighbouring
+ * outcome.
+ *
+ *   state_dev     device complex64[2^n], 16-byte aligned, e.g. the state
+ *                 kept by qnae_qaoa_run
+ *   cost_dev      optional device cost diagonal (cost_dtype QNAE_U8/U16);
+ *                 with it, sample_costs[q] = C(samples[q])
+ *   uniforms      host, count doubles in [0, 1) (the caller's random numbers)
+ *   samples       host, count outcomes; sample_costs host or NULL
+ *   count         0 <= count <= 2^24
+ *
+ * Synchronous. Errors: QNAE_EINVAL (bad n, count, pointer, cost_dtype, a
+ * uniform outside [0, 1), or a state of zero norm), QNAE_ENOMEM, QNAE_EHIP. */
+int qnae_sample(qnae_ctx *ctx, const void *state_dev, int32_t n, const void *cost_dev, int32_t cost_dtype,
+                const double *uniforms, int32_t count, uint64_t *samples, int32_t *sample_costs, void *stream);
+
 /* Tile shape of the sweep path (qnae_qaoa_run for n > 14). The mixer of one
  * layer is n butterfly passes over the state (appendix A.4); the library
  * fuses them into sweeps, each applying the passes of a group of index bits

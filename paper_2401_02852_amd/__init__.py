@@ -20,5 +20,7 @@ from ._binding import (  # noqa: F401
     qaoa_grad,
     qaoa_run,
     qaoa_run_batched,
+    running_time,
+    sample,
 )
 from .autograd import QAOAFunction  # noqa: F401

@@ -99,6 +99,8 @@ def load_library():
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _F64P, _F64P,
                                        ctypes.POINTER(_CResult), vp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.qnae_sample.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, _F64P, ctypes.c_int32, u64p, _I32P,
+                                    vp]
         tp = ctypes.POINTER(_CTune)
         lib.qnae_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, tp, vp]
         lib.qnae_set_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, tp]
@@ -115,7 +117,7 @@ def load_library():
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
-                   lib.qnae_set_tune, lib.qnae_get_tune):
+                   lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -372,6 +374,40 @@ def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_en
         dg.ctypes.data_as(_F64P) if p else None, db.ctypes.data_as(_F64P) if p else None,
         ctypes.byref(res), _stream(stream)))
     return dg, db, Result(res.p_success, res.expected_cost, res.norm)
+
+
+def sample(state, n: int, uniforms, *, cost=None, ctx: Optional[Context] = None, stream=None):
+    """Outcomes of measuring `state` (complex64, 2^n, on the device), one per
+    uniform in [0, 1): the smallest x whose cumulative |psi|^2 mass in index
+    order exceeds u times the total. Returns (samples uint64, costs int32 or
+    None); costs are C(sample) when the cost diagonal is given."""
+    import torch
+    if state.dtype != torch.complex64 or state.numel() != (1 << n):
+        raise ValueError("state must be complex64 with 2^n entries")
+    u = np.ascontiguousarray(np.atleast_1d(np.asarray(uniforms, dtype=np.float64)))
+    count = u.shape[0]
+    out = np.zeros(count, dtype=np.uint64)
+    costs = np.zeros(count, dtype=np.int32) if cost is not None else None
+    code = 0
+    if cost is not None:
+        if cost.numel() != (1 << n):
+            raise ValueError(f"cost has {cost.numel()} entries, expected 2^{n}")
+        code = QNAE_U8 if cost.dtype == torch.uint8 else QNAE_U16
+    ctx = ctx or default_context()
+    _check(load_library().qnae_sample(
+        ctx.handle, ctypes.c_void_p(state.data_ptr()), n,
+        ctypes.c_void_p(cost.data_ptr()) if cost is not None else None, code,
+        u.ctypes.data_as(_F64P) if count else None, count,
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if count else None,
+        costs.ctypes.data_as(_I32P) if costs is not None and count else None, _stream(stream)))
+    return out, costs
+
+
+def running_time(sample_costs) -> int:
+    """Instance running time (Section 4.2): draws until the first satisfying
+    one (cost 0), counting it; 0 when none of the draws satisfies."""
+    hit = np.flatnonzero(np.asarray(sample_costs) == 0)
+    return int(hit[0]) + 1 if hit.size else 0
 
 
 class Server:

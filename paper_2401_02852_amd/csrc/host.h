@@ -97,6 +97,9 @@ struct qnae_ctx {
     // sweep tile shapes chosen per (n, cost type), by qnae_autotune or qnae_set_tune
     std::map<std::pair<int, int>, qnae_tune> tunes;
     qnae_host::DevBuf tune_cost;
+    // sampling: tile masses and prefix sums, uniforms and outcomes
+    qnae_host::DevBuf s_dev;
+    qnae_host::HostBuf h_sample;
     int tile_bits = 13;                 // tile size of the plain sweeps (log2 amplitudes)
     int min_low_run = 4;                // minimum contiguous low run (log2 amplitudes)
     int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes

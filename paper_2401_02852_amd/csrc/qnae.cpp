@@ -51,9 +51,10 @@ int qnae_destroy(qnae_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->state, &ctx->partials, &ctx->luts, &ctx->clauses, &ctx->forms, &ctx->small, &ctx->b_blob,
                       &ctx->b_states, &ctx->b_partials, &ctx->b_results, &ctx->g_states, &ctx->g_blob,
-                      &ctx->g_partials, &ctx->tune_cost})
+                      &ctx->g_partials, &ctx->tune_cost, &ctx->s_dev})
         b->release();
-    for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results})
+    for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results,
+                       &ctx->h_sample})
         b->release();
     if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);

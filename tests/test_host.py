@@ -160,3 +160,17 @@ def test_tune_binding_without_gpu():
     assert b"reps=0" in lib.qnae_last_error(None)
     assert lib.qnae_autotune(None, 40, 1, 1, ctypes.byref(t), None) == -1
     assert b"n=40" in lib.qnae_last_error(None)
+
+
+def test_sample_validation_without_gpu():
+    b = _lib_or_skip()
+    lib = b.load_library()
+    u = (ctypes.c_double * 2)(0.5, 1.0)
+    out = (ctypes.c_uint64 * 2)()
+    assert lib.qnae_sample(None, ctypes.c_void_p(0x1000), 10, None, 0, u, 2, out, None, None) == -1
+    assert b"uniforms[1]=1" in lib.qnae_last_error(None)
+    assert lib.qnae_sample(None, ctypes.c_void_p(0x1008), 10, None, 0, u, 1, out, None, None) == -1
+    assert b"aligned" in lib.qnae_last_error(None)
+    assert lib.qnae_sample(None, ctypes.c_void_p(0x1000), 10, None, 0, u, 1, out, None, None) == -1
+    assert b"null context" in lib.qnae_last_error(None)
+    assert b.running_time([3, 2, 0, 1, 0]) == 3 and b.running_time([1, 1]) == 0
