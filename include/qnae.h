@@ -241,6 +241,28 @@ int qnae_server_stats(qnae_server *server, uint64_t *completed, uint64_t *ticks,
  * pool. Results not yet collected are lost. NULL is a no-op. */
 int qnae_server_destroy(qnae_server *server);
 
+/* Half-state simulation for NAE instances. The NAE cost is symmetric under
+ * flipping every variable (Section 2.2), and |+>, the phase and the mixer
+ * commute with that flip, so psi(x) = psi(NOT x) at every layer: the state
+ * and the cost diagonal are kept for x < 2^(n-1) only (the lower half), and
+ * the mixer factor of variable n-1 pairs a stored index y with 2^(n-1)-1-y.
+ * Half the memory and half the bytes per layer of qnae_qaoa_run.
+ *
+ * qnae_build_cost_diagonal_z2: as qnae_build_cost_diagonal (NAE predicate)
+ * for x in [0, 2^(n-1)); cost_dev holds 2^(n-1) elements; *num_solutions,
+ * if requested, counts the whole diagonal (twice the lower half). n >= 2.
+ *
+ * qnae_qaoa_run_z2: as qnae_qaoa_run on such a half diagonal; 15 <= n <=
+ * QNAE_MAX_N (smaller n run whole in one workgroup: use qnae_qaoa_run).
+ * state_dev, if not NULL, receives psi(x) for x < 2^(n-1) (2^(n-1)
+ * complex64); the upper half is psi(x) = psi(2^n - 1 - x). Results equal
+ * qnae_qaoa_run's within FP32 rounding. Errors as qnae_qaoa_run. */
+int qnae_build_cost_diagonal_z2(qnae_ctx *ctx, const int32_t *clauses, int32_t m, int32_t n, int32_t k,
+                                void *cost_dev, int32_t cost_dtype, uint64_t *num_solutions, void *stream);
+int qnae_qaoa_run_z2(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
+                     const double *gammas, const double *betas, int32_t p, void *state_dev, qnae_result *out,
+                     void *stream);
+
 /* Draws `count` bitstrings from the outcome distribution |psi(x)|^2 / norm of
  * a state, as measuring the final QAOA state does (Section 4.2: the instance
  * running time is the number of draws until one satisfies the instance). The

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     Result,
     Server,
     build_cost_diagonal,
+    build_cost_diagonal_z2,
     build_cost_diagonals,
     default_context,
     library_path,
@@ -20,6 +21,7 @@ from ._binding import (  # noqa: F401
     qaoa_grad,
     qaoa_run,
     qaoa_run_batched,
+    qaoa_run_z2,
     running_time,
     sample,
 )

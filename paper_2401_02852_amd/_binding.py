@@ -99,6 +99,10 @@ def load_library():
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _F64P, _F64P,
                                        ctypes.POINTER(_CResult), vp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.qnae_build_cost_diagonal_z2.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                                    ctypes.c_int32, u64p, vp]
+        lib.qnae_qaoa_run_z2.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
+                                         ctypes.c_int32, vp, ctypes.POINTER(_CResult), vp]
         lib.qnae_sample.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, _F64P, ctypes.c_int32, u64p, _I32P,
                                     vp]
         tp = ctypes.POINTER(_CTune)
@@ -117,7 +121,8 @@ def load_library():
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
-                   lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample):
+                   lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample, lib.qnae_build_cost_diagonal_z2,
+                   lib.qnae_qaoa_run_z2):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -374,6 +379,53 @@ def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_en
         dg.ctypes.data_as(_F64P) if p else None, db.ctypes.data_as(_F64P) if p else None,
         ctypes.byref(res), _stream(stream)))
     return dg, db, Result(res.p_success, res.expected_cost, res.norm)
+
+
+def build_cost_diagonal_z2(clauses, n: int, *, out=None, count_solutions: bool = False,
+                           ctx: Optional[Context] = None, stream=None):
+    """Lower half (x < 2^(n-1)) of the NAE cost diagonal, for qaoa_run_z2;
+    with count_solutions also the solution count of the whole diagonal."""
+    import torch
+    cl = np.ascontiguousarray(np.asarray(clauses, dtype=np.int32))
+    if cl.ndim != 2:
+        raise ValueError("clauses must be an [m, k] literal array")
+    m, k = cl.shape
+    if out is None:
+        out = torch.empty(1 << (n - 1), dtype=cost_dtype_for(m), device="cuda")
+    if out.numel() != (1 << (n - 1)):
+        raise ValueError(f"out has {out.numel()} entries, expected 2^{n - 1}")
+    code = QNAE_U8 if out.dtype == torch.uint8 else QNAE_U16
+    ctx = ctx or default_context()
+    sols = ctypes.c_uint64(0)
+    _check(load_library().qnae_build_cost_diagonal_z2(
+        ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1), ctypes.c_void_p(out.data_ptr()), code,
+        ctypes.byref(sols) if count_solutions else None, _stream(stream)))
+    return (out, int(sols.value)) if count_solutions else out
+
+
+def qaoa_run_z2(cost_half, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[Context] = None,
+                stream=None) -> Result:
+    """qaoa_run on the half-state representation (NAE instances, n >= 15):
+    ``cost_half`` from build_cost_diagonal_z2; ``state``, if given, receives
+    the lower half of the final state (2^(n-1) complex64)."""
+    import torch
+    g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
+    if g.shape != b.shape or g.ndim != 1:
+        raise ValueError("gammas and betas must be 1-D of equal length")
+    if cost_half.numel() != (1 << (n - 1)):
+        raise ValueError(f"cost has {cost_half.numel()} entries, expected 2^{n - 1}")
+    if state is not None and (state.dtype != torch.complex64 or state.numel() != (1 << (n - 1))):
+        raise ValueError("state must be complex64 with 2^(n-1) entries")
+    code = QNAE_U8 if cost_half.dtype == torch.uint8 else QNAE_U16
+    ctx = ctx or default_context()
+    res = _CResult()
+    p = g.shape[0]
+    _check(load_library().qnae_qaoa_run_z2(
+        ctx.handle, ctypes.c_void_p(cost_half.data_ptr()), code, n, m,
+        g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
+        ctypes.c_void_p(state.data_ptr()) if state is not None else None, ctypes.byref(res), _stream(stream)))
+    return Result(res.p_success, res.expected_cost, res.norm)
 
 
 def sample(state, n: int, uniforms, *, cost=None, ctx: Optional[Context] = None, stream=None):

@@ -126,10 +126,10 @@ __global__ __launch_bounds__(256) void cost_batch_kernel(const CostArgs* args, c
 }
 
 template <int NP, bool U16>
-hipError_t launch_np(const CostArgs& a, hipStream_t s) {
+hipError_t launch_np(const CostArgs& a, bool wide, hipStream_t s) {
     const uint64_t nthreads = a.n >= 5 ? (1ull << (a.n - 5)) : 1ull;
     const uint64_t blocks = (nthreads + 255) / 256;
-    if (a.n > 32)
+    if (wide)
         hipLaunchKernelGGL((cost_kernel<NP, true, U16>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((cost_kernel<NP, false, U16>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
@@ -138,15 +138,15 @@ hipError_t launch_np(const CostArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_cost(const CostArgs& a, int dtype, hipStream_t s) {
+hipError_t launch_cost(const CostArgs& a, int dtype, bool wide, hipStream_t s) {
     // Enough planes to count up to the number of (normalised) clauses.
     const int need = 32 - __builtin_clz((unsigned)a.num_clauses | 1u);
     if (dtype == 1) {
-        if (need <= 6) return launch_np<6, false>(a, s);
-        return launch_np<8, false>(a, s);
+        if (need <= 6) return launch_np<6, false>(a, wide, s);
+        return launch_np<8, false>(a, wide, s);
     }
-    if (need <= 12) return launch_np<12, true>(a, s);
-    return launch_np<16, true>(a, s);
+    if (need <= 12) return launch_np<12, true>(a, wide, s);
+    return launch_np<16, true>(a, wide, s);
 }
 
 hipError_t launch_cost_batch(const CostArgs* args, const uint32_t* first, int count, uint32_t blocks, int dtype,

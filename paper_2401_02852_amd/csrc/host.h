@@ -163,6 +163,7 @@ std::vector<Op> make_plan(int ngroups, int p, bool from_state = false);
 struct SweepPlan {
     int n = 0, m = 0, p = 0, TB = 13, dtype = QNAE_U8, lut_len = 1;
     bool keep = false;
+    bool half = false;  // state and cost over x < 2^(n-1) (NAE global-flip symmetry)
     std::vector<Group> groups;
     std::vector<Op> ops;
     std::vector<qnae::MixForm> forms;

@@ -32,7 +32,9 @@ struct CostArgs {
     unsigned long long* zeros;  // optional counter of states with cost 0
 };
 
-hipError_t launch_cost(const CostArgs& a, int dtype, hipStream_t s);
+// C(x) for x < 2^a.n. wide: clause variables reach index 32 or above
+// (64-bit pattern compares), required when any variable is >= 32.
+hipError_t launch_cost(const CostArgs& a, int dtype, bool wide, hipStream_t s);
 // Many diagonals of one cost type: instance i owns 256-thread blocks
 // first[i] .. first[i+1]-1 (32 states per thread). max_clauses bounds every
 // instance's clause count; wide when some instance has n > 32.
@@ -85,6 +87,15 @@ struct SweepArgs {
     float2 store_scale;    // readout kinds with store: final scalar factor
     int32_t store;         // readout kinds: also store the state
     int32_t cflip;         // read the cost at the complemented index
+    // Half-state sweeps (NAE global-flip symmetry): the state and cost hold
+    // only x < 2^(n-1); the amplitude of x with bit n-1 set is the one at
+    // its complement. With half set, tile bit vbit (pos[vbit] = n-1) is the
+    // virtual bit: flipping it maps a stored index y to mir - y, mir =
+    // 2^(n-1) - 1. Without a virtual bit (vbit < 0) a half sweep is a plain
+    // sweep over n-1 bits.
+    int32_t half;
+    int32_t vbit;
+    uint64_t mir;
 };
 
 hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s);

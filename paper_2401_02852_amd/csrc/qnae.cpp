@@ -74,9 +74,14 @@ int qnae_build_cost_diagonal(qnae_ctx* ctx, const int32_t* clauses, int32_t m, i
                                          stream);
 }
 
-int qnae_build_cost_diagonal_pred(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k,
-                                  int32_t predicate, void* cost_dev, int32_t cost_dtype, uint64_t* num_solutions,
-                                  void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Cost diagonal over x < 2^(n - half) (half: the lower half of the NAE
+// diagonal, which the global-flip symmetry mirrors onto the upper half).
+int build_cost(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k, int32_t predicate,
+               void* cost_dev, int32_t cost_dtype, uint64_t* num_solutions, void* stream, bool half) {
     if (predicate != QNAE_PRED_NAE && predicate != QNAE_PRED_SAT)
         return fail(QNAE_EINVAL, "predicate=%d is not QNAE_PRED_NAE/QNAE_PRED_SAT", predicate);
     if (int rc = check_cost_args(n, m, cost_dtype)) return rc;
@@ -84,6 +89,7 @@ int qnae_build_cost_diagonal_pred(qnae_ctx* ctx, const int32_t* clauses, int32_t
     if (int rc = check_literals(clauses, m, n, k)) return rc;
     if (int rc = enter(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
+    const int states = half ? n - 1 : n;
 
     HIP_TRY(ctx->h_clauses.reserve(sizeof(ClauseRec) * (size_t)(m > 0 ? m : 1)));
     ClauseRec* recs = (ClauseRec*)ctx->h_clauses.ptr;
@@ -97,25 +103,48 @@ int qnae_build_cost_diagonal_pred(qnae_ctx* ctx, const int32_t* clauses, int32_t
     qnae::CostArgs a;
     a.clauses = (const ClauseRec*)ctx->clauses.ptr;
     a.num_clauses = nrec;
-    a.n = n;
+    a.n = states;
     a.cost = cost_dev;
     a.zeros = num_solutions ? zeros : nullptr;
-    const double cost_bytes = (double)(cost_dtype == QNAE_U8 ? 1 : 2) * std::ldexp(1.0, n);
-    HIP_TRY(timed(ctx, K_COST, cost_bytes, s, [&] { return qnae::launch_cost(a, cost_dtype, s); }));
+    const double cost_bytes = (double)(cost_dtype == QNAE_U8 ? 1 : 2) * std::ldexp(1.0, states);
+    HIP_TRY(timed(ctx, K_COST, cost_bytes, s, [&] { return qnae::launch_cost(a, cost_dtype, n > 32, s); }));
     HIP_TRY(hipEventRecord(ctx->staging_done, s));
     if (num_solutions) {
         HIP_TRY(hipMemcpyAsync(ctx->h_small.ptr, zeros, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        *num_solutions = *(unsigned long long*)ctx->h_small.ptr;
+        *num_solutions = *(unsigned long long*)ctx->h_small.ptr * (half ? 2ull : 1ull);
     }
     return QNAE_OK;
 }
 
-int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
-                  const double* gammas, const double* betas, int32_t p, void* state_dev, qnae_result* out,
-                  void* stream) {
+}  // namespace
+
+extern "C" {
+
+int qnae_build_cost_diagonal_pred(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k,
+                                  int32_t predicate, void* cost_dev, int32_t cost_dtype, uint64_t* num_solutions,
+                                  void* stream) {
+    return build_cost(ctx, clauses, m, n, k, predicate, cost_dev, cost_dtype, num_solutions, stream, false);
+}
+
+int qnae_build_cost_diagonal_z2(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k, void* cost_dev,
+                                int32_t cost_dtype, uint64_t* num_solutions, void* stream) {
+    if (n < 2) return fail(QNAE_EINVAL, "n=%d below 2 for a half diagonal", n);
+    return build_cost(ctx, clauses, m, n, k, QNAE_PRED_NAE, cost_dev, cost_dtype, num_solutions, stream, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Depth-p run from |+>. half: state and cost hold x < 2^(n-1) only (NAE
+// global-flip symmetry); the readout sums then count every amplitude twice.
+int run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m, const double* gammas,
+        const double* betas, int32_t p, void* state_dev, qnae_result* out, void* stream, bool half) {
     if (int rc = check_run_args(n, m, cost_dtype, cost_dev, gammas, betas, p)) return rc;
     if (!out) return fail(QNAE_EINVAL, "null result pointer");
+    if (half && n <= kResidentMaxN)
+        return fail(QNAE_EINVAL, "n=%d: half-state runs need n > %d (smaller n: qnae_qaoa_run)", n, kResidentMaxN);
     if (int rc = enter(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
     const bool keep = state_dev != nullptr;
@@ -127,7 +156,7 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
     float2* tables = (float2*)ctx->h_luts.ptr;
     MixForm* forms = (MixForm*)ctx->h_forms.ptr;
     const std::complex<double> final_scale = build_tables(n, m, gammas, betas, p, tables, forms);
-    const double readout_scale = std::norm(final_scale);
+    const double readout_scale = std::norm(final_scale) * (half ? 2.0 : 1.0);
     const float2 store_scale = make_float2((float)final_scale.real(), (float)final_scale.imag());
 
     HIP_TRY(ctx->luts.reserve(sizeof(float2) * (size_t)T * lut_len));
@@ -153,22 +182,25 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
     } else {
         const qnae_tune tune = tune_for(ctx, n, cost_dtype);
         const int TB = tune.tile_bits;
+        const int stored = half ? n - 1 : n;
         float2* psi = (float2*)state_dev;
         if (!psi) {
-            HIP_TRY(ctx->state.reserve(sizeof(float2) << n));
+            HIP_TRY(ctx->state.reserve(sizeof(float2) << stored));
             psi = (float2*)ctx->state.ptr;
         }
-        const int64_t blocks = 1ll << (n - TB);
+        const int64_t blocks = 1ll << (stored - TB);
         HIP_TRY(ctx->partials.reserve(sizeof(double) * 3 * (size_t)blocks));
         SweepPlan P;
         plan_sweeps(P, n, m, p, cost_dtype, TB, tune.low_run_bits, tune.page_bit, keep, forms, final_scale);
+        P.half = half;
         for (const Op& op : P.ops) {
             SweepArgs a;
             sweep_args(P, op, psi, cost_dev, (const float2*)ctx->luts.ptr, (double*)ctx->partials.ptr, &a);
             HIP_TRY(timed(ctx, op_profile_kind(op), op_bytes(P, op), s,
                           [&] { return qnae::launch_sweep(TB, cost_dtype, op.kind, a, s); }));
         }
-        if (keep && p > 0 && P.flips_before[p])
+        // a symmetric state equals its all-qubit flip: nothing to undo when half
+        if (keep && !half && p > 0 && P.flips_before[p])
             HIP_TRY(timed(ctx, K_FINAL, 16.0 * std::ldexp(1.0, n), s,
                           [&] { return qnae::launch_reverse(psi, 1ull << n, s); }));
         HIP_TRY(timed(ctx, K_REDUCE, 24.0 * blocks, s, [&] {
@@ -183,6 +215,22 @@ int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32
     out->expected_cost = r[1] * readout_scale;
     out->norm = r[2] * readout_scale;
     return QNAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
+                  const double* gammas, const double* betas, int32_t p, void* state_dev, qnae_result* out,
+                  void* stream) {
+    return run(ctx, cost_dev, cost_dtype, n, m, gammas, betas, p, state_dev, out, stream, false);
+}
+
+int qnae_qaoa_run_z2(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
+                     const double* gammas, const double* betas, int32_t p, void* state_dev, qnae_result* out,
+                     void* stream) {
+    return run(ctx, cost_dev, cost_dtype, n, m, gammas, betas, p, state_dev, out, stream, true);
 }
 
 int qnae_profile_enable(qnae_ctx* ctx, int on) {

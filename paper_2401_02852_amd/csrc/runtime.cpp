@@ -382,6 +382,30 @@ void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost,
     a->cflip = op.kind == qnae::SK_BOUNDARY ? P.flips_before[op.lut_layer]
                : op.kind == qnae::SK_FINAL  ? P.flips_before[P.p]
                                             : 0;
+    a->half = 0;
+    a->vbit = -1;
+    a->mir = 0;
+    if (P.half) {
+        // Stored indices are x < 2^(n-1); full index x with bit n-1 set lives
+        // at its complement. Bit n-1 of the plan becomes the virtual tile bit
+        // (its flip mirrors the stored index); the tile index then fills the
+        // stored bits outside the tile except the highest one, which the
+        // virtual bit's mirror already covers.
+        const uint64_t stored = (1ull << (P.n - 1)) - 1ull;
+        uint64_t unit = 0;
+        for (int i = 0; i < P.TB; ++i) {
+            if (g.pos[i] == P.n - 1) a->vbit = i;
+            else unit |= 1ull << g.pos[i];
+        }
+        uint64_t wm = stored & ~unit;
+        if (a->vbit >= 0) wm &= ~(1ull << (63 - __builtin_clzll(wm)));
+        a->half = 1;
+        a->wmask = wm;
+        a->tile_bits = unit;
+        a->nw = P.n - 1 - P.TB;
+        a->mir = stored;
+        a->cflip = 0;  // the stored state is flip-symmetric: flipped reads are the same
+    }
 }
 
 double op_bytes(const SweepPlan& P, const Op& op) {
@@ -394,7 +418,7 @@ double op_bytes(const SweepPlan& P, const Op& op) {
         case qnae::SK_FINAL: per_amp = 8.0 + cb + (P.keep ? 8.0 : 0.0); break;
         default: per_amp = cb + (P.keep ? 8.0 : 0.0);
     }
-    return per_amp * std::ldexp(1.0, P.n);
+    return per_amp * std::ldexp(1.0, P.half ? P.n - 1 : P.n);
 }
 
 int op_profile_kind(const Op& op) {

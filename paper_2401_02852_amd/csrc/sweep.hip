@@ -28,9 +28,19 @@ namespace {
 
 using namespace tile;
 
+// Global index of tile element e = (thread part te) | (slot part se) in a
+// half-state sweep with a virtual bit: the unit tile bits deposit additively
+// (fwd = base + unit bits of te), and when the virtual bit of e is set the
+// index is mirrored, mir - (fwd + unit bits of se). HALF = false: plain
+// additive addresses.
+struct HalfAddr {
+    uint64_t fwd, mir;
+    bool tp;  // virtual bit in the thread part
+};
+
 // One workgroup's work on tile t of one sweep. Readout kinds write the three
 // block sums to partial[0..2].
-template <int TB, typename CT, int KIND>
+template <int TB, typename CT, int KIND, bool HALF>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, double* partial) {
     constexpr int WB = TB - 11;
     constexpr int NT = 64 << WB;
@@ -56,9 +66,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     // additive (XOR-linear) over disjoint bit sets of e: an address splits
     // into a per-thread offset and a per-slot offset that is the same for
     // every lane (scalar registers).
+    // Half sweeps: the virtual bit contributes no unit offset (bitval 0); it
+    // selects the mirrored address instead.
+    const uint32_t vb = HALF ? (uint32_t)a.vbit : 0u;
     uint64_t bitval[TB];
 #pragma unroll
-    for (int i = 0; i < TB; ++i) bitval[i] = 1ull << a.pos[i];
+    for (int i = 0; i < TB; ++i) bitval[i] = (HALF && (uint32_t)i == vb) ? 0ull : 1ull << a.pos[i];
     auto scat = [&](uint32_t e) -> uint64_t {
         uint64_t x = 0;
 #pragma unroll
@@ -76,13 +89,39 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         if (w & 1ull) base |= m & (~m + 1ull);
         w >>= 1;
     }
+    auto vpar = [&](uint32_t e) -> bool { return HALF && ((e >> vb) & 1u); };
+    auto haddr = [&](uint32_t te) -> HalfAddr {
+        HalfAddr h;
+        h.fwd = base + scat(te);
+        h.mir = a.mir - h.fwd;
+        h.tp = vpar(te);
+        return h;
+    };
+    // index of element (te | se) for a thread's HalfAddr
+    auto hidx = [&](const HalfAddr& h, uint32_t se) -> uint64_t {
+        const uint64_t so = scat(se);
+        return (h.tp != vpar(se)) ? h.mir - so : h.fwd + so;
+    };
 
     // Cost values of the 32 amplitudes in layout L2, loaded first; packed 4
     // (uint8) or 2 (uint16) per register. With cflip the stored state is the
     // true one with every qubit flipped (see MixForm), so cost values are read
     // at the complemented index: complemented tile base, thread part and slot.
     uint32_t cvp[NC];
-    if (NEED_COST) {
+    if (NEED_COST && HALF) {
+        // symmetric cost: no complemented reads, mirrored indices instead
+        const HalfAddr h = haddr(L::t2(lane, wave));
+        const CT* const cp = (const CT*)a.cost;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            uint32_t wv = 0u;
+#pragma unroll
+            for (int q = 0; q < PK; ++q) wv |= (uint32_t)cp[hidx(h, L::s2(PK * i + q))] << (8 * sizeof(CT) * q);
+            cvp[i] = wv;
+        }
+        if (NEED_LUT && LUT_LDS)
+            for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
+    } else if (NEED_COST) {
         const bool cf = a.cflip != 0;
         const uint64_t cbase = cf ? base ^ ((((uint64_t)1 << a.n) - 1ull) ^ a.tile_bits) : base;
         const uint32_t ct = cf ? L::t2(lane, wave) ^ L::t2(63u, (1u << WB) - 1u) : L::t2(lane, wave);
@@ -110,6 +149,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         __syncthreads();  // phase table visible
 #pragma unroll
         for (int j = 0; j < 32; ++j) v[j] = lut(cval(j));
+    } else if (HALF) {
+        // pairs along tile bit 0 (x bit 0): a mirrored pair is stored in
+        // reverse order one slot lower
+        const HalfAddr h = haddr(L::t0(lane, wave));
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const uint32_t se = L::s0(2 * jj);
+            const bool neg = h.tp != vpar(se);
+            const uint64_t so = scat(se);
+            const float4 q = *(const float4*)(a.psi_in + (neg ? h.mir - so - 1ull : h.fwd + so));
+            v[2 * jj] = neg ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
+            v[2 * jj + 1] = neg ? make_float2(q.x, q.y) : make_float2(q.z, q.w);
+        }
     } else {
         const float2* const p0 = a.psi_in + base + scat(L::t0(lane, wave));
 #pragma unroll
@@ -155,6 +207,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         }
         from_lds<TB, 0>(lds, v, lane, wave);
         mix32(v, L::sm0(m), tt);
+        if (HALF) {
+            const HalfAddr h = haddr(L::t0(lane, wave));
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const uint32_t se = L::s0(2 * jj);
+                const bool neg = h.tp != vpar(se);
+                const uint64_t so = scat(se);
+                const float2 lo = neg ? v[2 * jj + 1] : v[2 * jj], hi = neg ? v[2 * jj] : v[2 * jj + 1];
+                *(float4*)(a.psi + (neg ? h.mir - so - 1ull : h.fwd + so)) = make_float4(lo.x, lo.y, hi.x, hi.y);
+            }
+            return;
+        }
         float2* const p0 = a.psi + base + scat(L::t0(lane, wave));
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj)
@@ -194,16 +258,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
 #pragma unroll
             for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], a.store_scale);
         }
-        float2* const p2 = a.psi + base + scat(L::t2(lane, wave));
+        if (HALF) {
+            const HalfAddr h = haddr(L::t2(lane, wave));
 #pragma unroll
-        for (int j = 0; j < 32; ++j) p2[scat(L::s2(j))] = v[j];
+            for (int j = 0; j < 32; ++j) a.psi[hidx(h, L::s2(j))] = v[j];
+        } else {
+            float2* const p2 = a.psi + base + scat(L::t2(lane, wave));
+#pragma unroll
+            for (int j = 0; j < 32; ++j) p2[scat(L::s2(j))] = v[j];
+        }
     }
 }
 
 // One sweep over one state: block b handles tile b.
-template <int TB, typename CT, int KIND>
+template <int TB, typename CT, int KIND, bool HALF = false>
 __global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs a) {
-    sweep_tile<TB, CT, KIND>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
+    sweep_tile<TB, CT, KIND, HALF>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
 }
 
 // Instance of work item b in a ragged batch: the largest i with first[i] <= b.
@@ -225,7 +295,7 @@ __global__ __launch_bounds__(64 << (TB - 11)) void sweep_batch_kernel(const Swee
     const int i = batch_item(first, count, blockIdx.x);
     const SweepArgs a = args[i];
     const uint32_t t = blockIdx.x - first[i];
-    sweep_tile<TB, CT, KIND>(a, t, a.partials + 3 * (size_t)t);
+    sweep_tile<TB, CT, KIND, false>(a, t, a.partials + 3 * (size_t)t);
 }
 
 // psi[x] <-> psi[N - 1 - x]: undoes an X on every qubit (N >= 4).
@@ -364,7 +434,10 @@ __global__ __launch_bounds__(1024) void final_reduce_batch_kernel(const double* 
 
 template <int TB, typename CT, int KIND>
 hipError_t launch_kind(const SweepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0, s, a);
+    if (a.half && a.vbit >= 0)
+        hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND, true>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND, false>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0, s, a);
     return hipGetLastError();
 }
 
