@@ -133,6 +133,41 @@ def batched_bench(q, ctx, reps=5, count=512):
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
 
 
+def z2_bench(q, ctx, steps=5):
+    """The headline workload on the half-state path (NAE global-flip
+    symmetry: state and cost for x < 2^(n-1)): the same step (half cost
+    diagonal + p layers + readout), amp-layer updates of the full 2^n state
+    per second, and the half sweeps' bandwidth."""
+    import torch
+    rec, cl, g, b = load_workload("nae3_n30_p10")
+    n, m, p = rec["n"], rec["m"], rec["p"]
+    cost = torch.empty(1 << (n - 1), dtype=torch.uint8, device="cuda")
+
+    def step():
+        q.build_cost_diagonal_z2(cl, n, out=cost, ctx=ctx)
+        return q.qaoa_run_z2(cost, n, m, g, b, ctx=ctx)
+
+    step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.profile(False)
+    stats = ctx.profile_read()
+    kinds = [k for k in stats if k.startswith("sweep_")]
+    ms = sum(stats[k][1] for k in kinds)
+    by = sum(stats[k][2] for k in kinds)
+    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"workload": f"nae3_n30_p10 on the half state (2^{n - 1} stored amplitudes)",
+            "amp_layer_updates_per_s": (2 ** n) * p * steps / dt, "ms_per_step": dt * 1e3 / steps,
+            "sweep_GBps": achieved, "sweep_frac_of_peak": achieved / HBM_PEAK_GBS,
+            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in stats.items()},
+            "result": {"p_success": res.p_success, "expected_cost": res.expected_cost, "norm": res.norm}}
+
+
 def sampling_bench(q, ctx, draws=100_000, ensemble=200):
     """Drawing bitstrings from the final state (Section 4.2). (1) Draws from
     the n = 30 workload's state (ramp with beta negated): draws/s and the
@@ -322,6 +357,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
+    ap.add_argument("--no-z2", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -407,6 +443,8 @@ def main():
         out["batched"] = batched_bench(q, ctx)
     if not args.no_grad:
         out["gradient"] = grad_bench(q, ctx)
+    if not args.no_z2:
+        out["z2_half_state"] = z2_bench(q, ctx)
     if not args.no_sampling:
         out["sampling"] = sampling_bench(q, ctx)
     if not args.no_serving:
