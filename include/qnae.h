@@ -241,6 +241,26 @@ int qnae_server_stats(qnae_server *server, uint64_t *completed, uint64_t *ticks,
  * pool. Results not yet collected are lost. NULL is a no-op. */
 int qnae_server_destroy(qnae_server *server);
 
+/* One gradient of a batch: the arguments of qnae_qaoa_grad for one instance. */
+typedef struct {
+    const void *cost_dev;  /* device, 2^n of cost_dtype, values in [0, m] */
+    int32_t cost_dtype, n, m, p;
+    const double *gammas;  /* host, p entries (layer 0 first) */
+    const double *betas;   /* host, p entries */
+    double *dgammas;       /* host output, p entries */
+    double *dbetas;        /* host output, p entries */
+} qnae_grad_job;
+
+/* Gradients of w_psucc p_succ + w_energy E[C] for `count` instances (same
+ * definition as qnae_qaoa_grad), e.g. the terms of the training objective
+ * (1/t) sum_i p_succ(sigma_i) over t instances (Section 3.3, fixed-angle
+ * pretraining). Instances with n <= 13 run together in one launch per cost
+ * type, one workgroup each; larger ones run one after another. out[i]
+ * receives instance i's readout. Synchronous. Errors: QNAE_EINVAL (names the
+ * job), QNAE_ENOMEM, QNAE_EHIP. */
+int qnae_qaoa_grad_batched(qnae_ctx *ctx, const qnae_grad_job *jobs, int32_t count, double w_psucc, double w_energy,
+                           int32_t checkpoint_every, qnae_result *out, void *stream);
+
 /* Half-state simulation for NAE instances. The NAE cost is symmetric under
  * flipping every variable (Section 2.2), and |+>, the phase and the mixer
  * commute with that flip, so psi(x) = psi(NOT x) at every layer: the state

@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     library_path,
     load_library,
     qaoa_grad,
+    qaoa_grad_batched,
     qaoa_run,
     qaoa_run_batched,
     qaoa_run_z2,

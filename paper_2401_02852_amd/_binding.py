@@ -47,6 +47,16 @@ class _CInstance(ctypes.Structure):
                 ("betas", ctypes.POINTER(ctypes.c_double)), ("state_dev", ctypes.c_void_p)]
 
 
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+class _CGradJob(ctypes.Structure):
+    _fields_ = [("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("gammas", _F64P), ("betas", _F64P),
+                ("dgammas", _F64P), ("dbetas", _F64P)]
+
+
 class _CTune(ctypes.Structure):
     _fields_ = [("tile_bits", ctypes.c_int32), ("low_run_bits", ctypes.c_int32), ("page_bit", ctypes.c_int32),
                 ("ms_per_layer", ctypes.c_double)]
@@ -59,8 +69,6 @@ class _CKernelStat(ctypes.Structure):
 
 _lib = None
 _lock = threading.Lock()
-_I32P = ctypes.POINTER(ctypes.c_int32)
-_F64P = ctypes.POINTER(ctypes.c_double)
 
 
 def library_path() -> str:
@@ -99,6 +107,8 @@ def load_library():
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _F64P, _F64P,
                                        ctypes.POINTER(_CResult), vp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.qnae_qaoa_grad_batched.argtypes = [vp, ctypes.POINTER(_CGradJob), ctypes.c_int32, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_CResult), vp]
         lib.qnae_build_cost_diagonal_z2.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                                     ctypes.c_int32, u64p, vp]
         lib.qnae_qaoa_run_z2.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
@@ -122,7 +132,7 @@ def load_library():
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
                    lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample, lib.qnae_build_cost_diagonal_z2,
-                   lib.qnae_qaoa_run_z2):
+                   lib.qnae_qaoa_run_z2, lib.qnae_qaoa_grad_batched):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -379,6 +389,41 @@ def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_en
         dg.ctypes.data_as(_F64P) if p else None, db.ctypes.data_as(_F64P) if p else None,
         ctypes.byref(res), _stream(stream)))
     return dg, db, Result(res.p_success, res.expected_cost, res.norm)
+
+
+def qaoa_grad_batched(costs, ns, ms, gammas, betas, *, w_psucc: float = 1.0, w_energy: float = 0.0,
+                      checkpoint_every: int = 4, ctx: Optional[Context] = None, stream=None):
+    """qaoa_grad for many instances; returns (dgammas list, dbetas list,
+    Result list). Instances with n <= 13 share one launch."""
+    import torch
+    count = len(costs)
+    if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
+        raise ValueError("argument lists differ in length")
+    jobs = (_CGradJob * count)()
+    keep, dgs, dbs = [], [], []
+    for i in range(count):
+        g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas[i], dtype=np.float64)))
+        b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas[i], dtype=np.float64)))
+        if g.shape != b.shape or g.ndim != 1:
+            raise ValueError(f"instance {i}: gammas and betas must be 1-D of equal length")
+        if costs[i].numel() != (1 << int(ns[i])):
+            raise ValueError(f"instance {i}: cost has {costs[i].numel()} entries, expected 2^{ns[i]}")
+        p = g.shape[0]
+        dg, db = np.zeros(p), np.zeros(p)
+        keep += [g, b]
+        dgs.append(dg)
+        dbs.append(db)
+        jobs[i].cost_dev = costs[i].data_ptr()
+        jobs[i].cost_dtype = QNAE_U8 if costs[i].dtype == torch.uint8 else QNAE_U16
+        jobs[i].n, jobs[i].m, jobs[i].p = int(ns[i]), int(ms[i]), p
+        if p:
+            jobs[i].gammas, jobs[i].betas = g.ctypes.data_as(_F64P), b.ctypes.data_as(_F64P)
+            jobs[i].dgammas, jobs[i].dbetas = dg.ctypes.data_as(_F64P), db.ctypes.data_as(_F64P)
+    res = (_CResult * max(count, 1))()
+    ctx = ctx or default_context()
+    _check(load_library().qnae_qaoa_grad_batched(ctx.handle, jobs, count, float(w_psucc), float(w_energy),
+                                                 int(checkpoint_every), res, _stream(stream)))
+    return dgs, dbs, [Result(r.p_success, r.expected_cost, r.norm) for r in res[:count]]
 
 
 def build_cost_diagonal_z2(clauses, n: int, *, out=None, count_solutions: bool = False,

@@ -266,7 +266,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 template <typename CT>
-__global__ __launch_bounds__(256) void resident_grad_kernel(const ResidentGradArgs a) {
+__device__ __forceinline__ void resident_grad_body(const ResidentGradArgs& a) {
     __shared__ float2 ls[1 << 13];
     __shared__ float2 ps[1 << 13];
     __shared__ double red[4];
@@ -345,6 +345,18 @@ __global__ __launch_bounds__(256) void resident_grad_kernel(const ResidentGradAr
     }
 }
 
+template <typename CT>
+__global__ __launch_bounds__(256) void resident_grad_kernel(const ResidentGradArgs a) {
+    resident_grad_body<CT>(a);
+}
+
+// Many small gradients, one workgroup each.
+template <typename CT>
+__global__ __launch_bounds__(256) void resident_grad_batch_kernel(const ResidentGradArgs* args) {
+    const ResidentGradArgs a = args[blockIdx.x];
+    resident_grad_body<CT>(a);
+}
+
 }  // namespace
 
 hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s) {
@@ -377,6 +389,14 @@ hipError_t launch_weight(int dtype, const void* cost, const float2* psi, float2*
     else
         hipLaunchKernelGGL(weight_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)cost, psi, lam, N,
                            (float)w_psucc, (float)w_energy);
+    return hipGetLastError();
+}
+
+hipError_t launch_resident_grad_batch(int dtype, const ResidentGradArgs* args, int count, hipStream_t s) {
+    if (dtype == 1)
+        hipLaunchKernelGGL(resident_grad_batch_kernel<uint8_t>, dim3((uint32_t)count), dim3(256), 0, s, args);
+    else
+        hipLaunchKernelGGL(resident_grad_batch_kernel<uint16_t>, dim3((uint32_t)count), dim3(256), 0, s, args);
     return hipGetLastError();
 }
 

@@ -236,4 +236,109 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     return QNAE_OK;
 }
 
+int qnae_qaoa_grad_batched(qnae_ctx* ctx, const qnae_grad_job* jobs, int32_t count, double w_psucc, double w_energy,
+                           int32_t checkpoint_every, qnae_result* out, void* stream) {
+    if (count < 0 || (count > 0 && (!jobs || !out))) return fail(QNAE_EINVAL, "bad job array (count=%d)", count);
+    if (checkpoint_every < 0) return fail(QNAE_EINVAL, "checkpoint_every=%d < 0", checkpoint_every);
+    if (!std::isfinite(w_psucc) || !std::isfinite(w_energy)) return fail(QNAE_EINVAL, "non-finite weights");
+    for (int i = 0; i < count; ++i) {
+        const qnae_grad_job& j = jobs[i];
+        int rc = check_run_args(j.n, j.m, j.cost_dtype, j.cost_dev, j.gammas, j.betas, j.p);
+        if (!rc && j.p > 0 && (!j.dgammas || !j.dbetas)) rc = fail(QNAE_EINVAL, "null gradient arrays");
+        if (rc) return fail(rc, "job %d: %s", i, std::string(last_error()).c_str());
+    }
+    if (count == 0) return QNAE_OK;
+    const int every = checkpoint_every > 0 ? checkpoint_every : 4;
+    if (int rc = enter(ctx)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // Small jobs: per job its tables and outputs in one blob, checkpoints in
+    // one device buffer, one launch per cost type.
+    Blob B, C;
+    std::vector<size_t> lut_at(count), cs_at(count), out_at(count), ck_at(count);
+    std::vector<int> small[2];
+    for (int i = 0; i < count; ++i) {
+        const qnae_grad_job& j = jobs[i];
+        if (j.n > 13) continue;
+        const int T = j.p > 0 ? j.p : 1;
+        lut_at[i] = B.take(sizeof(float2) * (size_t)T * (j.m + 1));
+        cs_at[i] = B.take(sizeof(float2) * (size_t)T);
+        out_at[i] = B.take(sizeof(double) * (3 + 2 * (size_t)j.p));
+        const int nck = j.p > 1 ? (j.p - 1) / every : 0;
+        ck_at[i] = C.take(sizeof(float2) * ((size_t)1 << j.n) * (size_t)(nck > 0 ? nck : 1));
+        small[j.cost_dtype == QNAE_U16 ? 1 : 0].push_back(i);
+    }
+    size_t args_at[2];
+    for (int g = 0; g < 2; ++g) args_at[g] = B.take(sizeof(qnae::ResidentGradArgs) * small[g].size());
+    if (!small[0].empty() || !small[1].empty()) {
+        HIP_TRY(ctx->h_blob.reserve(B.size));
+        HIP_TRY(ctx->g_blob.reserve(B.size));
+        HIP_TRY(ctx->g_states.reserve(C.size));
+        char* h = (char*)ctx->h_blob.ptr;
+        char* d = (char*)ctx->g_blob.ptr;
+        for (int g = 0; g < 2; ++g) {
+            qnae::ResidentGradArgs* args = (qnae::ResidentGradArgs*)(h + args_at[g]);
+            for (size_t q = 0; q < small[g].size(); ++q) {
+                const int i = small[g][q];
+                const qnae_grad_job& j = jobs[i];
+                const int lut_len = j.m + 1;
+                float2* lut = (float2*)(h + lut_at[i]);
+                float2* cs = (float2*)(h + cs_at[i]);
+                for (int l = 0; l < j.p; ++l) {
+                    for (int c = 0; c <= j.m; ++c)
+                        lut[(size_t)l * lut_len + c] =
+                            make_float2((float)std::cos(j.gammas[l] * c), (float)-std::sin(j.gammas[l] * c));
+                    cs[l] = make_float2((float)std::cos(j.betas[l]), (float)std::sin(j.betas[l]));
+                }
+                qnae::ResidentGradArgs& a = args[q];
+                a.cost = j.cost_dev;
+                a.luts = (const float2*)(d + lut_at[i]);
+                a.cs = (const float2*)(d + cs_at[i]);
+                a.ckpt = (float2*)((char*)ctx->g_states.ptr + ck_at[i]);
+                a.out = (double*)(d + out_at[i]);
+                a.w_psucc = w_psucc;
+                a.w_energy = w_energy;
+                a.n = j.n;
+                a.p = j.p;
+                a.lut_len = lut_len;
+                a.every = every;
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(d, h, B.size, hipMemcpyHostToDevice, s));
+        for (int g = 0; g < 2; ++g) {
+            if (small[g].empty()) continue;
+            double bytes = 0.0;
+            for (int i : small[g]) bytes += std::ldexp(3.0 * jobs[i].p, jobs[i].n);
+            HIP_TRY(timed(ctx, K_RESIDENT, bytes, s, [&] {
+                return qnae::launch_resident_grad_batch(g ? QNAE_U16 : QNAE_U8,
+                                                         (const qnae::ResidentGradArgs*)(d + args_at[g]),
+                                                         (int)small[g].size(), s);
+            }));
+        }
+        HIP_TRY(hipMemcpyAsync(h, d, args_at[0], hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(ctx->staging_done, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int g = 0; g < 2; ++g)
+            for (int i : small[g]) {
+                const qnae_grad_job& j = jobs[i];
+                const double* r = (const double*)(h + out_at[i]);
+                out[i].p_success = r[0];
+                out[i].expected_cost = r[1];
+                out[i].norm = r[2];
+                for (int l = 0; l < j.p; ++l) {
+                    j.dgammas[l] = r[3 + l];
+                    j.dbetas[l] = r[3 + j.p + l];
+                }
+            }
+    }
+    // Large jobs: the tiled adjoint, one after another.
+    for (int i = 0; i < count; ++i) {
+        const qnae_grad_job& j = jobs[i];
+        if (j.n <= 13) continue;
+        if (int rc = qnae_qaoa_grad(ctx, j.cost_dev, j.cost_dtype, j.n, j.m, j.gammas, j.betas, j.p, w_psucc, w_energy,
+                                    checkpoint_every, j.dgammas, j.dbetas, &out[i], stream))
+            return fail(rc, "job %d: %s", i, std::string(last_error()).c_str());
+    }
+    return QNAE_OK;
+}
+
 }  // extern "C"

@@ -173,6 +173,8 @@ struct ResidentGradArgs {
     int32_t n, p, lut_len, every;
 };
 hipError_t launch_resident_grad(int dtype, const ResidentGradArgs& a, hipStream_t s);
+// One workgroup per entry of args (count entries, all of one cost type).
+hipError_t launch_resident_grad_batch(int dtype, const ResidentGradArgs* args, int count, hipStream_t s);
 hipError_t launch_resident_batch(int dtype, const ResidentArgs* args, int count, hipStream_t s);
 
 // Sum of 3-double block partials into out[3], FP64.

@@ -62,8 +62,8 @@ def random_angles(p: int, rng: np.random.Generator):
 
 # ---------------------------------------------------------------------------
 # Fixed workloads. Each is seeded; the satisfiable-instance seeds for the
-# single-instance workloads are chosen once by ``oracle/select_seeds.py`` and
-# stored in ``tests/golden/workload_seeds.json``.
+# single-instance workloads are chosen once by ``oracle/make_golden.py`` and
+# stored in ``tests/golden/workloads.json``.
 # ---------------------------------------------------------------------------
 
 SINGLE_WORKLOADS = {

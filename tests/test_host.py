@@ -174,3 +174,15 @@ def test_sample_validation_without_gpu():
     assert lib.qnae_sample(None, ctypes.c_void_p(0x1000), 10, None, 0, u, 1, out, None, None) == -1
     assert b"null context" in lib.qnae_last_error(None)
     assert b.running_time([3, 2, 0, 1, 0]) == 3 and b.running_time([1, 1]) == 0
+
+
+def test_pretrain_host_logic():
+    from paper_2401_02852_amd import pretrain
+    assert abs(pretrain.r_hat(3) - 2.1760) < 1e-4 and abs(pretrain.r_hat(5) - 10.4938) < 1e-4
+    ns = np.arange(12, 20)
+    c, d = pretrain.fit_exponent(ns, 2.0 ** (-0.31 * ns + 1.7))
+    assert abs(c + 0.31) < 1e-12 and abs(d - 1.7) < 1e-10
+    ev = {n: {"mean_p_success": 2.0 ** (-0.2 * n), "median_running_time": 2.0 ** (0.25 * n)} for n in ns}
+    ex = pretrain.exponents(ev)
+    assert abs(ex["C_hat"] - 0.2) < 1e-12 and abs(ex["C_tilde"] - 0.25) < 1e-12
+    assert abs(ex["relative_error"] - 0.25) < 1e-10
