@@ -133,6 +133,30 @@ def batched_bench(q, ctx, reps=5, count=512):
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
 
 
+def pretrain_bench(q, ctx, ks=(3, 9), p=8, v=200):
+    """Fixed-angle pretraining (t = 100 instances of CNF(12, k, r_hat_k),
+    Adam lr 0.01, 100 epochs, start (0.01, 0.01)) and evaluation on
+    satisfiable ensembles (v per n): mean p_succ, median running time, and
+    the fitted exponents C_hat, C_tilde with their relative error."""
+    from paper_2401_02852_amd import pretrain
+    out = {}
+    for k in ks:
+        t0 = time.perf_counter()
+        tr = pretrain.pretrain(k, p, ctx=ctx)
+        t1 = time.perf_counter()
+        ns = list(range(12, 19 if k < 6 else 17))
+        ev = pretrain.evaluate(k, tr["gammas"], tr["betas"], ns, v=v, ctx=ctx)
+        t2 = time.perf_counter()
+        out[f"k{k}"] = {"p": p, "train_s": t1 - t0, "epochs_per_s": 100 / (t1 - t0),
+                        "train_objective": [tr["history"][0], tr["history"][-1]],
+                        "gammas": [round(x, 5) for x in tr["gammas"]], "betas": [round(x, 5) for x in tr["betas"]],
+                        "eval_s": t2 - t1, "ensemble": v,
+                        "mean_p_success": {n: ev[n]["mean_p_success"] for n in ns},
+                        "median_running_time": {n: ev[n]["median_running_time"] for n in ns},
+                        **pretrain.exponents(ev)}
+    return out
+
+
 def z2_bench(q, ctx, steps=5):
     """The headline workload on the half-state path (NAE global-flip
     symmetry: state and cost for x < 2^(n-1)): the same step (half cost
@@ -358,6 +382,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-z2", action="store_true")
+    ap.add_argument("--no-pretrain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -445,6 +470,8 @@ def main():
         out["gradient"] = grad_bench(q, ctx)
     if not args.no_z2:
         out["z2_half_state"] = z2_bench(q, ctx)
+    if not args.no_pretrain:
+        out["pretraining"] = pretrain_bench(q, ctx)
     if not args.no_sampling:
         out["sampling"] = sampling_bench(q, ctx)
     if not args.no_serving:

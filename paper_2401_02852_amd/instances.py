@@ -47,6 +47,21 @@ def poisson_instance(n: int, k: int, r: float, seed: int) -> np.ndarray:
     return random_clauses(n, k, m, rng)
 
 
+def cnf_instance(n: int, k: int, r: float, seed: int) -> np.ndarray:
+    """CNF(n, k, r) of Definition 3.1 drawn with whole-array operations (for
+    large ensembles): m ~ Poisson(r n); a clause's k distinct variables are
+    the first k of an independent uniform permutation of the n variables;
+    signs Bernoulli(1/2). Same distribution as poisson_instance, different
+    random stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = int(rng.poisson(r * n))
+    if not (1 <= k <= n):
+        raise ValueError(f"need 1 <= k <= n, got k={k}, n={n}")
+    v = rng.permuted(np.tile(np.arange(n, dtype=np.int32), (m, 1)), axis=1)[:, :k]
+    neg = rng.integers(0, 2, (m, k))
+    return np.where(neg == 1, -(v + 1), v + 1).astype(np.int32)
+
+
 def ramp_angles(p: int):
     """Linear ramp gamma_l = 0.5 l / p, beta_l = 0.5 (1 - l / p), l = 1 .. p."""
     l = np.arange(1, p + 1, dtype=np.float64)

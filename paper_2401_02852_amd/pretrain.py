@@ -34,15 +34,16 @@ def r_hat(k: int) -> float:
 
 def random_set(k: int, n: int, count: int, seed: int, satisfiable: bool = False,
                ctx: Optional[Context] = None) -> List[np.ndarray]:
-    """`count` instances of CNF(n, k, r_hat_k) (Poisson m), instance i from
-    PCG64(seed * 1_000_003 + j) for j = 0, 1, ...; with `satisfiable`, the
-    ones without an NAE solution (counted on the GPU) are skipped."""
+    """`count` instances of CNF(n, k, r_hat_k) (Poisson m, cnf_instance),
+    instance j from PCG64(seed * 1_000_003 + j) for j = 0, 1, ...; with
+    `satisfiable`, the ones without an NAE solution (counted on the GPU) are
+    skipped."""
     out: List[np.ndarray] = []
     j = 0
     r = r_hat(k)
     while len(out) < count:
         want = count - len(out)
-        batch = [inst.poisson_instance(n, k, r, seed * 1_000_003 + j + i) for i in range(want)]
+        batch = [inst.cnf_instance(n, k, r, seed * 1_000_003 + j + i) for i in range(want)]
         j += want
         if not satisfiable:
             out += batch

@@ -186,3 +186,21 @@ def test_pretrain_host_logic():
     ex = pretrain.exponents(ev)
     assert abs(ex["C_hat"] - 0.2) < 1e-12 and abs(ex["C_tilde"] - 0.25) < 1e-12
     assert abs(ex["relative_error"] - 0.25) < 1e-10
+
+
+def test_cnf_instance_recipe():
+    import time
+    t0 = time.perf_counter()
+    cls = [inst.cnf_instance(16, 9, 176.9, s) for s in range(20)]
+    assert time.perf_counter() - t0 < 2.0
+    ms = np.array([c.shape[0] for c in cls])
+    assert abs(ms.mean() - 176.9 * 16) < 4 * np.sqrt(176.9 * 16 / 20)
+    for c in cls:
+        assert c.dtype == np.int32 and c.shape[1] == 9
+        assert np.all(np.abs(c) >= 1) and np.all(np.abs(c) <= 16)
+        assert all(len(set(np.abs(row))) == 9 for row in c[:200])
+    allc = np.concatenate(cls)
+    assert 0.48 < float((allc < 0).mean()) < 0.52
+    counts = np.bincount(np.abs(allc).ravel(), minlength=17)[1:]
+    assert counts.min() > 0.9 * counts.mean()
+    assert np.array_equal(cls[3], inst.cnf_instance(16, 9, 176.9, 3))
