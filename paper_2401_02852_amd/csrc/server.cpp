@@ -129,7 +129,7 @@ struct qnae_server {
     int error = QNAE_OK;
     std::string error_msg;
     uint64_t completed = 0, ticks = 0, launches = 0;
-    double tick_bytes = 2e9;  // state traffic per tick, about 0.4 ms of HBM time
+    double tick_bytes = 8e9;  // state traffic per tick, about 1.5 ms of HBM time
     std::thread worker;
 
     // Footprint blocks of a request; false if it can never fit the pool.
