@@ -383,11 +383,16 @@ def main():
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-z2", action="store_true")
     ap.add_argument("--no-pretrain", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the n=30 step (no other legs, no CPU baseline, no autotuning): for profiling")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.headline_only:
+        for leg in ("cpu_baseline", "batched", "serving", "grad", "sampling", "z2", "pretrain", "autotune"):
+            setattr(args, "no_" + leg, True)
     if args.calibrate_copy:
         import torch
         src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")

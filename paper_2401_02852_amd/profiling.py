@@ -40,9 +40,10 @@ def kernel_source_hash() -> str:
 
 def short_name(name: str) -> str:
     name = re.sub(r"qnae::\(anonymous namespace\)::", "", name)
-    m = re.match(r"void sweep_kernel<(\d+), ([a-z ]+), (\d)>", name)
+    m = re.match(r"void sweep_kernel<(\d+), ([a-z ]+), (\d)(?:, (true|false))?>", name)
     if m:
-        return f"sweep_kernel<TB={m.group(1)},{m.group(2).replace('unsigned ', 'u')}> {KIND_NAMES[m.group(3)]}"
+        half = ",half" if m.group(4) == "true" else ""
+        return f"sweep_kernel<TB={m.group(1)},{m.group(2).replace('unsigned ', 'u')}{half}> {KIND_NAMES[m.group(3)]}"
     return name.split("(")[0].replace("void ", "")
 
 
