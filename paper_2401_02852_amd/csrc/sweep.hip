@@ -177,10 +177,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         mix32(v, L::sm0(m), tt);
         to_lds<TB, 0>(lds, v, lane, wave);
         if (L::sm1(m)) {
-            __syncthreads();
+            wave_lds_sync();  // L0 -> L1 stays inside the wave's quarter
             from_lds<TB, 1>(lds, v, lane, wave);
             mix32(v, L::sm1(m), tt);
-            __syncthreads();
+            wave_lds_sync();
             to_lds<TB, 1>(lds, v, lane, wave);
         }
         __syncthreads();
@@ -201,9 +201,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         if (L::sm1(m)) {
             from_lds<TB, 1>(lds, v, lane, wave);
             mix32(v, L::sm1(m), tt);
-            __syncthreads();
+            wave_lds_sync();  // L1 -> L0 stays inside the wave's quarter
             to_lds<TB, 1>(lds, v, lane, wave);
-            __syncthreads();
+            wave_lds_sync();
         }
         from_lds<TB, 0>(lds, v, lane, wave);
         mix32(v, L::sm0(m), tt);

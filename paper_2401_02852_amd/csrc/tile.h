@@ -109,6 +109,17 @@ struct Lay {
     }
 };
 
+// Layouts L0 and L1 put the same tile bits (11 and up) in the wave index, so
+// a transpose between them moves data only inside each wave's own quarter of
+// the LDS tile. LDS operations of one wave complete in order, so such a
+// transpose needs no workgroup barrier: this keeps the compiler from moving
+// LDS accesses across the point (wavefront-scope fences emit no code).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // LDS position of tile element e: two padding slots after every 64 elements.
 // Any 16 consecutive lanes then hit 16 distinct 8-byte bank pairs in all three
 // layouts, and because the map is additive over disjoint bit sets of e, an
