@@ -111,7 +111,8 @@ int qnae_build_cost_diagonal_pred(qnae_ctx *ctx, const int32_t *clauses, int32_t
 /* Run depth-p QAOA from |+> on the cost diagonal and read out p_succ, E[C]
  * and the norm (Section 3.3; Definition of the success probability).
  *
- *   cost_dev     device, 2^n elements of cost_dtype, values in [0, m]
+ *   cost_dev     device, 2^n elements of cost_dtype, values in [0, m],
+ *                16-byte aligned
  *   n, m         1 <= n <= QNAE_MAX_N; m bounds the cost values (phase table
  *                length m + 1); m <= 255 for QNAE_U8, m <= 65535 for U16
  *   gammas, betas host FP64 arrays of length p (may be NULL when p = 0);
