@@ -107,9 +107,9 @@ constexpr int kBatchTileBits = 13;
 // first[i] .. first[i+1]-1 (first has count+1 entries, first[count] =
 // blocks), one per tile of its own geometry; args[i].partials receives 3
 // doubles per tile for readout kinds. Every instance must use
-// kBatchTileBits.
+// kBatchTileBits. half: every instance is a half-state sweep (args[i].half).
 hipError_t launch_sweep_batch(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
-                              uint32_t blocks, hipStream_t s);
+                              uint32_t blocks, hipStream_t s, bool half = false);
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s);
 
 // Whole circuit for n <= 14 in one workgroup (state resident in LDS).

@@ -5,6 +5,8 @@
 // of two of 8-byte amplitudes, so blocks do not fragment into odd sizes).
 // Each active request holds a cost block; a large one (n > 14) also holds a
 // state block and an aux block (phase tables, mixer forms, tile partial sums).
+// Requests are NAE instances, so a large one is solved on the half state
+// (x < 2^(n-1), the global-flip symmetry): half the pool and the traffic.
 //
 // Tick: admit queued requests (FIFO) while a slot is free and the pool can
 // hold them; upload everything new in one pinned copy; build the new cost
@@ -25,6 +27,7 @@
 #include <mutex>
 #include <set>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 
 #include "host.h"
@@ -95,6 +98,7 @@ struct Request {
     qnae_result result{};
     // active
     bool resident = false;
+    bool half = false;  // state and cost kept for x < 2^(n-1) (NAE global-flip symmetry)
     uint64_t state_off = 0, cost_off = 0, aux_off = 0;
     int state_order = -1, cost_order = -1, aux_order = -1;
     size_t form_off = 0, part_off = 0;  // inside the aux block (tables at 0)
@@ -130,14 +134,14 @@ struct qnae_server {
     std::string error_msg;
     uint64_t completed = 0, ticks = 0, launches = 0;
     double tick_bytes = 8e9;  // state traffic per tick, about 1.5 ms of HBM time
+    bool use_half = true;     // half-state solves for requests with n > 14 (QNAE_SERVER_HALF)
     std::thread worker;
 
-    // Footprint blocks of a request; false if it can never fit the pool.
     // Footprint blocks of a request (-1: none); false if it can never fit.
     // Large requests: state, cost, aux = [tables | forms | tile partials].
     // Small (resident) requests: cost only; their tables stay in the upload.
     bool plan_blocks(Request& r, int* so, int* co, int* ao) const {
-        const uint64_t N = 1ull << r.n;
+        const uint64_t N = 1ull << (r.n - (r.half ? 1 : 0));
         const int T = r.p > 0 ? r.p : 1;
         r.form_off = round_up(sizeof(float2) * (uint64_t)T * (r.m + 1), 256);
         r.part_off = r.form_off + round_up(sizeof(MixForm) * T, 256);
@@ -201,9 +205,11 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
         w.forms.resize((size_t)T);
         r.final_scale = build_tables(r.n, r.m, r.gammas.data(), r.betas.data(), r.p, w.tabs.data(), w.forms.data());
         w.tab_at = B.take(r.part_off);  // same layout as the aux block: tables, then forms
-        if (!r.resident)
+        if (!r.resident) {
             plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, qnae::kBatchTileBits, ctx->min_low_run, ctx->page_bit, false,
                         w.forms.data(), r.final_scale);
+            r.plan.half = r.half;
+        }
     }
     // Cost launches per cost type.
     std::vector<New*> cgroups[2];
@@ -227,24 +233,26 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
         if (!r->resident) {
             large.push_back(r);
             most = std::max(most, r->plan.ops.size() - r->next_op);
-            round_bytes += 17.0 * (double)(1ull << r->n);
+            round_bytes += 17.0 * (double)(1ull << (r->n - (r->half ? 1 : 0)));
         }
     size_t rounds = most;
     if (round_bytes > 0) rounds = std::min(rounds, std::max<size_t>(1, (size_t)(tick_bytes / round_bytes)));
     struct Launch {
         int kind, dtype;
+        bool half;
         std::vector<Request*> members;
         size_t args_at, first_at;
         uint32_t blocks;
     };
-    std::vector<std::map<std::pair<int, int>, Launch>> sweeps(rounds);
+    std::vector<std::map<std::tuple<int, int, bool>, Launch>> sweeps(rounds);
     std::vector<Request*> finishing;
     for (Request* r : large) {
         for (size_t k = 0; k < rounds && r->next_op + k < r->plan.ops.size(); ++k) {
             const Op& op = r->plan.ops[r->next_op + k];
-            Launch& L = sweeps[k][{op.kind, r->dtype}];
+            Launch& L = sweeps[k][std::make_tuple(op.kind, r->dtype, r->half)];
             L.kind = op.kind;
             L.dtype = r->dtype;
+            L.half = r->half;
             L.members.push_back(r);
         }
         if (r->next_op + rounds >= r->plan.ops.size()) finishing.push_back(r);
@@ -277,6 +285,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
     }
     uint32_t cblocks[2] = {0, 0};
     int cmax[2] = {0, 0};
+    bool cwide[2] = {false, false};  // some clause variable at index 32 or above
     for (int g = 0; g < 2; ++g) {
         qnae::CostArgs* args = (qnae::CostArgs*)(h + cargs_at[g]);
         uint32_t* first = (uint32_t*)(h + cfirst_at[g]);
@@ -284,11 +293,13 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
             const New& w = *cgroups[g][q];
             args[q].clauses = (const ClauseRec*)(d + w.rec_at);
             args[q].num_clauses = w.nrec;
-            args[q].n = w.r->n;
+            const int states = w.r->n - (w.r->half ? 1 : 0);  // half: the lower half of the diagonal
+            args[q].n = states;
             args[q].cost = pool + w.r->cost_off;
             args[q].zeros = nullptr;
             first[q] = cblocks[g];
-            const uint64_t threads = w.r->n >= 5 ? (1ull << (w.r->n - 5)) : 1ull;
+            cwide[g] = cwide[g] || w.r->n > 32;
+            const uint64_t threads = states >= 5 ? (1ull << (states - 5)) : 1ull;
             cblocks[g] += (uint32_t)((threads + 255) / 256);
             cmax[g] = std::max(cmax[g], w.nrec);
         }
@@ -345,7 +356,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
     for (int g = 0; g < 2; ++g) {
         if (cgroups[g].empty()) continue;
         HIP_TRY(qnae::launch_cost_batch((const qnae::CostArgs*)(d + cargs_at[g]), (const uint32_t*)(d + cfirst_at[g]),
-                                        (int)cgroups[g].size(), cblocks[g], g ? QNAE_U16 : QNAE_U8, cmax[g], false, s));
+                                        (int)cgroups[g].size(), cblocks[g], g ? QNAE_U16 : QNAE_U8, cmax[g], cwide[g], s));
         ++launches;
     }
     for (int g = 0; g < 2; ++g) {
@@ -358,7 +369,8 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
         for (auto& kv : sweeps[k]) {
             const Launch& L = kv.second;
             HIP_TRY(qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
-                                             (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, s));
+                                             (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, s,
+                                             L.half));
             ++launches;
         }
     if (!finishing.empty()) {
@@ -376,7 +388,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
         for (Request* r : large) r->next_op = std::min(r->plan.ops.size(), r->next_op + rounds);
         for (size_t q = 0; q < done.size(); ++q) {
             Request& r = *done[q];
-            const double sc = std::norm(r.final_scale);
+            const double sc = std::norm(r.final_scale) * (r.half ? 2.0 : 1.0);
             r.result.p_success = hres[3 * q] * sc;
             r.result.expected_cost = hres[3 * q + 1] * sc;
             r.result.norm = hres[3 * q + 2] * sc;
@@ -463,6 +475,7 @@ int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qn
     S->device = ctx->device;
     S->max_slots = max_slots;
     S->pool_bytes = 1ull << order;
+    if (const char* e = std::getenv("QNAE_SERVER_HALF")) S->use_half = std::atoi(e) != 0;
     if (const char* e = std::getenv("QNAE_SERVER_TICK_BYTES")) S->tick_bytes = std::max(1.0, std::atof(e));
     HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
     hipError_t e = hipMalloc((void**)&S->pool, S->pool_bytes);
@@ -500,7 +513,8 @@ int qnae_server_submit(qnae_server* S, const int32_t* clauses, int32_t m, int32_
         r->betas.assign(betas, betas + p);
     }
     r->resident = n <= kResidentMaxN;
-    r->tiles = r->resident ? 0u : 1u << (n - qnae::kBatchTileBits);
+    r->half = !r->resident && S->use_half;
+    r->tiles = r->resident ? 0u : 1u << (n - (r->half ? 1 : 0) - qnae::kBatchTileBits);
     int so, co, ao;
     if (!S->plan_blocks(*r, &so, &co, &ao))
         return fail(QNAE_EINVAL, "request with n=%d does not fit a pool of %llu bytes", n,

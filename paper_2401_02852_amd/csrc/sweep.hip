@@ -68,10 +68,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     // every lane (scalar registers).
     // Half sweeps: the virtual bit contributes no unit offset (bitval 0); it
     // selects the mirrored address instead.
-    const uint32_t vb = HALF ? (uint32_t)a.vbit : 0u;
+    // (a half sweep whose group lacks bit n-1 has vbit < 0: plain addresses)
+    const bool has_v = HALF && a.vbit >= 0;
+    const uint32_t vb = has_v ? (uint32_t)a.vbit : 0u;
     uint64_t bitval[TB];
 #pragma unroll
-    for (int i = 0; i < TB; ++i) bitval[i] = (HALF && (uint32_t)i == vb) ? 0ull : 1ull << a.pos[i];
+    for (int i = 0; i < TB; ++i) bitval[i] = (has_v && (uint32_t)i == vb) ? 0ull : 1ull << a.pos[i];
     auto scat = [&](uint32_t e) -> uint64_t {
         uint64_t x = 0;
 #pragma unroll
@@ -89,7 +91,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         if (w & 1ull) base |= m & (~m + 1ull);
         w >>= 1;
     }
-    auto vpar = [&](uint32_t e) -> bool { return HALF && ((e >> vb) & 1u); };
+    auto vpar = [&](uint32_t e) -> bool { return has_v && ((e >> vb) & 1u); };
     auto haddr = [&](uint32_t te) -> HalfAddr {
         HalfAddr h;
         h.fwd = base + scat(te);
@@ -289,13 +291,13 @@ __device__ __forceinline__ int batch_item(const uint32_t* first, int count, uint
 
 // One sweep step over many states at once (ragged): instance i owns blocks
 // first[i] .. first[i+1]-1, one per tile, with its own arguments.
-template <int TB, typename CT, int KIND>
+template <int TB, typename CT, int KIND, bool HALF>
 __global__ __launch_bounds__(64 << (TB - 11)) void sweep_batch_kernel(const SweepArgs* args, const uint32_t* first,
                                                                       int count) {
     const int i = batch_item(first, count, blockIdx.x);
     const SweepArgs a = args[i];
     const uint32_t t = blockIdx.x - first[i];
-    sweep_tile<TB, CT, KIND, false>(a, t, a.partials + 3 * (size_t)t);
+    sweep_tile<TB, CT, KIND, HALF>(a, t, a.partials + 3 * (size_t)t);
 }
 
 // psi[x] <-> psi[N - 1 - x]: undoes an X on every qubit (N >= 4).
@@ -442,9 +444,14 @@ hipError_t launch_kind(const SweepArgs& a, hipStream_t s) {
 }
 
 template <int TB, typename CT, int KIND>
-hipError_t launch_batch_kind(const SweepArgs* args, const uint32_t* first, int count, uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((sweep_batch_kernel<TB, CT, KIND>), dim3(blocks), dim3(64 << (TB - 11)), 0, s, args, first,
-                       count);
+hipError_t launch_batch_kind(const SweepArgs* args, const uint32_t* first, int count, uint32_t blocks, bool half,
+                             hipStream_t s) {
+    if (half)
+        hipLaunchKernelGGL((sweep_batch_kernel<TB, CT, KIND, true>), dim3(blocks), dim3(64 << (TB - 11)), 0, s, args,
+                           first, count);
+    else
+        hipLaunchKernelGGL((sweep_batch_kernel<TB, CT, KIND, false>), dim3(blocks), dim3(64 << (TB - 11)), 0, s, args,
+                           first, count);
     return hipGetLastError();
 }
 
@@ -462,13 +469,14 @@ hipError_t launch_tb(int kind, const SweepArgs& a, hipStream_t s) {
 
 template <typename CT>
 hipError_t launch_batch_ct(int kind, const SweepArgs* args, const uint32_t* first, int count, uint32_t blocks,
-                           hipStream_t s) {
+                           bool half, hipStream_t s) {
+    constexpr int TB = kBatchTileBits;
     switch (kind) {
-        case SK_FIRST: return launch_batch_kind<kBatchTileBits, CT, SK_FIRST>(args, first, count, blocks, s);
-        case SK_MIDDLE: return launch_batch_kind<kBatchTileBits, CT, SK_MIDDLE>(args, first, count, blocks, s);
-        case SK_BOUNDARY: return launch_batch_kind<kBatchTileBits, CT, SK_BOUNDARY>(args, first, count, blocks, s);
-        case SK_FINAL: return launch_batch_kind<kBatchTileBits, CT, SK_FINAL>(args, first, count, blocks, s);
-        case SK_P0: return launch_batch_kind<kBatchTileBits, CT, SK_P0>(args, first, count, blocks, s);
+        case SK_FIRST: return launch_batch_kind<TB, CT, SK_FIRST>(args, first, count, blocks, half, s);
+        case SK_MIDDLE: return launch_batch_kind<TB, CT, SK_MIDDLE>(args, first, count, blocks, half, s);
+        case SK_BOUNDARY: return launch_batch_kind<TB, CT, SK_BOUNDARY>(args, first, count, blocks, half, s);
+        case SK_FINAL: return launch_batch_kind<TB, CT, SK_FINAL>(args, first, count, blocks, half, s);
+        case SK_P0: return launch_batch_kind<TB, CT, SK_P0>(args, first, count, blocks, half, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -490,9 +498,9 @@ hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStre
 }
 
 hipError_t launch_sweep_batch(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
-                              uint32_t blocks, hipStream_t s) {
-    return dtype == 1 ? launch_batch_ct<uint8_t>(kind, args, first, count, blocks, s)
-                      : launch_batch_ct<uint16_t>(kind, args, first, count, blocks, s);
+                              uint32_t blocks, hipStream_t s, bool half) {
+    return dtype == 1 ? launch_batch_ct<uint8_t>(kind, args, first, count, blocks, half, s)
+                      : launch_batch_ct<uint16_t>(kind, args, first, count, blocks, half, s);
 }
 
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s) {

@@ -1,6 +1,8 @@
 """Continuous-batching server (qnae_server_*) through the C ABI: every result
-equals the single-instance path whatever else shares its launches, against
-the FP64 oracle on a sample; pool limits queue requests rather than fail them."""
+equals the single-instance path whatever else shares its launches (the
+half-state path for n > 14, which the server uses for these NAE requests
+unless QNAE_SERVER_HALF=0), against the FP64 oracle on a sample; pool limits
+queue requests rather than fail them."""
 import threading
 import time
 
@@ -38,8 +40,10 @@ def requests(count, seed, n_lo=3, n_hi=20, p_hi=6):
     return out
 
 
-def alone(q, r):
+def alone(q, r, half=True):
     n, k, m, cl, g, b = r
+    if half and n > 14:
+        return q.qaoa_run_z2(q.build_cost_diagonal_z2(cl, n), n, m, g, b)
     c = q.build_cost_diagonal(cl, n)
     return q.qaoa_run(c, n, m, g, b)
 
@@ -48,12 +52,15 @@ def close(a, b):
     return np.allclose(tuple(a), tuple(b), rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("slots,tick_bytes", [(1, None), (5, None), (64, None), (7, "1"), (64, "3e7")])
-def test_server_results_equal_single_path(q, slots, tick_bytes, monkeypatch):
+@pytest.mark.parametrize("slots,tick_bytes,half", [(1, None, "1"), (5, None, "1"), (64, None, "1"), (7, "1", "1"),
+                                                   (64, "3e7", "1"), (5, None, "0"), (64, "3e7", "0")])
+def test_server_results_equal_single_path(q, slots, tick_bytes, half, monkeypatch):
     """tick_bytes 1: one sweep round per scheduler tick; 3e7: a few rounds;
-    default: every round of a lightly loaded server in one tick."""
+    default: every round of a lightly loaded server in one tick. half 0: full
+    states."""
     if tick_bytes:
         monkeypatch.setenv("QNAE_SERVER_TICK_BYTES", tick_bytes)
+    monkeypatch.setenv("QNAE_SERVER_HALF", half)
     reqs = requests(40, slots)
     with q.Server(pool_bytes=1 << 28, max_slots=slots) as s:
         tickets = [s.submit(r[3], r[0], r[4], r[5]) for r in reqs]
@@ -63,7 +70,7 @@ def test_server_results_equal_single_path(q, slots, tick_bytes, monkeypatch):
     assert st["peak_pool_bytes"] <= 1 << 28
     for r, (res, lat) in zip(reqs, got):
         assert lat > 0
-        assert close(res, alone(q, r)), (r[0], r[2], len(r[4]))
+        assert close(res, alone(q, r, half == "1")), (r[0], r[2], len(r[4]))
     for r, (res, _) in list(zip(reqs, got))[::7]:
         n, k, m, cl, g, b = r
         ref = oracle.qaoa(oracle.cost(cl, n), n, g, b)
@@ -83,12 +90,13 @@ def test_server_admission_order_does_not_change_results(q):
 
 
 def test_small_pool_queues_requests(q):
-    """A 1 MiB pool holds one n = 16 request (512 KiB state + 64 KiB costs +
-    tables) at a time, so the others wait in the queue; n = 17 can never fit."""
-    reqs = requests(6, 11, n_lo=16, n_hi=16)
+    """A 1 MiB pool holds one n = 17 request (half state: 512 KiB state +
+    64 KiB costs + tables) at a time, so the others wait in the queue; n = 18
+    can never fit."""
+    reqs = requests(6, 11, n_lo=17, n_hi=17)
     with q.Server(pool_bytes=1 << 20, max_slots=8) as s:
         with pytest.raises(q.QNAEError, match="does not fit"):
-            s.submit(inst.instance(17, 3, 30, 0), 17, [0.1], [0.2])
+            s.submit(inst.instance(18, 3, 30, 0), 18, [0.1], [0.2])
         tickets = [s.submit(r[3], r[0], r[4], r[5]) for r in reqs]
         got = [s.wait(t)[0] for t in tickets]
         assert s.stats()["peak_pool_bytes"] <= 1 << 20
