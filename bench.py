@@ -108,6 +108,18 @@ def batched_bench(q, ctx, reps=5, count=512):
         q.qaoa_run_batched(costs, ns, ms, gs, bs, ctx=ctx)
     torch.cuda.synchronize()
     t_without = (time.perf_counter() - t0) / reps
+    # the same batch with half-state solves for n > 14 (NAE global-flip symmetry)
+    half = [n > 14 for n in ns]
+    hcosts = q.build_cost_diagonals(cls, ns, half=half, ctx=ctx)
+    q.qaoa_run_batched(hcosts, ns, ms, gs, bs, half=half, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q.build_cost_diagonals(cls, ns, outs=hcosts, half=half, ctx=ctx)
+        q.qaoa_run_batched(hcosts, ns, ms, gs, bs, half=half, ctx=ctx)
+    torch.cuda.synchronize()
+    t_half = (time.perf_counter() - t0) / reps
+    del hcosts
     for i in range(count):  # warm the plain path
         q.build_cost_diagonal(cls[i], ns[i], out=costs[i], ctx=ctx)
         q.qaoa_run(costs[i], ns[i], ms[i], gs[i], bs[i], ctx=ctx)
@@ -130,6 +142,7 @@ def batched_bench(q, ctx, reps=5, count=512):
             "plain_instance_layers_per_s": layers / t_plain,
             "plain_instance_layers_per_s_cost_resident": layers / t_plain_nc,
             "speedup_vs_plain": t_plain / t_with,
+            "instance_layers_per_s_half_state": layers / t_half,
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
 
 

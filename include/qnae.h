@@ -167,6 +167,8 @@ typedef struct {
     int32_t cost_dtype;       /* QNAE_U8 (m <= 255) or QNAE_U16 */
     uint64_t *num_solutions;  /* optional host pointer (the call then waits) */
     int32_t predicate;        /* QNAE_PRED_NAE (0) or QNAE_PRED_SAT */
+    int32_t half;             /* 1: the lower half only, as qnae_build_cost_diagonal_z2
+                                 (NAE; cost_dev holds 2^(n-1); counts are of the whole) */
 } qnae_cost_job;
 
 /* Builds `count` cost diagonals (same definition as qnae_build_cost_diagonal)
@@ -182,6 +184,8 @@ typedef struct {
     const double *gammas;  /* host, p entries (layer 0 first) */
     const double *betas;   /* host, p entries */
     void *state_dev;       /* optional device complex64[2^n] for the final state */
+    int32_t half;          /* 1: half-state solve as qnae_qaoa_run_z2 (n > 14; cost_dev
+                              and state_dev then hold 2^(n-1) entries) */
 } qnae_instance;
 
 /* Runs `count` independent depth-p QAOA solves (Section 3.3) together and

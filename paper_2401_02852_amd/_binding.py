@@ -38,13 +38,14 @@ class _CResult(ctypes.Structure):
 class _CCostJob(ctypes.Structure):
     _fields_ = [("clauses", ctypes.POINTER(ctypes.c_int32)), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32),
-                ("num_solutions", ctypes.POINTER(ctypes.c_uint64)), ("predicate", ctypes.c_int32)]
+                ("num_solutions", ctypes.POINTER(ctypes.c_uint64)), ("predicate", ctypes.c_int32),
+                ("half", ctypes.c_int32)]
 
 
 class _CInstance(ctypes.Structure):
     _fields_ = [("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("gammas", ctypes.POINTER(ctypes.c_double)),
-                ("betas", ctypes.POINTER(ctypes.c_double)), ("state_dev", ctypes.c_void_p)]
+                ("betas", ctypes.POINTER(ctypes.c_double)), ("state_dev", ctypes.c_void_p), ("half", ctypes.c_int32)]
 
 
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -300,18 +301,28 @@ def qaoa_run(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[C
     return Result(res.p_success, res.expected_cost, res.norm)
 
 
+def _per_item(value, count, name):
+    vals = list(value) if isinstance(value, (list, tuple)) else [value] * count
+    if len(vals) != count:
+        raise ValueError(f"{name} list has {len(vals)} entries, expected {count}")
+    return vals
+
+
 def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = False, predicate="nae",
-                         ctx: Optional[Context] = None, stream=None):
+                         half=False, ctx: Optional[Context] = None, stream=None):
     """Batched build_cost_diagonal: one tensor per (clauses, n) pair, built
     with one launch per cost type. ``predicate`` is one name for all or a list
-    of names. Returns the list of tensors, or (tensors, solution counts) with
-    count_solutions."""
+    of names; ``half`` (one flag or a list) builds the lower half only, as
+    build_cost_diagonal_z2. Returns the list of tensors, or (tensors, solution
+    counts) with count_solutions."""
     import torch
     arrs = [np.ascontiguousarray(np.asarray(c, dtype=np.int32)) for c in clause_sets]
     if len(arrs) != len(ns):
         raise ValueError("clause_sets and ns differ in length")
+    halves = _per_item(half, len(arrs), "half")
     if outs is None:
-        outs = [torch.empty(1 << n, dtype=cost_dtype_for(a.shape[0]), device="cuda") for a, n in zip(arrs, ns)]
+        outs = [torch.empty(1 << (n - (1 if hf else 0)), dtype=cost_dtype_for(a.shape[0]), device="cuda")
+                for a, n, hf in zip(arrs, ns, halves)]
     jobs = (_CCostJob * len(arrs))()
     sols = [ctypes.c_uint64(0) for _ in arrs]
     preds = [predicate] * len(arrs) if isinstance(predicate, str) else list(predicate)
@@ -327,18 +338,24 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
         jobs[i].cost_dtype = QNAE_U8 if o.dtype == torch.uint8 else QNAE_U16
         jobs[i].num_solutions = ctypes.pointer(sols[i]) if count_solutions else None
         jobs[i].predicate = _pred_code(preds[i])
+        jobs[i].half = 1 if halves[i] else 0
+        if o.numel() != (1 << (int(n) - jobs[i].half)):
+            raise ValueError(f"job {i}: cost has {o.numel()} entries, expected 2^{int(n) - jobs[i].half}")
     ctx = ctx or default_context()
     _check(load_library().qnae_build_cost_diagonal_batched(ctx.handle, jobs, len(arrs), _stream(stream)))
     return (outs, [int(v.value) for v in sols]) if count_solutions else outs
 
 
-def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, ctx: Optional[Context] = None,
+def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, ctx: Optional[Context] = None,
                      stream=None):
-    """Batched qaoa_run over many instances; returns a list of Result."""
+    """Batched qaoa_run over many instances; returns a list of Result.
+    ``half`` (one flag or a list) solves an instance on the half state as
+    qaoa_run_z2 (its cost and state then hold 2^(n-1) entries)."""
     import torch
     count = len(costs)
     if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
         raise ValueError("argument lists differ in length")
+    halves = _per_item(half, count, "half")
     inst = (_CInstance * count)()
     keep = []
     for i in range(count):
@@ -346,18 +363,20 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, ctx: Optional
         b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas[i], dtype=np.float64)))
         if g.shape != b.shape or g.ndim != 1:
             raise ValueError(f"instance {i}: gammas and betas must be 1-D of equal length")
-        if costs[i].numel() != (1 << int(ns[i])):
-            raise ValueError(f"instance {i}: cost has {costs[i].numel()} entries, expected 2^{ns[i]}")
+        stored = int(ns[i]) - (1 if halves[i] else 0)
+        if costs[i].numel() != (1 << stored):
+            raise ValueError(f"instance {i}: cost has {costs[i].numel()} entries, expected 2^{stored}")
         keep += [g, b]
         st = states[i] if states is not None else None
-        if st is not None and (st.dtype != torch.complex64 or st.numel() != (1 << int(ns[i]))):
-            raise ValueError(f"instance {i}: state must be complex64 with 2^n entries")
+        if st is not None and (st.dtype != torch.complex64 or st.numel() != (1 << stored)):
+            raise ValueError(f"instance {i}: state must be complex64 with 2^{stored} entries")
         inst[i].cost_dev = costs[i].data_ptr()
         inst[i].cost_dtype = QNAE_U8 if costs[i].dtype == torch.uint8 else QNAE_U16
         inst[i].n, inst[i].m, inst[i].p = int(ns[i]), int(ms[i]), g.shape[0]
         inst[i].gammas = g.ctypes.data_as(_F64P) if g.shape[0] else None
         inst[i].betas = b.ctypes.data_as(_F64P) if g.shape[0] else None
         inst[i].state_dev = st.data_ptr() if st is not None else None
+        inst[i].half = 1 if halves[i] else 0
     res = (_CResult * count)()
     ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <utility>
 
 #include "host.h"
@@ -30,6 +31,8 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
         if (!rc) rc = check_literals(j.clauses, j.m, j.n, j.k);
         if (!rc && j.predicate != QNAE_PRED_NAE && j.predicate != QNAE_PRED_SAT)
             rc = fail(QNAE_EINVAL, "predicate=%d is not QNAE_PRED_NAE/QNAE_PRED_SAT", j.predicate);
+        if (!rc && j.half && (j.predicate != QNAE_PRED_NAE || j.n < 2))
+            rc = fail(QNAE_EINVAL, "half diagonals need the NAE predicate and n >= 2");
         if (rc) return fail(rc, "job %d: %s", i, std::string(last_error()).c_str());
     }
     if (count == 0) return QNAE_OK;
@@ -74,16 +77,17 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
             const int i = groups[g][q];
             args[q].clauses = (const ClauseRec*)(d + rec_at) + rec_off[i];
             args[q].num_clauses = nrec[i];
-            args[q].n = jobs[i].n;
+            const int states = jobs[i].n - (jobs[i].half ? 1 : 0);
+            args[q].n = states;
             args[q].cost = jobs[i].cost_dev;
             args[q].zeros = zeros_dev + i;
             first[q] = blocks[g];
-            const uint64_t threads = jobs[i].n >= 5 ? (1ull << (jobs[i].n - 5)) : 1ull;
+            const uint64_t threads = states >= 5 ? (1ull << (states - 5)) : 1ull;
             const uint64_t nb = (threads + 255) / 256;
             if (blocks[g] + nb > 0x7fffffffull) return fail(QNAE_EINVAL, "batch too large for one grid");
             blocks[g] += (uint32_t)nb;
             maxc[g] = std::max(maxc[g], nrec[i]);
-            bytes[g] += std::ldexp(jobs[i].cost_dtype == QNAE_U8 ? 1.0 : 2.0, jobs[i].n);
+            bytes[g] += std::ldexp(jobs[i].cost_dtype == QNAE_U8 ? 1.0 : 2.0, states);
         }
         first[groups[g].size()] = blocks[g];
     }
@@ -106,7 +110,7 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
         HIP_TRY(hipStreamSynchronize(s));
         const unsigned long long* z = (const unsigned long long*)ctx->h_results.ptr;
         for (int i = 0; i < count; ++i)
-            if (jobs[i].num_solutions) *jobs[i].num_solutions = z[i];
+            if (jobs[i].num_solutions) *jobs[i].num_solutions = z[i] * (jobs[i].half ? 2ull : 1ull);
     }
     return QNAE_OK;
 }
@@ -117,6 +121,8 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         const qnae_instance& q = inst[i];
         if (int rc = check_run_args(q.n, q.m, q.cost_dtype, q.cost_dev, q.gammas, q.betas, q.p))
             return fail(rc, "instance %d: %s", i, std::string(last_error()).c_str());
+        if (q.half && q.n <= kResidentMaxN)
+            return fail(QNAE_EINVAL, "instance %d: half-state solves need n > %d", i, kResidentMaxN);
     }
     if (count == 0) return QNAE_OK;
     if (int rc = enter(ctx)) return rc;
@@ -145,11 +151,12 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         lut_elems += (size_t)J.T * (q.m + 1);
         J.form_at = form_elems;
         form_elems += (size_t)J.T;
-        J.tiles = J.resident ? 0u : 1u << (q.n - TB);
+        const int stored = q.n - (q.half ? 1 : 0);
+        J.tiles = J.resident ? 0u : 1u << (stored - TB);
         J.part_at = part_elems;
         part_elems += 3 * (size_t)J.tiles;
         J.state_at = state_elems;
-        if (!J.resident && !q.state_dev) state_elems += (size_t)1 << q.n;
+        if (!J.resident && !q.state_dev) state_elems += (size_t)1 << stored;
     }
     std::vector<float2> tables(lut_elems);
     std::vector<MixForm> forms(form_elems);
@@ -160,6 +167,7 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         if (!J.resident) {
             plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, TB, ctx->min_low_run, ctx->page_bit,
                         q.state_dev != nullptr, forms.data() + J.form_at, J.final_scale);
+            J.plan.half = q.half != 0;
             steps = std::max(steps, (int)J.plan.ops.size());
         }
     }
@@ -169,6 +177,7 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     // Sweep launches: step s, bucket (kind, cost type).
     struct Launch {
         int kind, dtype, step;
+        bool half;
         std::vector<int> members;
         size_t args_at, first_at;
         uint32_t blocks;
@@ -176,15 +185,15 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     };
     std::vector<Launch> launches;
     for (int st = 0; st < steps; ++st) {
-        std::map<std::pair<int, int>, size_t> bucket;
+        std::map<std::tuple<int, int, bool>, size_t> bucket;
         for (int i = 0; i < count; ++i) {
             const Job& J = jobs[i];
             if (J.resident || st >= (int)J.plan.ops.size()) continue;
-            const auto key = std::make_pair(J.plan.ops[st].kind, inst[i].cost_dtype);
+            const auto key = std::make_tuple(J.plan.ops[st].kind, inst[i].cost_dtype, J.plan.half);
             auto it = bucket.find(key);
             if (it == bucket.end()) {
                 it = bucket.emplace(key, launches.size()).first;
-                launches.push_back({key.first, key.second, st, {}, 0, 0, 0u, 0.0});
+                launches.push_back({std::get<0>(key), std::get<1>(key), st, std::get<2>(key), {}, 0, 0, 0u, 0.0});
             }
             launches[it->second].members.push_back(i);
         }
@@ -286,12 +295,14 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         for (const Launch& L : launches) {
             HIP_TRY(run(K_BATCH_SWEEP, L.bytes, [&] {
                 return qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
-                                                (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, st);
+                                                (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, st,
+                                                L.half);
             }));
         }
         for (int i : sweep_members) {
             const SweepPlan& P = jobs[i].plan;
-            if (P.keep && P.p > 0 && P.flips_before[P.p]) HIP_TRY(qnae::launch_reverse(psi_of(i), 1ull << inst[i].n, st));
+            if (P.keep && !P.half && P.p > 0 && P.flips_before[P.p])
+                HIP_TRY(qnae::launch_reverse(psi_of(i), 1ull << inst[i].n, st));
         }
         if (!sweep_members.empty()) {
             HIP_TRY(run(K_BATCH_REDUCE, 24.0 * part_elems / 3, [&] {
@@ -314,12 +325,12 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         mix(B.size);
         for (int g = 0; g < 2; ++g) mix(res_members[g].size());
         for (const Launch& L : launches) {
-            mix((uint64_t)L.kind << 40 | (uint64_t)L.dtype << 32 | L.blocks);
+            mix((uint64_t)L.half << 48 | (uint64_t)L.kind << 40 | (uint64_t)L.dtype << 32 | L.blocks);
             mix(L.members.size() << 32 | L.args_at);
         }
         for (int i : sweep_members) {
             const SweepPlan& P = jobs[i].plan;
-            if (P.keep && P.p > 0 && P.flips_before[P.p]) mix((uint64_t)(uintptr_t)psi_of(i) ^ inst[i].n);
+            if (P.keep && !P.half && P.p > 0 && P.flips_before[P.p]) mix((uint64_t)(uintptr_t)psi_of(i) ^ inst[i].n);
         }
         mix(sweep_members.size());
         hipGraphExec_t exec = nullptr;
@@ -351,7 +362,7 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     HIP_TRY(hipStreamSynchronize(s));
     const double* r = (const double*)ctx->h_results.ptr;
     for (int i = 0; i < count; ++i) {
-        const double sc = std::norm(jobs[i].final_scale);
+        const double sc = std::norm(jobs[i].final_scale) * (inst[i].half ? 2.0 : 1.0);
         out[i].p_success = r[3 * i] * sc;
         out[i].expected_cost = r[3 * i + 1] * sc;
         out[i].norm = r[3 * i + 2] * sc;

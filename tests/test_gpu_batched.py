@@ -110,3 +110,45 @@ def test_graph_replay_matches_eager(q, monkeypatch):
         torch.cuda.synchronize()
     eager.close()
     graph.close()
+
+
+def test_batched_half_state_instances(q):
+    """Half-state instances (n > 14) next to full ones in one batch: each
+    equals qaoa_run_z2 (or qaoa_run) alone; half cost jobs equal
+    build_cost_diagonal_z2; a sample against the oracle."""
+    import torch
+    batch = inst.batched_workload(count=48, seed=3)
+    ns = [x["n"] for x in batch]
+    ms = [x["m"] for x in batch]
+    cls = [x["clauses"] for x in batch]
+    half = [x["n"] > 14 and i % 3 != 0 for i, x in enumerate(batch)]
+    costs, sols = q.build_cost_diagonals(cls, ns, half=half, count_solutions=True)
+    states = [torch.empty(1 << (n - (1 if h else 0)), dtype=torch.complex64, device="cuda") for n, h in zip(ns, half)]
+    gs = [x["gammas"] for x in batch]
+    bs = [x["betas"] for x in batch]
+    res = q.qaoa_run_batched(costs, ns, ms, gs, bs, half=half, states=states)
+    again = q.qaoa_run_batched(costs, ns, ms, gs, bs, half=half)  # graph replay of the same shape
+    assert again == res
+    for i, x in enumerate(batch):
+        n, m = x["n"], x["m"]
+        if half[i]:
+            c1, s1 = q.build_cost_diagonal_z2(cls[i], n, count_solutions=True)
+            assert torch.equal(c1, costs[i]) and s1 == sols[i]
+            st = torch.empty(1 << (n - 1), dtype=torch.complex64, device="cuda")
+            alone = q.qaoa_run_z2(c1, n, m, gs[i], bs[i], state=st)
+        else:
+            c1 = q.build_cost_diagonal(cls[i], n)
+            assert torch.equal(c1, costs[i])
+            st = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+            alone = q.qaoa_run(c1, n, m, gs[i], bs[i], state=st)
+        assert np.allclose(res[i], alone, rtol=1e-12, atol=1e-15), (i, n, half[i])
+        assert torch.equal(st, states[i])
+    for i in range(0, 48, 5):
+        x = batch[i]
+        ref = oracle.qaoa(oracle.cost(x["clauses"], x["n"]), x["n"], x["gammas"], x["betas"])
+        assert abs(res[i].p_success - ref[0]) <= 1e-5
+        assert abs(res[i].expected_cost - ref[1]) <= 1e-5 * ref[1]
+    with pytest.raises(q.QNAEError, match="half-state"):
+        small = [k for k, x in enumerate(batch) if x["n"] <= 14][0]
+        q.qaoa_run_batched([costs[small][: 1 << (ns[small] - 1)]], [ns[small]], [ms[small]], [gs[small]], [bs[small]],
+                           half=True)
