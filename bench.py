@@ -416,7 +416,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy << 20}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(instances would shard by the top state bits across GPUs, not implemented)", file=sys.stderr)
         sys.exit(2)
 
