@@ -51,8 +51,9 @@ enum {
     QNAE_EINVAL = -1,   /* invalid argument; nothing was enqueued */
     QNAE_ENOMEM = -2,   /* device or pinned host allocation failed */
     QNAE_EHIP = -3,     /* HIP runtime error (message has hipGetErrorString) */
-    QNAE_EBUSY = -4,    /* server queue or pool full */
-    QNAE_ETIMEDOUT = -5 /* server wait timed out */
+    QNAE_EBUSY = -4,     /* server queue or pool full */
+    QNAE_ETIMEDOUT = -5, /* server wait timed out */
+    QNAE_ECANCELED = -6  /* server request cancelled */
 };
 
 /* Largest number of variables (qubits) accepted: 2^34 complex64 amplitudes
@@ -236,6 +237,17 @@ int qnae_server_submit(qnae_server *server, const int32_t *clauses, int32_t m, i
  * request failed on the device). */
 int qnae_server_wait(qnae_server *server, uint64_t ticket, int32_t timeout_ms, qnae_result *out,
                      double *latency_s);
+
+/* Cancels a request: a queued one leaves the queue, an active one is dropped
+ * before the next scheduler tick (its pool blocks are freed). Returns QNAE_OK
+ * when the request will not complete (qnae_server_wait then returns
+ * QNAE_ECANCELED), 1 when it had already completed (its result can still be
+ * collected). Errors: QNAE_EINVAL (unknown ticket). */
+int qnae_server_cancel(qnae_server *server, uint64_t ticket);
+
+/* Bytes of the pool held by requests now (0 once every request has ended,
+ * completed, failed or cancelled). */
+int qnae_server_pool_in_use(qnae_server *server, uint64_t *bytes);
 
 /* Counters: completed requests, scheduler ticks, kernel launches, peak pool
  * bytes in use, requests waiting and active now. Any pointer may be NULL. */

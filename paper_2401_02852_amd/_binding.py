@@ -15,7 +15,7 @@ QNAE_U8 = 1
 QNAE_U16 = 2
 PREDICATES = {"nae": 0, "sat": 1}  # QNAE_PRED_NAE, QNAE_PRED_SAT
 _STATUS = {0: "QNAE_OK", -1: "QNAE_EINVAL", -2: "QNAE_ENOMEM", -3: "QNAE_EHIP",
-           -4: "QNAE_EBUSY", -5: "QNAE_ETIMEDOUT"}
+           -4: "QNAE_EBUSY", -5: "QNAE_ETIMEDOUT", -6: "QNAE_ECANCELED"}
 
 
 class QNAEError(RuntimeError):
@@ -127,13 +127,16 @@ def load_library():
                                          ctypes.POINTER(ctypes.c_double)]
         lib.qnae_server_stats.argtypes = [vp, u64p, u64p, u64p, u64p, u64p, u64p]
         lib.qnae_server_destroy.argtypes = [vp]
+        lib.qnae_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        lib.qnae_server_pool_in_use.argtypes = [vp, u64p]
         for fn in (lib.qnae_create, lib.qnae_destroy, lib.qnae_build_cost_diagonal, lib.qnae_qaoa_run,
                    lib.qnae_build_cost_diagonal_pred,
                    lib.qnae_profile_enable, lib.qnae_profile_read, lib.qnae_build_cost_diagonal_batched,
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
                    lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample, lib.qnae_build_cost_diagonal_z2,
-                   lib.qnae_qaoa_run_z2, lib.qnae_qaoa_grad_batched):
+                   lib.qnae_qaoa_run_z2, lib.qnae_qaoa_grad_batched, lib.qnae_server_cancel,
+                   lib.qnae_server_pool_in_use):
             fn.restype = ctypes.c_int
         _lib = lib
         return lib
@@ -559,6 +562,18 @@ class Server:
         _check(load_library().qnae_server_wait(self._h, int(ticket), int(timeout_ms), ctypes.byref(res),
                                                ctypes.byref(lat)))
         return Result(res.p_success, res.expected_cost, res.norm), float(lat.value)
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request will not complete (wait then raises
+        QNAEError with code -6), False if it had already completed."""
+        rc = load_library().qnae_server_cancel(self._h, int(ticket))
+        _check(rc if rc < 0 else 0)
+        return rc == 0
+
+    def pool_in_use(self) -> int:
+        v = ctypes.c_uint64(0)
+        _check(load_library().qnae_server_pool_in_use(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def stats(self) -> dict:
         v = [ctypes.c_uint64(0) for _ in range(6)]

@@ -81,6 +81,7 @@ class Buddy {
         free_[order].insert(at);
     }
     uint64_t peak() const { return peak_; }
+    uint64_t used() const { return used_; }
 
    private:
     int max_order_;
@@ -94,7 +95,8 @@ struct Request {
     std::vector<int32_t> clauses;
     std::vector<double> gammas, betas;
     double t_submit = 0, t_done = 0;
-    enum { QUEUED, ACTIVE, DONE, FAILED } state = QUEUED;
+    enum { QUEUED, ACTIVE, DONE, FAILED, CANCELED } state = QUEUED;
+    bool cancel = false;  // drop before the next tick
     qnae_result result{};
     // active
     bool resident = false;
@@ -135,6 +137,9 @@ struct qnae_server {
     uint64_t completed = 0, ticks = 0, launches = 0;
     double tick_bytes = 8e9;  // state traffic per tick, about 1.5 ms of HBM time
     bool use_half = true;     // half-state solves for requests with n > 14 (QNAE_SERVER_HALF)
+    // QNAE_FAULT_INJECT=server_tick:K makes tick K (1-based) fail as a device
+    // error would, before it launches anything: for tests of failure handling.
+    uint64_t fault_tick = 0;
     std::thread worker;
 
     // Footprint blocks of a request (-1: none); false if it can never fit.
@@ -180,6 +185,8 @@ int fail_server(qnae_server* S, int code) {
 // often.
 int qnae_server::tick(std::vector<Request*>& admitted) {
     hipStream_t s = stream;
+    if (fault_tick && ticks + 1 == fault_tick) return fail(QNAE_EHIP, "injected fault at scheduler tick %llu",
+                                                           (unsigned long long)fault_tick);
     Blob B;
     // Host side of new requests: clause records, tables, plans. Tables go
     // through the upload blob; large requests copy them on into their aux
@@ -393,11 +400,14 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
             r.result.expected_cost = hres[3 * q + 1] * sc;
             r.result.norm = hres[3 * q + 2] * sc;
             r.t_done = t;
-            r.state = Request::DONE;
+            r.state = r.cancel ? Request::CANCELED : Request::DONE;  // a cancel promised no result
             release(r);
-            ++completed;
+            if (r.state == Request::DONE) ++completed;
         }
-        active.erase(std::remove_if(active.begin(), active.end(), [](Request* r) { return r->state == Request::DONE; }),
+        active.erase(std::remove_if(active.begin(), active.end(),
+                                    [](Request* r) {
+                                        return r->state == Request::DONE || r->state == Request::CANCELED;
+                                    }),
                      active.end());
         ++ticks;
     }
@@ -413,6 +423,20 @@ void qnae_server::run() {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
             if (queue.empty() && active.empty() && stop) return;
+            // cancelled active requests leave between ticks (no work of theirs is in flight)
+            bool dropped = false;
+            for (Request* r : active)
+                if (r->cancel) {
+                    r->state = Request::CANCELED;
+                    release(*r);
+                    dropped = true;
+                }
+            if (dropped) {
+                active.erase(std::remove_if(active.begin(), active.end(),
+                                            [](Request* r) { return r->state == Request::CANCELED; }),
+                             active.end());
+                cv_done.notify_all();
+            }
             // FIFO admission while a slot and the pool allow it
             while (!queue.empty() && (int)active.size() < max_slots) {
                 Request& r = *queue.front();
@@ -476,6 +500,8 @@ int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qn
     S->max_slots = max_slots;
     S->pool_bytes = 1ull << order;
     if (const char* e = std::getenv("QNAE_SERVER_HALF")) S->use_half = std::atoi(e) != 0;
+    if (const char* e = std::getenv("QNAE_FAULT_INJECT"))
+        if (std::strncmp(e, "server_tick:", 12) == 0) S->fault_tick = std::strtoull(e + 12, nullptr, 10);
     if (const char* e = std::getenv("QNAE_SERVER_TICK_BYTES")) S->tick_bytes = std::max(1.0, std::atof(e));
     HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
     hipError_t e = hipMalloc((void**)&S->pool, S->pool_bytes);
@@ -538,10 +564,16 @@ int qnae_server_wait(qnae_server* S, uint64_t ticket, int32_t timeout_ms, qnae_r
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return fail(QNAE_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
     Request* r = it->second.get();
-    auto ready = [&] { return r->state == Request::DONE || r->state == Request::FAILED; };
+    auto ready = [&] {
+        return r->state == Request::DONE || r->state == Request::FAILED || r->state == Request::CANCELED;
+    };
     if (timeout_ms < 0) S->cv_done.wait(lk, ready);
     else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
         return fail(QNAE_ETIMEDOUT, "ticket %llu not done", (unsigned long long)ticket);
+    if (r->state == Request::CANCELED) {
+        S->all.erase(it);
+        return fail(QNAE_ECANCELED, "ticket %llu was cancelled", (unsigned long long)ticket);
+    }
     if (r->state == Request::FAILED) {
         const std::string msg = S->error_msg;
         S->all.erase(it);
@@ -550,6 +582,34 @@ int qnae_server_wait(qnae_server* S, uint64_t ticket, int32_t timeout_ms, qnae_r
     *out = r->result;
     if (latency_s) *latency_s = r->t_done - r->t_submit;
     S->all.erase(it);
+    return QNAE_OK;
+}
+
+int qnae_server_cancel(qnae_server* S, uint64_t ticket) {
+    if (!S) return fail(QNAE_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(QNAE_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second.get();
+    switch (r->state) {
+        case Request::DONE: return 1;
+        case Request::QUEUED:
+            S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
+            r->state = Request::CANCELED;
+            S->cv_done.notify_all();
+            return QNAE_OK;
+        case Request::ACTIVE:
+            r->cancel = true;  // the scheduler drops it before its next tick
+            S->cv_work.notify_one();
+            return QNAE_OK;
+        default: return QNAE_OK;  // failed or already cancelled: it will not complete
+    }
+}
+
+int qnae_server_pool_in_use(qnae_server* S, uint64_t* bytes) {
+    if (!S || !bytes) return fail(QNAE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    *bytes = S->buddy->used();
     return QNAE_OK;
 }
 

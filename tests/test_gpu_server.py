@@ -163,3 +163,59 @@ def test_serving_trace_sample(q):
         ref = oracle.qaoa(oracle.cost(r["clauses"], r["n"]), r["n"], r["gammas"], r["betas"])
         assert abs(res.p_success - ref[0]) <= 1e-5
         assert abs(res.expected_cost - ref[1]) <= 1e-5 * ref[1]
+
+
+def test_cancel_queued_and_active(q, monkeypatch):
+    """A queued request leaves the queue; an active one is dropped between
+    ticks; both report QNAE_ECANCELED and free their pool blocks; the others
+    complete unchanged."""
+    monkeypatch.setenv("QNAE_SERVER_TICK_BYTES", "1")  # one sweep round per tick: long-lived requests
+    big = requests(1, 21, n_lo=24, n_hi=24, p_hi=0)[0]
+    g = np.linspace(0.1, 0.9, 80)
+    reqs = requests(6, 22, n_lo=15, n_hi=18)
+    with q.Server(pool_bytes=1 << 30, max_slots=1) as s:
+        tb = s.submit(big[3], big[0], g, g[::-1])
+        tickets = [s.submit(r[3], r[0], r[4], r[5]) for r in reqs]
+        assert s.cancel(tickets[-1]) and s.cancel(tickets[-2])  # still queued behind the big one
+        for _ in range(2000):
+            if s.stats()["active"] == 1 and s.stats()["ticks"] > 2:
+                break
+            time.sleep(0.001)
+        assert s.cancel(tb)  # active
+        with pytest.raises(q.QNAEError, match="cancel"):
+            s.wait(tb)
+        for t in tickets[-2:]:
+            with pytest.raises(q.QNAEError, match="cancel"):
+                s.wait(t)
+        got = [s.wait(t)[0] for t in tickets[:-2]]
+        assert s.pool_in_use() == 0
+        done = s.submit(reqs[0][3], reqs[0][0], reqs[0][4], reqs[0][5])
+        s.wait(done)
+        with pytest.raises(q.QNAEError, match="unknown ticket"):
+            s.cancel(done)  # collected: forgotten
+    for r, res in zip(reqs, got):
+        assert close(res, alone(q, r))
+
+
+def test_injected_fault_fails_cleanly(q, monkeypatch):
+    """A device error at a scheduler tick (injected on the host before the tick
+    launches anything) fails every request in flight or queued, frees the
+    pool, and makes later submissions fail; the server still shuts down."""
+    monkeypatch.setenv("QNAE_FAULT_INJECT", "server_tick:3")
+    monkeypatch.setenv("QNAE_SERVER_TICK_BYTES", "1")
+    reqs = requests(8, 23, n_lo=16, n_hi=20, p_hi=6)
+    s = q.Server(pool_bytes=1 << 28, max_slots=3)
+    tickets = [s.submit(r[3], r[0], r[4], r[5]) for r in reqs]
+    outcomes = []
+    for t in tickets:
+        try:
+            s.wait(t, timeout_ms=60000)
+            outcomes.append("ok")
+        except q.QNAEError as e:
+            assert e.status == -3 and "injected" in str(e)
+            outcomes.append("failed")
+    assert "failed" in outcomes
+    assert s.pool_in_use() == 0
+    with pytest.raises(q.QNAEError, match="injected"):
+        s.submit(reqs[0][3], reqs[0][0], reqs[0][4], reqs[0][5])
+    s.close()

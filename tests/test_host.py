@@ -204,3 +204,12 @@ def test_cnf_instance_recipe():
     counts = np.bincount(np.abs(allc).ravel(), minlength=17)[1:]
     assert counts.min() > 0.9 * counts.mean()
     assert np.array_equal(cls[3], inst.cnf_instance(16, 9, 176.9, 3))
+
+
+def test_server_cancel_and_pool_without_gpu():
+    b = _lib_or_skip()
+    lib = b.load_library()
+    assert lib.qnae_server_cancel(None, 1) == -1
+    assert b"null server" in lib.qnae_last_error(None)
+    assert lib.qnae_server_pool_in_use(None, None) == -1
+    assert b._STATUS[-6] == "QNAE_ECANCELED"
