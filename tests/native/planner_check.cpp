@@ -1,0 +1,133 @@
+// Host-side checks of the sweep planner and the clause records of the cost
+// kernel, built with AddressSanitizer and UBSan for the host (no GPU call).
+// Exit status 0 when every check holds.
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "../../paper_2401_02852_amd/csrc/host.h"
+
+using namespace qnae_host;
+
+#define CHECK(c)                                                                   \
+    do {                                                                           \
+        if (!(c)) {                                                                \
+            std::fprintf(stderr, "FAILED %s:%d: %s\n", __FILE__, __LINE__, #c);    \
+            std::exit(1);                                                          \
+        }                                                                          \
+    } while (0)
+
+static int popcount64(uint64_t v) { return __builtin_popcountll(v); }
+
+// Every index bit is mixed by exactly one group; a tile has TB distinct bits
+// below n whose lowest four are x bits 0..3; each layer of a plan mixes every
+// group once, with the phase table of layer l between its mixings.
+static void check_groups_and_plans() {
+    std::vector<qnae::MixForm> forms(8, qnae::MixForm{0.5f, 0});
+    for (int TB = 12; TB <= 14; ++TB)
+        for (int cmin = 4; cmin <= 6; ++cmin)
+            for (int page : {18, 64})
+                for (int n = TB + 1; n <= 34; ++n) {
+                    const std::vector<Group> g = make_groups(n, TB, cmin, page);
+                    uint64_t mixed = 0;
+                    for (const Group& gr : g) {
+                        CHECK((int)gr.pos.size() == TB);
+                        uint64_t seen = 0;
+                        for (int i = 0; i < TB; ++i) {
+                            CHECK(gr.pos[i] >= 0 && gr.pos[i] < n);
+                            CHECK(!((seen >> gr.pos[i]) & 1u));
+                            seen |= 1ull << gr.pos[i];
+                            if (i < 4) CHECK(gr.pos[i] == i);
+                            if ((gr.mask >> i) & 1u) {
+                                CHECK(!((mixed >> gr.pos[i]) & 1u));
+                                mixed |= 1ull << gr.pos[i];
+                            }
+                        }
+                    }
+                    CHECK(mixed == ((n == 64 ? 0ull : 1ull << n) - 1ull));
+                    for (int p : {0, 1, 2, 5}) {
+                        const std::vector<Op> ops = make_plan((int)g.size(), p);
+                        std::vector<int> count((size_t)(p > 0 ? p : 1) * g.size(), 0);
+                        for (const Op& op : ops) {
+                            CHECK(op.group >= 0 && op.group < (int)g.size());
+                            for (int l : {op.pre_layer, op.post_layer})
+                                if (l >= 0) {
+                                    CHECK(l < p);
+                                    ++count[(size_t)l * g.size() + op.group];
+                                }
+                        }
+                        if (p > 0)
+                            for (int c : count) CHECK(c == 1);
+                        // half-state sweeps: the tile index fills n-1-TB stored bits
+                        if (n - 1 > TB && n >= 15) {
+                            SweepPlan P;
+                            plan_sweeps(P, n, 10, p, QNAE_U8, TB, cmin, page, false, forms.data(),
+                                        std::complex<double>(1.0, 0.0));
+                            P.half = true;
+                            for (const Op& op : P.ops) {
+                                qnae::SweepArgs a;
+                                sweep_args(P, op, nullptr, nullptr, nullptr, nullptr, &a);
+                                CHECK(a.half == 1 && a.nw == n - 1 - TB);
+                                CHECK(popcount64(a.wmask) == n - 1 - TB);
+                                CHECK((a.wmask >> (n - 1)) == 0ull && (a.wmask & a.tile_bits) == 0ull);
+                                const Group& gr = P.groups[op.group];
+                                bool has_top = false;
+                                for (int i = 0; i < TB; ++i) has_top |= gr.pos[i] == n - 1;
+                                CHECK(has_top == (a.vbit >= 0));
+                                if (a.vbit >= 0) CHECK(gr.pos[a.vbit] == n - 1);
+                                CHECK(a.mir == (1ull << (n - 1)) - 1ull);
+                            }
+                        }
+                    }
+                }
+}
+
+// The records' tables and masks reproduce the clause predicate at every
+// position of a 32-state run, for random high bits (NAE and k-SAT).
+static void check_clause_records() {
+    std::mt19937_64 rng(7);
+    for (int trial = 0; trial < 4000; ++trial) {
+        const int n = 6 + (int)(rng() % 40), k = 1 + (int)(rng() % 6);
+        std::vector<int32_t> cl(k);
+        for (int j = 0; j < k; ++j) {
+            const int v = 1 + (int)(rng() % n);
+            cl[j] = (rng() & 1u) ? -v : v;
+        }
+        for (int pred : {QNAE_PRED_NAE, QNAE_PRED_SAT}) {
+            qnae::ClauseRec r;
+            const int nrec = make_clause_records(cl.data(), 1, k, &r, pred);
+            for (int rep = 0; rep < 8; ++rep) {
+                const uint64_t xhi = (rng() & ((n >= 64 ? ~0ull : (1ull << n) - 1ull))) & ~31ull;
+                for (uint32_t j = 0; j < 32; ++j) {
+                    const uint64_t x = xhi | j;
+                    int ntrue = 0;
+                    for (int q = 0; q < k; ++q) {
+                        const int v = (cl[q] > 0 ? cl[q] : -cl[q]) - 1;
+                        const int bit = (int)((x >> v) & 1u);
+                        ntrue += cl[q] > 0 ? bit : 1 - bit;
+                    }
+                    const bool want = pred == QNAE_PRED_NAE ? (ntrue == 0 || ntrue == k) : ntrue == 0;
+                    bool got = false;
+                    if (nrec == 1) {
+                        const uint32_t hlo = ((uint32_t)x ^ r.pat_lo) & r.mask_hi_lo;
+                        const uint32_t hhi = ((uint32_t)(x >> 32) ^ r.pat_hi) & r.mask_hi_hi;
+                        const bool none = (hlo | hhi) == 0u;
+                        const bool all = hlo == r.mask_hi_lo && hhi == r.mask_hi_hi;
+                        const uint32_t carry = (none ? r.zero_tab : 0u) | (all ? r.full_tab : 0u);
+                        got = (carry >> j) & 1u;
+                    }
+                    CHECK(got == want);
+                }
+            }
+        }
+    }
+}
+
+int main() {
+    check_groups_and_plans();
+    check_clause_records();
+    std::printf("planner and clause records ok\n");
+    return 0;
+}
