@@ -38,8 +38,15 @@ def build(verbose: bool = False) -> str:
 
     jobs = max(1, min(len(cmds), os.cpu_count() or 1, int(os.environ.get("MAX_JOBS", "16"))))
     with ThreadPoolExecutor(max_workers=jobs) as pool:
-        for f in [pool.submit(compile_one, c) for c in cmds]:
-            f.result()
+        futures = [pool.submit(compile_one, c) for c in cmds]
+        # every compile ends before a failure is raised, so none is left
+        # writing temporaries behind the caller's back
+        errors = [f.exception() for f in futures]
+    if any(errors):
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
+        raise next(e for e in errors if e)
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
