@@ -73,6 +73,28 @@ struct HalfAddr {
     bool tp;  // virtual bit in the thread part
 };
 
+// Waves per SIMD a sweep kernel is register-allocated for. The final kind's
+// plane transposes leave LDS room for 4 workgroups per CU; capping its
+// registers at 3 waves per SIMD keeps most of that (the other kinds fit
+// their LDS-bound occupancy without a cap).
+constexpr int sweep_waves(int kind, bool half) { return kind == SK_FINAL && !half ? 3 : 1; }
+
+// The tile from layout A to layout B through LDS: whole float2 elements, or
+// (PLANES) one component plane after the other in half the LDS. CROSS: the
+// layouts differ in the wave index (workgroup barriers); otherwise each wave
+// stays inside its own quarter of the tile.
+template <int TB, bool PLANES, int A, int B, bool CROSS>
+__device__ __forceinline__ void move(float* lds, float2 (&v)[32], uint32_t lane, uint32_t wave) {
+    if constexpr (PLANES) {
+        relayout<TB, A, B, CROSS>(lds, v, lane, wave);
+    } else {
+        to_lds<TB, A>((float2*)lds, v, lane, wave);
+        if (CROSS) __syncthreads();
+        else wave_lds_sync();
+        from_lds<TB, B>((const float2*)lds, v, lane, wave);
+    }
+}
+
 // One workgroup's work on tile t of one sweep. Readout kinds write the three
 // block sums to partial[0..2].
 template <int TB, typename CT, int KIND, bool HALF>
@@ -85,13 +107,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     constexpr bool POST = KIND == SK_FIRST || KIND == SK_BOUNDARY;
     constexpr bool REDUCE = KIND == SK_FINAL || KIND == SK_P0;
     constexpr bool STREAM = KIND == SK_MIDDLE || KIND == SK_FINAL;
+    // Kinds that move state one way (only stored, or only read for the
+    // readout) gain from more resident workgroups: their transposes go
+    // through LDS one component plane at a time.
+    // (Half-state final sweeps need too many registers for that to pay.)
+    constexpr bool PLANES = KIND == SK_FIRST || (KIND == SK_FINAL && !HALF);
+    // Straight-line butterflies in the kinds that mix the tile once and hold
+    // no readout state: measured faster there (the boundary kind measured
+    // slower, and the final kind needs the registers).
+    constexpr bool UNCOND = KIND == SK_FIRST || KIND == SK_MIDDLE;
     constexpr bool NEED_COST = INIT || PHASE || REDUCE;
     constexpr bool NEED_LUT = INIT || PHASE;
     constexpr bool LUT_LDS = sizeof(CT) == 1;
     constexpr int PK = 4 / (int)sizeof(CT);  // cost values per packed register
     constexpr int NC = NEED_COST ? 32 / PK : 1;
     using L = Lay<TB>;
-    __shared__ float2 lds[lds_elems<TB>()];
+    __shared__ __align__(16) float lds[PLANES ? plane_elems<TB>() : 2 * lds_elems<TB>()];
     __shared__ float2 lut_s[NEED_LUT && LUT_LDS ? 256 : 1];
     __shared__ double red[3][1 << WB];
 
@@ -212,18 +243,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     if (PRE) {
         const uint32_t m = a.pre_mask;
         const float tt = a.pre_t;
-        mix32(v, L::sm0(m), tt);
-        to_lds<TB, 0>(lds, v, lane, wave);
+        mix32<UNCOND>(v, L::sm0(m), tt);
         if (L::sm1(m)) {
-            wave_lds_sync();  // L0 -> L1 stays inside the wave's quarter
-            from_lds<TB, 1>(lds, v, lane, wave);
-            mix32(v, L::sm1(m), tt);
+            move<TB, PLANES, 0, 1, false>(lds, v, lane, wave);  // inside the wave's quarter
+            mix32<UNCOND>(v, L::sm1(m), tt);
             wave_lds_sync();
-            to_lds<TB, 1>(lds, v, lane, wave);
+            move<TB, PLANES, 1, 2, true>(lds, v, lane, wave);
+        } else {
+            move<TB, PLANES, 0, 2, true>(lds, v, lane, wave);
         }
-        __syncthreads();
-        from_lds<TB, 2>(lds, v, lane, wave);
-        mix32(v, L::sm2(m), tt);
+        mix32<UNCOND>(v, L::sm2(m), tt);
     }
     if (PHASE) {
 #pragma unroll
@@ -232,19 +261,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     if (POST) {
         const uint32_t m = a.post_mask;
         const float tt = a.post_t;
-        mix32(v, L::sm2(m), tt);
-        if (PRE) __syncthreads();
-        to_lds<TB, 2>(lds, v, lane, wave);
-        __syncthreads();
+        mix32<UNCOND>(v, L::sm2(m), tt);
+        if (PRE) __syncthreads();  // every wave has read its L2 part
         if (L::sm1(m)) {
-            from_lds<TB, 1>(lds, v, lane, wave);
-            mix32(v, L::sm1(m), tt);
-            wave_lds_sync();  // L1 -> L0 stays inside the wave's quarter
-            to_lds<TB, 1>(lds, v, lane, wave);
+            move<TB, PLANES, 2, 1, true>(lds, v, lane, wave);
+            mix32<UNCOND>(v, L::sm1(m), tt);
             wave_lds_sync();
+            move<TB, PLANES, 1, 0, false>(lds, v, lane, wave);  // inside the wave's quarter
+        } else {
+            move<TB, PLANES, 2, 0, true>(lds, v, lane, wave);
         }
-        from_lds<TB, 0>(lds, v, lane, wave);
-        mix32(v, L::sm0(m), tt);
+        mix32<UNCOND>(v, L::sm0(m), tt);
         if (HALF) {
             const HalfAddr h = haddr(L::t0(lane, wave));
 #pragma unroll
@@ -310,7 +337,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
 
 // One sweep over one state: block b handles tile b.
 template <int TB, typename CT, int KIND, bool HALF = false>
-__global__ __launch_bounds__(64 << (TB - 11)) void sweep_kernel(const SweepArgs a) {
+__global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(KIND, HALF)))) void sweep_kernel(
+    const SweepArgs a) {
     sweep_tile<TB, CT, KIND, HALF>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
 }
 
@@ -328,7 +356,7 @@ __device__ __forceinline__ int batch_item(const uint32_t* first, int count, uint
 // One sweep step over many states at once (ragged): instance i owns blocks
 // first[i] .. first[i+1]-1, one per tile, with its own arguments.
 template <int TB, typename CT, int KIND, bool HALF>
-__global__ __launch_bounds__(64 << (TB - 11)) void sweep_batch_kernel(const SweepArgs* args, const uint32_t* first,
+__global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(KIND, HALF)))) void sweep_batch_kernel(const SweepArgs* args, const uint32_t* first,
                                                                       int count) {
     const int i = batch_item(first, count, blockIdx.x);
     const SweepArgs a = args[i];

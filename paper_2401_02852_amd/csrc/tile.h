@@ -25,7 +25,20 @@ __device__ __forceinline__ void bfly(float2 (&v)[NE], float t) {
     }
 }
 
+// Butterflies on the register bits set in sm. UNCOND: all five run, with
+// t = 0 (an exact identity) on the bits not in sm; straight-line code lets the
+// compiler rename registers instead of copying each butterfly's results back
+// for the next conditional block, which measured faster where most bits mix.
+template <bool UNCOND = false>
 __device__ __forceinline__ void mix32(float2 (&v)[32], uint32_t sm, float t) {
+    if (UNCOND) {
+        bfly<32, 0>(v, (sm & 1u) ? t : 0.f);
+        bfly<32, 1>(v, (sm & 2u) ? t : 0.f);
+        bfly<32, 2>(v, (sm & 4u) ? t : 0.f);
+        bfly<32, 3>(v, (sm & 8u) ? t : 0.f);
+        bfly<32, 4>(v, (sm & 16u) ? t : 0.f);
+        return;
+    }
     if (sm & 1u) bfly<32, 0>(v, t);
     if (sm & 2u) bfly<32, 1>(v, t);
     if (sm & 4u) bfly<32, 2>(v, t);
@@ -167,6 +180,104 @@ __device__ __forceinline__ void from_lds(const float2* lds, float2 (&v)[32], uin
 #pragma unroll
         for (int j = 0; j < 32; ++j) v[j] = p[phys(L::s2(j))];
     }
+}
+
+// Plane transposes: the real parts of a tile go through LDS first, then the
+// imaginary parts, so a tile needs a float per element instead of a float2
+// and twice as many workgroups fit in a CU's LDS. Element e sits at float
+// physf(e) = e + sum of c_i over the set bits i >= 6 of e. The coefficients
+// are non-decreasing sums (so the map is one-to-one) chosen so that, with
+// 64 four-byte banks, every b32 access of 64 lanes in layouts L1 and L2 and
+// every b64 access of 32 lanes in layout L0 hits 64 distinct banks; L0 pairs
+// (tile bit 0) stay adjacent because bit 0 carries no padding.
+template <int TB>
+struct PlanePad;
+template <>
+struct PlanePad<12> {
+    static constexpr uint32_t c[6] = {2, 4, 16, 32, 72, 126};
+};
+template <>
+struct PlanePad<13> {
+    static constexpr uint32_t c[7] = {2, 16, 32, 68, 136, 254, 508};
+};
+template <>
+struct PlanePad<14> {
+    static constexpr uint32_t c[8] = {2, 4, 8, 16, 32, 64, 128, 256};
+};
+template <int TB>
+__device__ __forceinline__ constexpr uint32_t physf(uint32_t e) {
+    uint32_t p = e;
+    for (int i = 6; i < TB; ++i) p += ((e >> i) & 1u) * PlanePad<TB>::c[i - 6];
+    return p;
+}
+template <int TB>
+constexpr uint32_t plane_elems() {
+    uint32_t p = (1u << TB) - 1u;
+    for (int i = 6; i < TB; ++i) p += PlanePad<TB>::c[i - 6];
+    return p + 1u;
+}
+
+template <int C>
+__device__ __forceinline__ float part(const float2& a) { return C == 0 ? a.x : a.y; }
+template <int C>
+__device__ __forceinline__ void set_part(float2& a, float x) {
+    if (C == 0) a.x = x;
+    else a.y = x;
+}
+
+// Component C (0 real, 1 imaginary) of the tile in layout LAYOUT to LDS.
+template <int TB, int LAYOUT, int C>
+__device__ __forceinline__ void to_plane(float* lds, const float2 (&v)[32], uint32_t lane, uint32_t wave) {
+    using L = Lay<TB>;
+    if (LAYOUT == 0) {
+        float* const p = lds + physf<TB>(L::t0(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) p[physf<TB>(L::s0(j))] = part<C>(v[j]);
+    } else if (LAYOUT == 1) {
+        float* const p = lds + physf<TB>(L::t1(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) p[physf<TB>(L::s1(j))] = part<C>(v[j]);
+    } else {
+        float* const p = lds + physf<TB>(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) p[physf<TB>(L::s2(j))] = part<C>(v[j]);
+    }
+}
+
+template <int TB, int LAYOUT, int C>
+__device__ __forceinline__ void from_plane(const float* lds, float2 (&v)[32], uint32_t lane, uint32_t wave) {
+    using L = Lay<TB>;
+    if (LAYOUT == 0) {
+        const float* const p = lds + physf<TB>(L::t0(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) set_part<C>(v[j], p[physf<TB>(L::s0(j))]);
+    } else if (LAYOUT == 1) {
+        const float* const p = lds + physf<TB>(L::t1(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) set_part<C>(v[j], p[physf<TB>(L::s1(j))]);
+    } else {
+        const float* const p = lds + physf<TB>(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) set_part<C>(v[j], p[physf<TB>(L::s2(j))]);
+    }
+}
+
+// The tile from layout A to layout B, one plane after the other. CROSS: the
+// layouts differ in the wave index, so waves exchange data (workgroup
+// barriers); otherwise each wave stays inside its own quarter. The caller
+// orders this against earlier LDS reads of the buffer by other waves.
+template <int TB, int A, int B, bool CROSS>
+__device__ __forceinline__ void relayout(float* lds, float2 (&v)[32], uint32_t lane, uint32_t wave) {
+    to_plane<TB, A, 0>(lds, v, lane, wave);
+    if (CROSS) __syncthreads();
+    else wave_lds_sync();
+    from_plane<TB, B, 0>(lds, v, lane, wave);
+    if (CROSS) __syncthreads();
+    else wave_lds_sync();
+    to_plane<TB, A, 1>(lds, v, lane, wave);
+    if (CROSS) __syncthreads();
+    else wave_lds_sync();
+    from_plane<TB, B, 1>(lds, v, lane, wave);
 }
 
 }  // namespace tile
