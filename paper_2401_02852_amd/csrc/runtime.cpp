@@ -217,11 +217,13 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
 // Bits at or above `page` select a 2 MiB page of the state (8-byte
 // amplitudes); a tile that spans k of them touches 2^k pages, so these bits
 // are dealt out evenly over the groups to keep every tile within a few TLB
-// entries. Group A takes the lowest page bits; the others take consecutive
-// runs of the rest, and of the bits below `page`, in ascending order. Of the
-// layouts measured at n = 30 (13-bit tiles), this one ran the sweeps that
-// carry the phase fastest (2% on the whole run over dealing page bits out
-// round-robin with the top ones in group A).
+// entries. Group A takes the top page bits. The other groups take
+// consecutive runs of the bits below `page` in ascending order, and
+// consecutive runs of the remaining page bits in descending order, so the
+// group with the lowest middle bits gets the highest page run. Measured at
+// n = 30 (13-bit tiles): a tile that mixes index bits 14..17 together with
+// page bits streams slowest, least so beside bits 18..21; this arrangement
+// ran 3% faster than dealing the page bits out round-robin.
 std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
     std::vector<Group> g;
     Group A;
@@ -238,7 +240,7 @@ std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
     const int target = ((int)P.size() + h) / (h + 1);
     const int a = std::min(std::min(target, TB - cmin), (int)P.size());
     const int cA = TB - a;
-    std::vector<int> apage(P.begin(), P.begin() + a);
+    std::vector<int> apage(P.end() - a, P.end());
     for (int i = 0; i < cA; ++i) A.pos.push_back(i);
     for (int b : apage) A.pos.push_back(b);
     A.mask = (1u << TB) - 1u;
@@ -253,8 +255,11 @@ std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
     std::vector<std::vector<int>> piece(h);
     std::vector<int> size(h);
     for (int i = 0; i < h; ++i) size[i] = R / h + (i < R % h ? 1 : 0);
-    for (int i = 0, q = 0; i < h; ++i)  // consecutive page bits, evenly
-        for (int c = 0; c < (int)RP.size() / h + (i < (int)RP.size() % h ? 1 : 0); ++c) piece[i].push_back(RP[q++]);
+    for (int i = 0, q = (int)RP.size(); i < h; ++i) {  // consecutive page runs, evenly, top run first
+        const int c = (int)RP.size() / h + (i < (int)RP.size() % h ? 1 : 0);
+        q -= c;
+        for (int k = 0; k < c; ++k) piece[i].push_back(RP[q + k]);
+    }
     size_t nx = 0;
     for (int i = 0; i < h; ++i)
         while ((int)piece[i].size() < size[i]) piece[i].push_back(RN[nx++]);
