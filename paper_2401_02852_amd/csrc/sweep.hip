@@ -33,39 +33,24 @@ using namespace tile;
 // (fwd = base + unit bits of te), and when the virtual bit of e is set the
 // index is mirrored, mir - (fwd + unit bits of se). HALF = false: plain
 // additive addresses.
-// The middle and final kinds stream the state through nontemporal loads and
-// stores: each amplitude is touched once per sweep, and keeping it out of the
-// caches' normal replacement measured faster for them. The first and boundary
-// kinds keep ordinary accesses, which measured faster there (their cost byte
-// reads share the caches with the state stream).
+// Every sweep streams the state through nontemporal loads and stores: each
+// amplitude is touched once per sweep, and keeping it out of the caches'
+// normal replacement measured faster in every kind (with the current qubit
+// groups; the cost bytes, which neighbouring tiles share in the L2, keep
+// ordinary loads).
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
-template <bool NT>
 __device__ __forceinline__ float4 ld_state(const float2* p) {
-    if constexpr (NT) {
-        const f4v v = __builtin_nontemporal_load((const f4v*)p);
-        return make_float4(v.x, v.y, v.z, v.w);
-    } else {
-        return *(const float4*)p;
-    }
+    const f4v v = __builtin_nontemporal_load((const f4v*)p);
+    return make_float4(v.x, v.y, v.z, v.w);
 }
-template <bool NT>
 __device__ __forceinline__ void st_state(float2* p, float4 q) {
-    if constexpr (NT) {
-        f4v v = {q.x, q.y, q.z, q.w};
-        __builtin_nontemporal_store(v, (f4v*)p);
-    } else {
-        *(float4*)p = q;
-    }
+    f4v v = {q.x, q.y, q.z, q.w};
+    __builtin_nontemporal_store(v, (f4v*)p);
 }
-template <bool NT>
 __device__ __forceinline__ void st_state(float2* p, float2 q) {
-    if constexpr (NT) {
-        f2v v = {q.x, q.y};
-        __builtin_nontemporal_store(v, (f2v*)p);
-    } else {
-        *p = q;
-    }
+    f2v v = {q.x, q.y};
+    __builtin_nontemporal_store(v, (f2v*)p);
 }
 
 struct HalfAddr {
@@ -106,7 +91,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     constexpr bool PHASE = KIND == SK_BOUNDARY;
     constexpr bool POST = KIND == SK_FIRST || KIND == SK_BOUNDARY;
     constexpr bool REDUCE = KIND == SK_FINAL || KIND == SK_P0;
-    constexpr bool STREAM = KIND == SK_MIDDLE || KIND == SK_FINAL;
     // Kinds that move state one way (only stored, or only read for the
     // readout) gain from more resident workgroups: their transposes go
     // through LDS one component plane at a time.
@@ -227,7 +211,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
             const uint32_t se = L::s0(2 * jj);
             const bool neg = h.tp != vpar(se);
             const uint64_t so = scat(se);
-            const float4 q = ld_state<STREAM>(a.psi_in + (neg ? h.mir - so - 1ull : h.fwd + so));
+            const float4 q = ld_state(a.psi_in + (neg ? h.mir - so - 1ull : h.fwd + so));
             v[2 * jj] = neg ? make_float2(q.z, q.w) : make_float2(q.x, q.y);
             v[2 * jj + 1] = neg ? make_float2(q.x, q.y) : make_float2(q.z, q.w);
         }
@@ -235,7 +219,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         const float2* const p0 = a.psi_in + base + scat(L::t0(lane, wave));
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
-            const float4 q = ld_state<STREAM>(p0 + scat(L::s0(2 * jj)));
+            const float4 q = ld_state(p0 + scat(L::s0(2 * jj)));
             v[2 * jj] = make_float2(q.x, q.y);
             v[2 * jj + 1] = make_float2(q.z, q.w);
         }
@@ -280,14 +264,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
                 const bool neg = h.tp != vpar(se);
                 const uint64_t so = scat(se);
                 const float2 lo = neg ? v[2 * jj + 1] : v[2 * jj], hi = neg ? v[2 * jj] : v[2 * jj + 1];
-                st_state<STREAM>(a.psi + (neg ? h.mir - so - 1ull : h.fwd + so), make_float4(lo.x, lo.y, hi.x, hi.y));
+                st_state(a.psi + (neg ? h.mir - so - 1ull : h.fwd + so), make_float4(lo.x, lo.y, hi.x, hi.y));
             }
             return;
         }
         float2* const p0 = a.psi + base + scat(L::t0(lane, wave));
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj)
-            st_state<STREAM>(p0 + scat(L::s0(2 * jj)), make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y));
+            st_state(p0 + scat(L::s0(2 * jj)), make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y));
         return;
     }
     if (REDUCE) {
@@ -326,11 +310,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         if (HALF) {
             const HalfAddr h = haddr(L::t2(lane, wave));
 #pragma unroll
-            for (int j = 0; j < 32; ++j) st_state<STREAM>(a.psi + hidx(h, L::s2(j)), v[j]);
+            for (int j = 0; j < 32; ++j) st_state(a.psi + hidx(h, L::s2(j)), v[j]);
         } else {
             float2* const p2 = a.psi + base + scat(L::t2(lane, wave));
 #pragma unroll
-            for (int j = 0; j < 32; ++j) st_state<STREAM>(p2 + scat(L::s2(j)), v[j]);
+            for (int j = 0; j < 32; ++j) st_state(p2 + scat(L::s2(j)), v[j]);
         }
     }
 }
