@@ -6,9 +6,10 @@
 // clause on variables >= 5 is constant over the run (one compare against the
 // thread's index), and the part on variables 0..4 is a per-clause table built
 // on the host. The per-state counters are kept as NP bit-planes (a vertical
-// ripple-carry counter), so one clause costs about 2 NP + 6 integer operations
-// per 32 states. At the end the planes are transposed into bytes (uint8) or
-// half-words (uint16) and written with 16-byte stores.
+// counter); clauses go in eight at a time through a carry-save adder tree, so
+// one clause costs about 9 integer operations per 32 states. At the end the
+// planes are transposed into bytes (uint8) or half-words (uint16) and written
+// with 16-byte stores.
 #include "internal.h"
 
 namespace qnae {
@@ -25,7 +26,8 @@ __device__ __forceinline__ void cost_chunk(const CostArgs& a, uint64_t tid) {
         uint32_t plane[NP];
 #pragma unroll
         for (int b = 0; b < NP; ++b) plane[b] = 0u;
-        for (int i = 0; i < a.num_clauses; ++i) {
+        // Violation word of clause i over the 32 states.
+        auto viol = [&](int i) -> uint32_t {
             const ClauseRec r = a.clauses[i];
             const uint32_t hlo = (xlo ^ r.pat_lo) & r.mask_hi_lo;
             bool none, all;
@@ -37,14 +39,40 @@ __device__ __forceinline__ void cost_chunk(const CostArgs& a, uint64_t tid) {
                 none = hlo == 0u;
                 all = hlo == r.mask_hi_lo;
             }
-            uint32_t carry = (none ? r.zero_tab : 0u) | (all ? r.full_tab : 0u);
+            return (none ? r.zero_tab : 0u) | (all ? r.full_tab : 0u);
+        };
+        // Adds carry * 2^b0 to the counter (ripple through the planes above).
+        auto add_at = [&](int b0, uint32_t carry) {
 #pragma unroll
             for (int b = 0; b < NP; ++b) {
+                if (b < b0) continue;
                 const uint32_t t = plane[b] & carry;
                 plane[b] ^= carry;
                 carry = t;
             }
+        };
+        // Full adder per bit: x + p + q = x' + 2 carry.
+        auto csa = [](uint32_t& x, uint32_t p, uint32_t q) -> uint32_t {
+            const uint32_t t = x ^ p;
+            const uint32_t carry = (t & q) | (~t & x);
+            x = t ^ q;
+            return carry;
+        };
+        // Eight clauses at a time through a carry-save tree (7 full adders
+        // into the planes of weight 1, 2 and 4, one ripple from weight 8):
+        // the counter value after the block is exactly the sum it had plus
+        // the eight violation bits, per state.
+        int i = 0;
+        for (; i + 8 <= a.num_clauses; i += 8) {
+            const uint32_t c2a = csa(plane[0], viol(i), viol(i + 1));
+            const uint32_t c2b = csa(plane[0], viol(i + 2), viol(i + 3));
+            const uint32_t c2c = csa(plane[0], viol(i + 4), viol(i + 5));
+            const uint32_t c2d = csa(plane[0], viol(i + 6), viol(i + 7));
+            const uint32_t c4a = csa(plane[1], c2a, c2b);
+            const uint32_t c4b = csa(plane[1], c2c, c2d);
+            add_at(3, csa(plane[2], c4a, c4b));
         }
+        for (; i < a.num_clauses; ++i) add_at(0, viol(i));
         const uint32_t valid = a.n >= 5 ? 0xffffffffu : ((1u << (1u << a.n)) - 1u);
         uint32_t any = 0u;
 #pragma unroll
