@@ -21,6 +21,8 @@
 // The butterfly on a pair (a, b) is own' = own - i t partner (two FMAs per
 // amplitude); see MixForm for how t, the dropped X and the scalar factor
 // encode R(beta) = cos(beta) I - i sin(beta) X.
+#include <type_traits>
+
 #include "tile.h"
 
 namespace qnae {
@@ -100,6 +102,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     // no readout state: measured faster there (the boundary kind measured
     // slower, and the final kind needs the registers).
     constexpr bool UNCOND = KIND == SK_FIRST || KIND == SK_MIDDLE;
+    // The first sweep (no cost flip) of a group without the virtual bit reads
+    // its costs in layout L0 and mixes L0, L1, L2 in that order (see below).
+    // Decided the same way in half and full kernels, whose addressing agrees
+    // for such groups, so both give the same rounding.
     constexpr bool NEED_COST = INIT || PHASE || REDUCE;
     constexpr bool NEED_LUT = INIT || PHASE;
     constexpr bool LUT_LDS = sizeof(CT) == 1;
@@ -121,6 +127,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     // selects the mirrored address instead.
     // (a half sweep whose group lacks bit n-1 has vbit < 0: plain addresses)
     const bool has_v = HALF && a.vbit >= 0;
+    const bool first_l0 = KIND == SK_FIRST && !has_v;
     const uint32_t vb = has_v ? (uint32_t)a.vbit : 0u;
     uint64_t bitval[TB];
 #pragma unroll
@@ -161,7 +168,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     // true one with every qubit flipped (see MixForm), so cost values are read
     // at the complemented index: complemented tile base, thread part and slot.
     uint32_t cvp[NC];
-    if (NEED_COST && HALF) {
+    if (NEED_COST && HALF && !first_l0) {
         // symmetric cost: no complemented reads, mirrored indices instead
         const HalfAddr h = haddr(L::t2(lane, wave));
         const CT* const cp = (const CT*)a.cost;
@@ -174,7 +181,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         }
         if (NEED_LUT && LUT_LDS)
             for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
-    } else if (NEED_COST) {
+    } else if (NEED_COST && !first_l0) {
         const bool cf = a.cflip != 0;
         const uint64_t cbase = cf ? base ^ ((((uint64_t)1 << a.n) - 1ull) ^ a.tile_bits) : base;
         const uint32_t ct = cf ? L::t2(lane, wave) ^ L::t2(63u, (1u << WB) - 1u) : L::t2(lane, wave);
@@ -196,6 +203,45 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     auto cval = [&](int j) -> uint32_t {
         return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
     };
+
+    if (KIND == SK_FIRST && first_l0) {
+        // In layout L0 the pair of a thread's slots along tile bit 0 are
+        // adjacent costs, and the 64 lanes cover tile bits 1..6, so a wave
+        // reads 128 consecutive cost bytes per load (layout L2 reads four
+        // runs of 16). The tile is then mixed in L0, L1, L2 and stored from
+        // L2; the order of the mixings within a layer does not matter.
+        using PT = typename std::conditional<sizeof(CT) == 1, uint16_t, uint32_t>::type;
+        const CT* const c0 = (const CT*)a.cost + base + scat(L::t0(lane, wave));
+        PT cp[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) cp[jj] = *(const PT*)(c0 + scat(L::s0(2 * jj)));
+        if (LUT_LDS)
+            for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
+        __syncthreads();  // phase table visible
+        constexpr uint32_t CB = 8 * sizeof(CT);
+        float2 v[32];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            v[2 * jj] = lut((uint32_t)cp[jj] & ((1u << CB) - 1u));
+            v[2 * jj + 1] = lut((uint32_t)cp[jj] >> CB);
+        }
+        const uint32_t m = a.post_mask;
+        const float tt = a.post_t;
+        mix32<UNCOND>(v, L::sm0(m), tt);
+        if (L::sm1(m)) {
+            move<TB, PLANES, 0, 1, false>(lds, v, lane, wave);  // inside the wave's quarter
+            mix32<UNCOND>(v, L::sm1(m), tt);
+            wave_lds_sync();
+            move<TB, PLANES, 1, 2, true>(lds, v, lane, wave);
+        } else {
+            move<TB, PLANES, 0, 2, true>(lds, v, lane, wave);
+        }
+        mix32<UNCOND>(v, L::sm2(m), tt);
+        float2* const p2 = a.psi + base + scat(L::t2(lane, wave));
+#pragma unroll
+        for (int j = 0; j < 32; ++j) st_state(p2 + scat(L::s2(j)), v[j]);
+        return;
+    }
 
     float2 v[32];
     if (INIT) {
