@@ -59,9 +59,10 @@ def _load():
                                                 _U64P]
     lib.oracle_sample.argtypes = [ctypes.c_int, _F64P, _F64P, ctypes.c_int64, _U64P]
     lib.oracle_num_threads.argtypes = []
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     for fn in (lib.oracle_cost, lib.oracle_cost_at, lib.oracle_count_solutions, lib.oracle_state,
                lib.oracle_qaoa, lib.oracle_qaoa_grad, lib.oracle_num_threads, lib.oracle_cost_pred,
-               lib.oracle_cost_at_pred, lib.oracle_count_solutions_pred, lib.oracle_sample):
+               lib.oracle_cost_at_pred, lib.oracle_count_solutions_pred, lib.oracle_sample, lib.oracle_set_threads):
         fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -220,3 +221,8 @@ def finite_difference_grad(cost_arr, n: int, gammas, betas, w_psucc=1.0, w_energ
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_threads(threads: int) -> int:
+    """OpenMP threads for the following oracle calls; returns the count in effect."""
+    return int(_load().oracle_set_threads(int(threads)))

@@ -418,3 +418,15 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads for the following calls (timing of the oracle itself); returns the
+   number now in effect. */
+int oracle_set_threads(int threads) {
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+    return omp_get_max_threads();
+#else
+    (void)threads;
+    return 1;
+#endif
+}
