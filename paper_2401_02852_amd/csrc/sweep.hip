@@ -141,9 +141,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     };
     // Consecutive tiles go to one XCD (blocks are dealt round-robin over the
     // 8 XCDs), so tiles that share cache lines of the cost diagonal share an
-    // L2. The tile index is deposited into the bits outside the tile (scalar
-    // ALU only).
-    uint64_t w = ntiles >= 8 ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
+    // L2: each XCD takes one contiguous eighth of the tiles, except in the
+    // boundary kind, where each XCD takes every eighth chunk of 32
+    // consecutive tiles, so the 8 XCDs work on neighbouring chunks at once
+    // (measured faster there: 3.41 -> 3.29 ms at n = 30; slower for the
+    // middle kind). The tile index is deposited into the bits outside the
+    // tile (scalar ALU only).
+    constexpr uint32_t kChunk = 32;
+    uint64_t w = (KIND == SK_BOUNDARY && ntiles >= 8 * kChunk)
+                     ? (uint64_t)((t >> 3) / kChunk) * (8 * kChunk) + (uint64_t)(t & 7u) * kChunk + ((t >> 3) % kChunk)
+                 : ntiles >= 8 ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3)
+                               : (uint64_t)t;
     uint64_t base = 0;
     for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull) {
         if (w & 1ull) base |= m & (~m + 1ull);
