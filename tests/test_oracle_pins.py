@@ -517,3 +517,23 @@ def test_sample_frequencies_and_running_time():
     assert oracle.running_time(s[c[s] > 0], c) == 0
     mean = np.mean(runs)
     assert abs(mean - 1 / ps) <= 5 * np.sqrt((1 - ps) / ps ** 2 / len(runs)), (mean, 1 / ps)
+
+
+def test_oracle_threads_do_not_change_results():
+    """The state update is elementwise, so any thread count gives the same
+    state bit for bit; the readout sums differ only in rounding order."""
+    cl = inst.instance(12, 3, 25, 3)
+    c = oracle.cost(cl, 12)
+    g, b = inst.ramp_angles(3)
+    threads = oracle.num_threads()
+    try:
+        assert oracle.set_threads(1) == 1
+        s1 = oracle.state(c, 12, g, b)
+        r1 = oracle.qaoa(c, 12, g, b)
+    finally:
+        oracle.set_threads(threads)
+    assert oracle.num_threads() == threads
+    sn = oracle.state(c, 12, g, b)
+    rn = oracle.qaoa(c, 12, g, b)
+    assert np.array_equal(s1, sn)
+    assert np.allclose(r1, rn, rtol=1e-13, atol=1e-16)
