@@ -52,6 +52,33 @@ _I32P = ctypes.POINTER(ctypes.c_int32)
 _F64P = ctypes.POINTER(ctypes.c_double)
 
 
+def _np_view(carr, cls):
+    """A numpy structured view of a ctypes array of `cls` (pointer fields as
+    uint64 addresses), for filling many records without a Python loop."""
+    kinds = {ctypes.c_int32: np.int32, ctypes.c_double: np.float64, ctypes.c_uint64: np.uint64}
+    names, formats, offsets = [], [], []
+    for fname, ftype in cls._fields_:
+        names.append(fname)
+        formats.append(kinds.get(ftype, np.uint64))
+        offsets.append(getattr(cls, fname).offset)
+    dt = np.dtype({"names": names, "formats": formats, "offsets": offsets, "itemsize": ctypes.sizeof(cls)})
+    return np.frombuffer(carr, dtype=dt)
+
+
+def _packed_angles(values, name):
+    """Concatenated float64 angles of every item, their offsets and counts."""
+    arrs = []
+    for i, x in enumerate(values):
+        a = np.asarray(x, dtype=np.float64)
+        if a.ndim > 1:
+            raise ValueError(f"instance {i}: {name} must be 1-D")
+        arrs.append(a.reshape(-1))
+    counts = np.fromiter((a.shape[0] for a in arrs), dtype=np.int64, count=len(arrs))
+    offsets = np.concatenate(([0], np.cumsum(counts)[:-1])) if len(arrs) else np.zeros(0, dtype=np.int64)
+    flat = np.ascontiguousarray(np.concatenate(arrs)) if counts.sum() else np.zeros(1)
+    return flat, offsets.astype(np.uint64), counts
+
+
 class _CGradJob(ctypes.Structure):
     _fields_ = [("cost_dev", ctypes.c_void_p), ("cost_dtype", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("gammas", _F64P), ("betas", _F64P),
@@ -326,27 +353,37 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     if outs is None:
         outs = [torch.empty(1 << (n - (1 if hf else 0)), dtype=cost_dtype_for(a.shape[0]), device="cuda")
                 for a, n, hf in zip(arrs, ns, halves)]
-    jobs = (_CCostJob * len(arrs))()
-    sols = [ctypes.c_uint64(0) for _ in arrs]
-    preds = [predicate] * len(arrs) if isinstance(predicate, str) else list(predicate)
-    if len(preds) != len(arrs):
+    count = len(arrs)
+    preds = [predicate] * count if isinstance(predicate, str) else list(predicate)
+    if len(preds) != count:
         raise ValueError("predicate list and clause_sets differ in length")
-    for i, (a, n, o) in enumerate(zip(arrs, ns, outs)):
-        if a.ndim != 2:
-            raise ValueError("clauses must be [m, k] literal arrays")
-        m, k = a.shape
-        jobs[i].clauses = a.ctypes.data_as(_I32P) if m else None
-        jobs[i].m, jobs[i].n, jobs[i].k = m, int(n), max(k, 1)
-        jobs[i].cost_dev = o.data_ptr()
-        jobs[i].cost_dtype = QNAE_U8 if o.dtype == torch.uint8 else QNAE_U16
-        jobs[i].num_solutions = ctypes.pointer(sols[i]) if count_solutions else None
-        jobs[i].predicate = _pred_code(preds[i])
-        jobs[i].half = 1 if halves[i] else 0
-        if o.numel() != (1 << (int(n) - jobs[i].half)):
-            raise ValueError(f"job {i}: cost has {o.numel()} entries, expected 2^{int(n) - jobs[i].half}")
+    if any(a.ndim != 2 for a in arrs):
+        raise ValueError("clauses must be [m, k] literal arrays")
+    mk = np.array([a.shape for a in arrs], dtype=np.int64).reshape(count, 2)
+    hv = np.asarray(halves, dtype=bool)
+    nv = np.asarray(ns, dtype=np.int64).reshape(count)
+    numel = np.fromiter((o.numel() for o in outs), dtype=np.int64, count=count)
+    bad = np.nonzero(numel != np.left_shift(np.int64(1), nv - hv))[0]
+    if bad.size:
+        i = int(bad[0])
+        raise ValueError(f"job {i}: cost has {int(numel[i])} entries, expected 2^{int(nv[i] - hv[i])}")
+    sols = np.zeros(max(count, 1), dtype=np.uint64)
+    jobs = (_CCostJob * count)()
+    v = _np_view(jobs, _CCostJob)
+    v["clauses"] = np.fromiter((a.ctypes.data if a.shape[0] else 0 for a in arrs), dtype=np.uint64, count=count)
+    v["m"] = mk[:, 0]
+    v["n"] = nv
+    v["k"] = np.maximum(mk[:, 1], 1)
+    v["cost_dev"] = np.fromiter((o.data_ptr() for o in outs), dtype=np.uint64, count=count)
+    v["cost_dtype"] = np.fromiter((QNAE_U8 if o.dtype == torch.uint8 else QNAE_U16 for o in outs), dtype=np.int32,
+                                  count=count)
+    v["num_solutions"] = (np.uint64(sols.ctypes.data) + np.uint64(8) * np.arange(count, dtype=np.uint64)
+                          if count_solutions else np.uint64(0))
+    v["predicate"] = np.fromiter((_pred_code(x) for x in preds), dtype=np.int32, count=count)
+    v["half"] = hv
     ctx = ctx or default_context()
-    _check(load_library().qnae_build_cost_diagonal_batched(ctx.handle, jobs, len(arrs), _stream(stream)))
-    return (outs, [int(v.value) for v in sols]) if count_solutions else outs
+    _check(load_library().qnae_build_cost_diagonal_batched(ctx.handle, jobs, count, _stream(stream)))
+    return (outs, [int(x) for x in sols[:count]]) if count_solutions else outs
 
 
 def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, ctx: Optional[Context] = None,
@@ -358,32 +395,44 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     count = len(costs)
     if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
         raise ValueError("argument lists differ in length")
-    halves = _per_item(half, count, "half")
+    halves = np.asarray(_per_item(half, count, "half"), dtype=bool)
+    G, goff, gcnt = _packed_angles(gammas, "gammas")
+    B, boff, bcnt = _packed_angles(betas, "betas")
+    bad = np.nonzero(gcnt != bcnt)[0]
+    if bad.size:
+        raise ValueError(f"instance {int(bad[0])}: gammas and betas must be 1-D of equal length")
+    nv = np.asarray(ns, dtype=np.int64).reshape(count)
+    stored = nv - halves
+    numel = np.fromiter((c.numel() for c in costs), dtype=np.int64, count=count)
+    bad = np.nonzero(numel != np.left_shift(np.int64(1), stored))[0]
+    if bad.size:
+        i = int(bad[0])
+        raise ValueError(f"instance {i}: cost has {int(numel[i])} entries, expected 2^{int(stored[i])}")
+    state_ptr = np.zeros(count, dtype=np.uint64)
+    if states is not None:
+        for i, st in enumerate(states):
+            if st is None:
+                continue
+            if st.dtype != torch.complex64 or st.numel() != (1 << int(stored[i])):
+                raise ValueError(f"instance {i}: state must be complex64 with 2^{int(stored[i])} entries")
+            state_ptr[i] = st.data_ptr()
     inst = (_CInstance * count)()
-    keep = []
-    for i in range(count):
-        g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas[i], dtype=np.float64)))
-        b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas[i], dtype=np.float64)))
-        if g.shape != b.shape or g.ndim != 1:
-            raise ValueError(f"instance {i}: gammas and betas must be 1-D of equal length")
-        stored = int(ns[i]) - (1 if halves[i] else 0)
-        if costs[i].numel() != (1 << stored):
-            raise ValueError(f"instance {i}: cost has {costs[i].numel()} entries, expected 2^{stored}")
-        keep += [g, b]
-        st = states[i] if states is not None else None
-        if st is not None and (st.dtype != torch.complex64 or st.numel() != (1 << stored)):
-            raise ValueError(f"instance {i}: state must be complex64 with 2^{stored} entries")
-        inst[i].cost_dev = costs[i].data_ptr()
-        inst[i].cost_dtype = QNAE_U8 if costs[i].dtype == torch.uint8 else QNAE_U16
-        inst[i].n, inst[i].m, inst[i].p = int(ns[i]), int(ms[i]), g.shape[0]
-        inst[i].gammas = g.ctypes.data_as(_F64P) if g.shape[0] else None
-        inst[i].betas = b.ctypes.data_as(_F64P) if g.shape[0] else None
-        inst[i].state_dev = st.data_ptr() if st is not None else None
-        inst[i].half = 1 if halves[i] else 0
+    v = _np_view(inst, _CInstance)
+    v["cost_dev"] = np.fromiter((c.data_ptr() for c in costs), dtype=np.uint64, count=count)
+    v["cost_dtype"] = np.fromiter((QNAE_U8 if c.dtype == torch.uint8 else QNAE_U16 for c in costs), dtype=np.int32,
+                                  count=count)
+    v["n"] = nv
+    v["m"] = np.asarray(ms, dtype=np.int64).reshape(count)
+    v["p"] = gcnt
+    v["gammas"] = np.where(gcnt > 0, np.uint64(G.ctypes.data) + np.uint64(8) * goff, np.uint64(0))
+    v["betas"] = np.where(gcnt > 0, np.uint64(B.ctypes.data) + np.uint64(8) * boff, np.uint64(0))
+    v["state_dev"] = state_ptr
+    v["half"] = halves
     res = (_CResult * count)()
     ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))
-    return [Result(r.p_success, r.expected_cost, r.norm) for r in res]
+    out = np.frombuffer(res, dtype=np.float64).reshape(count, 3)
+    return [Result(float(r[0]), float(r[1]), float(r[2])) for r in out]
 
 
 def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_energy: float = 0.0,
