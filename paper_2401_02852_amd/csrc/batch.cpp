@@ -57,14 +57,19 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
     char* h = (char*)ctx->h_blob.ptr;
     char* d = (char*)ctx->b_blob.ptr;
     ClauseRec* recs = (ClauseRec*)(h + rec_at);
+    // each job's records start at the sum of the clause counts before it
     std::vector<size_t> rec_off(count);
     std::vector<int> nrec(count);
     size_t at = 0;
     for (int i = 0; i < count; ++i) {
         rec_off[i] = at;
-        nrec[i] = make_clause_records(jobs[i].clauses, jobs[i].m, jobs[i].k, recs + at, jobs[i].predicate);
-        at += (size_t)nrec[i];
+        at += (size_t)jobs[i].m;
     }
+    constexpr int kChunk = 16;  // jobs per host task
+    parallel_for(ctx, (count + kChunk - 1) / kChunk, total_recs, [&](int c) {
+        for (int i = c * kChunk; i < std::min(count, (c + 1) * kChunk); ++i)
+            nrec[i] = make_clause_records(jobs[i].clauses, jobs[i].m, jobs[i].k, recs + rec_off[i], jobs[i].predicate);
+    });
     std::memset(h + zero_at, 0, sizeof(unsigned long long) * count);
     unsigned long long* zeros_dev = (unsigned long long*)(d + zero_at);
     uint32_t blocks[4] = {0, 0, 0, 0};
@@ -160,17 +165,22 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     }
     std::vector<float2> tables(lut_elems);
     std::vector<MixForm> forms(form_elems);
-    for (int i = 0; i < count; ++i) {
-        const qnae_instance& q = inst[i];
-        Job& J = jobs[i];
-        J.final_scale = build_tables(q.n, q.m, q.gammas, q.betas, q.p, tables.data() + J.lut_at, forms.data() + J.form_at);
-        if (!J.resident) {
-            plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, TB, ctx->min_low_run, ctx->page_bit,
-                        q.state_dev != nullptr, forms.data() + J.form_at, J.final_scale);
-            J.plan.half = q.half != 0;
-            steps = std::max(steps, (int)J.plan.ops.size());
+    constexpr int kChunk = 16;  // instances per host task
+    parallel_for(ctx, (count + kChunk - 1) / kChunk, lut_elems, [&](int c) {
+        for (int i = c * kChunk; i < std::min(count, (c + 1) * kChunk); ++i) {
+            const qnae_instance& q = inst[i];
+            Job& J = jobs[i];
+            J.final_scale =
+                build_tables(q.n, q.m, q.gammas, q.betas, q.p, tables.data() + J.lut_at, forms.data() + J.form_at);
+            if (!J.resident) {
+                plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, TB, ctx->min_low_run, ctx->page_bit,
+                            q.state_dev != nullptr, forms.data() + J.form_at, J.final_scale);
+                J.plan.half = q.half != 0;
+            }
         }
-    }
+    });
+    for (int i = 0; i < count; ++i)
+        if (!jobs[i].resident) steps = std::max(steps, (int)jobs[i].plan.ops.size());
     Blob B;
     const size_t lut_at = B.take(sizeof(float2) * lut_elems);
     const size_t form_at = B.take(sizeof(MixForm) * form_elems);

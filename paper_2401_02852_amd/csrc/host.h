@@ -5,9 +5,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <complex>
+#include <condition_variable>
+#include <functional>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -78,6 +84,37 @@ struct Blob {
 
 }  // namespace qnae_host
 
+namespace qnae_host {
+
+// A few host threads kept for the context's lifetime. run(count, fn) calls
+// fn(i) for every i in [0, count) on the workers and the calling thread and
+// returns when all calls are done; one run at a time (the context is used by
+// one thread at a time).
+class WorkerPool {
+public:
+    explicit WorkerPool(int workers);
+    ~WorkerPool();
+    WorkerPool(const WorkerPool&) = delete;
+    WorkerPool& operator=(const WorkerPool&) = delete;
+    void run(int count, const std::function<void(int)>& fn);
+    int size() const { return (int)threads_.size() + 1; }
+
+private:
+    void work();
+    void drain();
+    std::vector<std::thread> threads_;
+    std::mutex mu_;
+    std::condition_variable wake_, done_;
+    const std::function<void(int)>* fn_ = nullptr;
+    int count_ = 0;
+    std::atomic<int> next_{0};
+    int busy_ = 0;
+    uint64_t generation_ = 0;
+    bool stop_ = false;
+};
+
+}  // namespace qnae_host
+
 struct qnae_ctx {
     int device = 0;
     qnae_host::Profiler prof;
@@ -103,12 +140,17 @@ struct qnae_ctx {
     int tile_bits = 13;                 // tile size of the plain sweeps (log2 amplitudes)
     int min_low_run = 4;                // minimum contiguous low run (log2 amplitudes)
     int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes
+    // host threads for per-instance planning of large batches (made on first use)
+    std::unique_ptr<qnae_host::WorkerPool> pool;
 };
 
 namespace qnae_host {
 
 // Makes the context's device current and waits until pinned staging is free.
 int enter(qnae_ctx* ctx);
+// fn(i) for i in [0, count), spread over the context's host threads when the
+// work is large enough to pay for the hand-off (`items` units of it).
+void parallel_for(qnae_ctx* ctx, int count, size_t items, const std::function<void(int)>& fn);
 int check_cost_args(int32_t n, int32_t m, int32_t dtype);
 // Sweep tile shape at (n, cost type): the tuned one if set, else the context defaults.
 qnae_tune tune_for(const qnae_ctx* ctx, int n, int dtype);

@@ -101,6 +101,69 @@ std::complex<double> build_tables_from(int n, int m, const double* gammas, const
     return p > 0 ? prev : std::complex<double>(1.0, 0.0);
 }
 
+WorkerPool::WorkerPool(int workers) {
+    for (int i = 0; i < workers; ++i) threads_.emplace_back([this] { work(); });
+}
+
+WorkerPool::~WorkerPool() {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
+    }
+    wake_.notify_all();
+    for (std::thread& t : threads_) t.join();
+}
+
+void WorkerPool::drain() {
+    for (int i = next_.fetch_add(1); i < count_; i = next_.fetch_add(1)) (*fn_)(i);
+}
+
+void WorkerPool::work() {
+    uint64_t seen = 0;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            wake_.wait(lk, [&] { return stop_ || generation_ != seen; });
+            if (stop_) return;
+            seen = generation_;
+        }
+        drain();
+        std::lock_guard<std::mutex> lk(mu_);
+        if (--busy_ == 0) done_.notify_all();
+    }
+}
+
+void WorkerPool::run(int count, const std::function<void(int)>& fn) {
+    if (count <= 0) return;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        fn_ = &fn;
+        count_ = count;
+        next_.store(0);
+        busy_ = (int)threads_.size();
+        ++generation_;
+    }
+    wake_.notify_all();
+    drain();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return busy_ == 0; });
+    fn_ = nullptr;
+}
+
+void parallel_for(qnae_ctx* ctx, int count, size_t items, const std::function<void(int)>& fn) {
+    // below this much work (clause records or table entries) one thread is faster
+    constexpr size_t kMinItems = 8192;
+    if (count <= 1 || items < kMinItems) {
+        for (int i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    if (!ctx->pool) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        ctx->pool.reset(new WorkerPool((int)std::min(7u, hw > 1 ? hw - 1 : 1u)));
+    }
+    ctx->pool->run(count, fn);
+}
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;

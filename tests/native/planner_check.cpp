@@ -1,6 +1,7 @@
 // Host-side checks of the sweep planner and the clause records of the cost
 // kernel, built with AddressSanitizer and UBSan for the host (no GPU call).
 // Exit status 0 when every check holds.
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -125,9 +126,26 @@ static void check_clause_records() {
     }
 }
 
+// The host worker pool runs every index exactly once per run, across many
+// runs of different sizes, and shuts down cleanly.
+static void check_worker_pool() {
+    for (int workers : {1, 3, 7}) {
+        qnae_host::WorkerPool pool(workers);
+        for (int count : {0, 1, 2, 5, 64, 1000}) {
+            for (int rep = 0; rep < 20; ++rep) {
+                std::vector<std::atomic<int>> hits(count > 0 ? count : 1);
+                for (auto& h : hits) h.store(0);
+                pool.run(count, [&](int i) { hits[i].fetch_add(1); });
+                for (int i = 0; i < count; ++i) CHECK(hits[i].load() == 1);
+            }
+        }
+    }
+}
+
 int main() {
     check_groups_and_plans();
     check_clause_records();
+    check_worker_pool();
     std::printf("planner and clause records ok\n");
     return 0;
 }
