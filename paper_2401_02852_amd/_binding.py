@@ -67,6 +67,11 @@ def _np_view(carr, cls):
 
 def _packed_angles(values, name):
     """Concatenated float64 angles of every item, their offsets and counts."""
+    if all(type(x) is np.ndarray and x.ndim == 1 and x.dtype == np.float64 for x in values):
+        counts = np.fromiter((x.shape[0] for x in values), dtype=np.int64, count=len(values))
+        offsets = np.concatenate(([0], np.cumsum(counts)[:-1])) if len(values) else np.zeros(0, dtype=np.int64)
+        flat = np.ascontiguousarray(np.concatenate(values)) if counts.sum() else np.zeros(1)
+        return flat, offsets.astype(np.uint64), counts
     arrs = []
     for i, x in enumerate(values):
         a = np.asarray(x, dtype=np.float64)
@@ -431,8 +436,7 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     res = (_CResult * count)()
     ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))
-    out = np.frombuffer(res, dtype=np.float64).reshape(count, 3)
-    return [Result(float(r[0]), float(r[1]), float(r[2])) for r in out]
+    return list(map(Result._make, np.frombuffer(res, dtype=np.float64).reshape(count, 3).tolist()))
 
 
 def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_energy: float = 0.0,
