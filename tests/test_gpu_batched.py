@@ -71,10 +71,21 @@ def test_batched_states(q):
 
 
 def test_batched_workload_512(q):
-    """The 512-instance ragged batch: every result equals the single-instance
-    path; a sample is checked against the oracle."""
+    """The 512-instance ragged batch (large enough that its clause records,
+    tables and plans are built on the host thread pool): every result equals
+    the single-instance path; costs and solution counts of a sample equal the
+    single builds and the oracle; a sample is checked against the oracle."""
+    import torch
     batch = inst.batched_workload(count=512)
-    costs = q.build_cost_diagonals([x["clauses"] for x in batch], [x["n"] for x in batch])
+    costs, sols = q.build_cost_diagonals([x["clauses"] for x in batch], [x["n"] for x in batch],
+                                         count_solutions=True)
+    for i in range(0, 512, 17):
+        x = batch[i]
+        c1, s1 = q.build_cost_diagonal(x["clauses"], x["n"], count_solutions=True)
+        assert torch.equal(c1, costs[i]) and s1 == sols[i], i
+    for i in range(0, 512, 101):
+        x = batch[i]
+        assert sols[i] == oracle.count_solutions(x["clauses"], x["n"]), i
     res = q.qaoa_run_batched(costs, [x["n"] for x in batch], [x["m"] for x in batch],
                              [x["gammas"] for x in batch], [x["betas"] for x in batch])
     for x, c, r in zip(batch, costs, res):
