@@ -186,19 +186,21 @@ __device__ __forceinline__ void from_lds(const float2* lds, float2 (&v)[32], uin
 // imaginary parts, so a tile needs a float per element instead of a float2
 // and twice as many workgroups fit in a CU's LDS. Element e sits at float
 // physf(e) = e + sum of c_i over the set bits i >= 6 of e. The coefficients
-// are non-decreasing sums (so the map is one-to-one) chosen so that, with
-// 64 four-byte banks, every b32 access of 64 lanes in layouts L1 and L2 and
-// every b64 access of 32 lanes in layout L0 hits 64 distinct banks; L0 pairs
-// (tile bit 0) stay adjacent because bit 0 carries no padding.
+// are non-decreasing sums (so the map is one-to-one) chosen so that every
+// b32 access of 32 lanes in layouts L1 and L2 and every b64 access of 32 lanes
+// in layout L0 hits 32 distinct four-byte banks (rocprofv3 counted bank
+// conflicts for b32 accesses of lanes 0..31 sharing a bank modulo 32, so
+// that is the constraint); L0 pairs (tile bit 0) stay adjacent because bit 0
+// carries no padding.
 template <int TB>
 struct PlanePad;
 template <>
 struct PlanePad<12> {
-    static constexpr uint32_t c[6] = {2, 4, 16, 32, 72, 126};
+    static constexpr uint32_t c[6] = {2, 4, 16, 40, 62, 124};
 };
 template <>
 struct PlanePad<13> {
-    static constexpr uint32_t c[7] = {2, 16, 32, 68, 136, 254, 508};
+    static constexpr uint32_t c[7] = {2, 16, 36, 72, 126, 252, 504};
 };
 template <>
 struct PlanePad<14> {
