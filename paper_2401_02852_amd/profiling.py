@@ -25,7 +25,7 @@ import sys
 from collections import OrderedDict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/sweep.hip", "csrc/cost.hip"]
+KERNEL_SOURCES = ["csrc/sweep.hip", "csrc/tile.h", "csrc/cost.hip"]
 
 KIND_NAMES = {"0": "sweep_first", "1": "sweep_middle", "2": "sweep_boundary", "3": "sweep_final", "4": "sweep_p0"}
 
