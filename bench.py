@@ -263,7 +263,7 @@ def sampling_bench(q, ctx, draws=100_000, ensemble=200):
     st = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     res = q.qaoa_run(cost, n, m, g, -b, state=st, ctx=ctx)
     u = np.random.default_rng(0).random(draws)
-    q.sample(st, n, u[:1000], cost=cost, ctx=ctx)
+    q.sample(st, n, u, cost=cost, ctx=ctx)  # sizes the context's device and pinned buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, costs = q.sample(st, n, u, cost=cost, ctx=ctx)

@@ -188,11 +188,14 @@ hipError_t launch_final_reduce_batch(const double* const* partials, const uint32
 // ---------------------------------------------------------------------------
 
 constexpr int kSampleTileBits = 12;
+constexpr int kSampleChunks = 1024;  // tile-prefix chunks
 // Draw `count` outcomes of psi (2^n complex64) for the given uniforms in
-// [0, 1): mass (ceil(2^n / 4096) doubles) and pref (one more) are scratch.
-// out[q] = ~0 marks a zero state. out_cost, if not null, receives C at each
-// outcome (or -1 without a cost diagonal).
+// [0, 1): mass (ceil(2^n / 4096) doubles), pref (one more) and chunk
+// (kSampleChunks doubles) are scratch. out[q] = ~0 marks a zero state.
+// out_cost, if not null, receives C at each outcome (or -1 without a cost
+// diagonal).
 hipError_t launch_sample(const float2* psi, int n, const void* cost, int cost_dtype, const double* uniforms,
-                         int count, double* mass, double* pref, uint64_t* out, int32_t* out_cost, hipStream_t s);
+                         int count, double* mass, double* pref, double* chunk, uint64_t* out, int32_t* out_cost,
+                         hipStream_t s);
 
 }  // namespace qnae

@@ -28,6 +28,7 @@ int qnae_sample(qnae_ctx* ctx, const void* state_dev, int32_t n, const void* cos
     Blob B;
     const size_t mass_at = B.take(sizeof(double) * T);
     const size_t pref_at = B.take(sizeof(double) * (T + 1));
+    const size_t chunk_at = B.take(sizeof(double) * qnae::kSampleChunks);
     const size_t u_at = B.take(sizeof(double) * (size_t)count);
     const size_t out_at = B.take(sizeof(uint64_t) * (size_t)count);
     const size_t cost_at = B.take(sizeof(int32_t) * (size_t)count);
@@ -40,7 +41,7 @@ int qnae_sample(qnae_ctx* ctx, const void* state_dev, int32_t n, const void* cos
         HIP_TRY(hipMemcpyAsync(d + u_at, h, sizeof(double) * (size_t)count, hipMemcpyHostToDevice, s));
     }
     HIP_TRY(qnae::launch_sample((const float2*)state_dev, n, cost_dev, cost_dtype, (const double*)(d + u_at), count,
-                                (double*)(d + mass_at), (double*)(d + pref_at), (uint64_t*)(d + out_at),
+                                (double*)(d + mass_at), (double*)(d + pref_at), (double*)(d + chunk_at), (uint64_t*)(d + out_at),
                                 sample_costs ? (int32_t*)(d + cost_at) : nullptr, s));
     if (count > 0)
         HIP_TRY(hipMemcpyAsync(h + (out_at - u_at), d + out_at, B.size - out_at, hipMemcpyDeviceToHost, s));

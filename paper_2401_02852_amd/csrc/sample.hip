@@ -38,17 +38,25 @@ __device__ TileScan tile_scan(const float2* __restrict__ psi, uint64_t N, uint64
                               double* wsum) {
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint64_t base = tile * (uint64_t)kTile;
+    constexpr int kLoads = kTile / 512;
+    // float4s (amplitude pairs) of this tile inside the state: 2048 for every
+    // tile when N >= 4096, else N / 2 >= 1 (N is even). Indices past it load
+    // the last pair in range and read as zero, so all loads are unconditional
+    // and in flight together.
+    const uint32_t lim = (uint32_t)min<uint64_t>(N - base, (uint64_t)kTile) / 2u;
+    const float4* tp = (const float4*)(psi + base);  // uniform base, 32-bit offsets
+    float4 q[kLoads];
 #pragma unroll
-    for (int i = 0; i < kTile / 512; ++i) {
+    for (int i = 0; i < kLoads; ++i) {
+        const uint32_t j = tid + 256u * i;
+        q[i] = tp[j < lim ? j : lim - 1u];
+        if (j >= lim) q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < kLoads; ++i) {
         const uint32_t e = 2u * tid + 512u * i;
-        float p0 = 0.f, p1 = 0.f;
-        if (base + e < N) {  // N is even, so e + 1 is in range too
-            const float4 q = *(const float4*)(psi + base + e);
-            p0 = fmaf(q.x, q.x, q.y * q.y);
-            p1 = fmaf(q.z, q.z, q.w * q.w);
-        }
-        prob[pad(e)] = p0;
-        prob[pad(e + 1)] = p1;
+        prob[pad(e)] = fmaf(q[i].x, q[i].x, q[i].y * q[i].y);
+        prob[pad(e + 1)] = fmaf(q[i].z, q[i].z, q[i].w * q[i].w);
     }
     __syncthreads();
     double s = 0.0;
@@ -79,32 +87,67 @@ __global__ __launch_bounds__(256) void tile_mass_kernel(const float2* __restrict
     if (threadIdx.x == 0) mass[blockIdx.x] = r.total;
 }
 
-// One workgroup of 1024 threads: P[t] for t < T (in place over the masses'
-// copy `pref`) and P[T] = total. Thread i owns tiles [i*chunk, (i+1)*chunk).
-__global__ __launch_bounds__(1024) void tile_prefix_kernel(const double* __restrict__ mass, double* __restrict__ pref,
-                                                           uint32_t T, uint32_t chunk) {
-    __shared__ double C[1025];
-    const uint32_t i = threadIdx.x;
+// The tile level in three launches. Thread i of the first owns tiles
+// [i*chunk, (i+1)*chunk) of the kSampleChunks chunks and writes their prefix
+// within the chunk, from zero, and the chunk total. T and chunk are powers of
+// two, so a chunk of 16 or more splits into whole runs of 16 tiles: their
+// loads are issued together, then summed in tile order. The threads spread
+// over 16 workgroups, as each load instruction touches 64 chunks' lines.
+constexpr int kRun = 16;
+
+__global__ __launch_bounds__(64) void chunk_run_kernel(const double* __restrict__ mass, double* __restrict__ pref,
+                                                       double* __restrict__ chunk_total, uint32_t T, uint32_t chunk) {
+    const uint32_t i = blockIdx.x * 64u + threadIdx.x;
     const uint32_t lo = min(T, i * chunk), hi = min(T, lo + chunk);
     double run = 0.0;
-    for (uint32_t t = lo; t < hi; ++t) {
-        pref[t] = run;  // within the chunk, from zero
+    uint32_t t = lo;
+    for (; t + kRun <= hi; t += kRun) {
+        double v[kRun];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) v[j] = mass[t + j];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+            const double mj = v[j];
+            v[j] = run;
+            run += mj;
+        }
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) pref[t + j] = v[j];
+    }
+    for (; t < hi; ++t) {
+        pref[t] = run;
         run += mass[t];
     }
-    C[i + 1] = run;
-    __syncthreads();
-    if (i == 0) {
-        double acc = 0.0;
-        C[0] = 0.0;
-        for (int q = 1; q <= 1024; ++q) {
-            acc += C[q];
-            C[q] = acc;
+    chunk_total[i] = run;
+}
+
+// One thread: the chunk level, C[0] = 0 and C[i+1] = C[i] + total[i] in
+// chunk order, in place over the totals, and P[T] = C[kSampleChunks].
+__global__ __launch_bounds__(64) void chunk_offset_kernel(double* __restrict__ chunk_total, double* __restrict__ pref,
+                                                          uint32_t T) {
+    if (threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int q = 0; q < kSampleChunks; q += kRun) {
+        double v[kRun];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) v[j] = chunk_total[q + j];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+            const double tj = v[j];
+            v[j] = acc;
+            acc += tj;
         }
-        pref[T] = acc;
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) chunk_total[q + j] = v[j];
     }
-    __syncthreads();
-    const double c0 = C[i];
-    for (uint32_t t = lo; t < hi; ++t) pref[t] = c0 + pref[t];
+    pref[T] = acc;
+}
+
+// P[t] = C[t / chunk] + (prefix within the chunk), one tile per thread.
+__global__ __launch_bounds__(256) void chunk_add_kernel(double* __restrict__ pref, const double* __restrict__ C,
+                                                        uint32_t T, uint32_t chunk_bits) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t < T) pref[t] = C[t >> chunk_bits] + pref[t];
 }
 
 // One workgroup per draw.
@@ -175,13 +218,22 @@ __global__ __launch_bounds__(256) void sample_kernel(const float2* __restrict__ 
 }  // namespace
 
 hipError_t launch_sample(const float2* psi, int n, const void* cost, int cost_dtype, const double* uniforms,
-                         int count, double* mass, double* pref, uint64_t* out, int32_t* out_cost, hipStream_t s) {
+                         int count, double* mass, double* pref, double* chunk_scratch, uint64_t* out, int32_t* out_cost,
+                         hipStream_t s) {
     const uint64_t N = 1ull << n;
     const uint32_t T = (uint32_t)((N + kTile - 1) / kTile);
     hipLaunchKernelGGL(tile_mass_kernel, dim3(T), dim3(256), 0, s, psi, N, mass);
     if (hipError_t e = hipGetLastError()) return e;
-    const uint32_t chunk = (T + 1023) / 1024;
-    hipLaunchKernelGGL(tile_prefix_kernel, dim3(1), dim3(1024), 0, s, mass, pref, T, chunk);
+    static_assert(kSampleChunks % 64 == 0 && kSampleChunks % kRun == 0, "chunk launch shape");
+    const uint32_t chunk = (T + kSampleChunks - 1) / kSampleChunks;  // T is a power of two
+    const uint32_t chunk_bits = (uint32_t)__builtin_ctz(chunk);
+    hipLaunchKernelGGL(chunk_run_kernel, dim3(kSampleChunks / 64), dim3(64), 0, s, mass, pref, chunk_scratch, T,
+                       chunk);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(chunk_offset_kernel, dim3(1), dim3(64), 0, s, chunk_scratch, pref, T);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(chunk_add_kernel, dim3((T + 255) / 256), dim3(256), 0, s, pref,
+                       (const double*)chunk_scratch, T, chunk_bits);
     if (hipError_t e = hipGetLastError()) return e;
     if (count == 0) return hipSuccess;
     if (cost_dtype == 2)

@@ -76,6 +76,32 @@ def test_sample_uniform_state_full_size(q):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n", [22, 23, 25, 26])
+def test_sample_exact_sums_every_chunk_shape(q, n):
+    """Amplitudes (a + ib) 2^-10 with integers a, b in [0, 7]: every
+    probability is a multiple of 2^-20 below 2^-13 and every partial sum is
+    exact in FP64 whatever its order, so each draw is the oracle's exactly.
+    n = 22..26 gives tile-prefix chunks of 1, 2, 8 and 16 tiles (4096
+    amplitudes each); runs of zero tiles at the start, across the middle
+    chunk boundary and at the end exercise the skip over empty tiles."""
+    import torch
+    rng = np.random.default_rng(200 + n)
+    N = 1 << n
+    a = rng.integers(0, 8, N).astype(np.float32)
+    b = rng.integers(0, 8, N).astype(np.float32)
+    psi = ((a + 1j * b) * np.float32(2.0 ** -10)).astype(np.complex64)
+    psi[: 3 << 12] = 0
+    psi[N // 2 - 5000: N // 2 + 9000] = 0
+    psi[N - (1 << 12):] = 0
+    st = torch.from_numpy(psi).to("cuda")
+    u = np.concatenate([rng.random(20000), [0.0, 1 - 2 ** -53, 0.5]])
+    got, _ = q.sample(st, n, u)
+    ref = oracle.sample(psi.astype(np.complex128), n, u)
+    assert np.array_equal(got, ref)
+    del st
+    torch.cuda.empty_cache()
+
+
 def test_sample_workload_n30_statistics(q, golden):
     """The n = 30 workload with the ramp (beta negated): the share of
     satisfying draws and the mean cost of the draws agree with the oracle's
