@@ -121,26 +121,43 @@ __global__ __launch_bounds__(64) void chunk_run_kernel(const double* __restrict_
     chunk_total[i] = run;
 }
 
-// One thread: the chunk level, C[0] = 0 and C[i+1] = C[i] + total[i] in
-// chunk order, in place over the totals, and P[T] = C[kSampleChunks].
+// The chunk level: C[0] = 0 and C[i+1] = C[i] + total[i] in chunk order, in
+// place over the totals, for the `used` = T / chunk chunks that hold tiles
+// (the others hold none and add nothing), and P[T] = C[used]. One wave stages
+// the totals in LDS; one thread adds them in order.
 __global__ __launch_bounds__(64) void chunk_offset_kernel(double* __restrict__ chunk_total, double* __restrict__ pref,
-                                                          uint32_t T) {
-    if (threadIdx.x != 0) return;
-    double acc = 0.0;
-    for (int q = 0; q < kSampleChunks; q += kRun) {
-        double v[kRun];
+                                                          uint32_t T, uint32_t used) {
+    __shared__ double c[kSampleChunks];
+    const uint32_t lane = threadIdx.x;
 #pragma unroll
-        for (int j = 0; j < kRun; ++j) v[j] = chunk_total[q + j];
+    for (int j = 0; j < kSampleChunks / 64; ++j) c[lane + 64u * j] = chunk_total[lane + 64u * j];
+    __syncthreads();
+    if (lane == 0) {
+        double acc = 0.0;
+        uint32_t q = 0;
+        for (; q + kRun <= used; q += kRun) {
+            double v[kRun];
 #pragma unroll
-        for (int j = 0; j < kRun; ++j) {
-            const double tj = v[j];
-            v[j] = acc;
-            acc += tj;
+            for (int j = 0; j < kRun; ++j) v[j] = c[q + j];
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) {
+                const double tj = v[j];
+                v[j] = acc;
+                acc += tj;
+            }
+#pragma unroll
+            for (int j = 0; j < kRun; ++j) c[q + j] = v[j];
         }
-#pragma unroll
-        for (int j = 0; j < kRun; ++j) chunk_total[q + j] = v[j];
+        for (; q < used; ++q) {
+            const double tq = c[q];
+            c[q] = acc;
+            acc += tq;
+        }
+        pref[T] = acc;
     }
-    pref[T] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSampleChunks / 64; ++j) chunk_total[lane + 64u * j] = c[lane + 64u * j];
 }
 
 // P[t] = C[t / chunk] + (prefix within the chunk), one tile per thread.
@@ -230,7 +247,7 @@ hipError_t launch_sample(const float2* psi, int n, const void* cost, int cost_dt
     hipLaunchKernelGGL(chunk_run_kernel, dim3(kSampleChunks / 64), dim3(64), 0, s, mass, pref, chunk_scratch, T,
                        chunk);
     if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(chunk_offset_kernel, dim3(1), dim3(64), 0, s, chunk_scratch, pref, T);
+    hipLaunchKernelGGL(chunk_offset_kernel, dim3(1), dim3(64), 0, s, chunk_scratch, pref, T, T / chunk);
     if (hipError_t e = hipGetLastError()) return e;
     hipLaunchKernelGGL(chunk_add_kernel, dim3((T + 255) / 256), dim3(256), 0, s, pref,
                        (const double*)chunk_scratch, T, chunk_bits);
