@@ -46,8 +46,7 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
         float2* lut = (float2*)(h + lut_at);
         float2* cs = (float2*)(h + cs_at);
         for (int l = 0; l < p; ++l) {
-            for (int c = 0; c <= m; ++c)
-                lut[(size_t)l * lut_len + c] = make_float2((float)std::cos(gammas[l] * c), (float)-std::sin(gammas[l] * c));
+            phase_row(gammas[l], m, 1.0, -1, lut + (size_t)l * lut_len);
             cs[l] = make_float2((float)std::cos(betas[l]), (float)std::sin(betas[l]));
         }
         const int nck = p > 1 ? (p - 1) / every : 0;
@@ -117,11 +116,8 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
                     S.final_scale, j > 0);
         // reverse tables: b-layer i is forward layer b - 1 - i, exp(+i gamma c)
         S.blut_at = (size_t)S.a * lut_len;
-        for (int i = 0; i < L; ++i) {
-            const double g = gammas[S.b - 1 - i];
-            for (int c = 0; c <= m; ++c)
-                btab[S.blut_at + (size_t)i * lut_len + c] = make_float2((float)std::cos(g * c), (float)std::sin(g * c));
-        }
+        for (int i = 0; i < L; ++i)
+            phase_row(gammas[S.b - 1 - i], m, 1.0, +1, btab.data() + S.blut_at + (size_t)i * lut_len);
         if (L > 0) S.aops = make_adjoint_plan((int)groups.size(), L);
         total_aops += (int)S.aops.size();
     }
@@ -284,9 +280,7 @@ int qnae_qaoa_grad_batched(qnae_ctx* ctx, const qnae_grad_job* jobs, int32_t cou
                 float2* lut = (float2*)(h + lut_at[i]);
                 float2* cs = (float2*)(h + cs_at[i]);
                 for (int l = 0; l < j.p; ++l) {
-                    for (int c = 0; c <= j.m; ++c)
-                        lut[(size_t)l * lut_len + c] =
-                            make_float2((float)std::cos(j.gammas[l] * c), (float)-std::sin(j.gammas[l] * c));
+                    phase_row(j.gammas[l], j.m, 1.0, -1, lut + (size_t)l * lut_len);
                     cs[l] = make_float2((float)std::cos(j.betas[l]), (float)std::sin(j.betas[l]));
                 }
                 qnae::ResidentGradArgs& a = args[q];

@@ -177,6 +177,8 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
 // QNAE_EINVAL if some literal is 0 or outside +-[1, n].
 int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k);
 
+// scale * exp(sign i g c) for c = 0..m (sign -1 or +1) as m + 1 FP32 pairs.
+void phase_row(double g, int m, std::complex<double> scale, int sign, float2* out);
 // Phase tables (p tables of m + 1 entries, or one when p = 0) and per-layer
 // mixer forms; returns the scalar factor left after the last layer.
 std::complex<double> build_tables(int n, int m, const double* gammas, const double* betas, int p, float2* tables,

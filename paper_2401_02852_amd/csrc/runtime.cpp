@@ -48,50 +48,54 @@ std::complex<double> build_tables(int n, int m, const double* gammas, const doub
     return build_tables_from(n, m, gammas, betas, p, tables, forms, std::complex<double>(std::pow(2.0, -0.5 * n), 0.0));
 }
 
+// scale * exp(sign i g c) for c = 0..m: exp(sign i g c) = exp(sign i g 16 q)
+// exp(sign i g r) for c = 16 q + r, both factors from short angle-addition
+// recurrences (at most 15 FP64 products from a directly computed value), and
+// every entry then one independent product, instead of a sine and a cosine of
+// a large argument per entry (the batched solves build tens of thousands of
+// entries per call). The entries differ from a direct sine and cosine by at
+// most about 1e-13 for m <= 255 and 1e-10 for m up to 65535 (the size of the
+// rounding of g c itself there), far below the FP32 rounding of the entries.
+// Products are written out: std::complex multiplication carries the infinity
+// and NaN recovery of C99 Annex G, a library call per product.
+void phase_row(double g, int m, std::complex<double> scale, int sign, float2* out) {
+    const double sg = sign < 0 ? -1.0 : 1.0;
+    double lo_r[16], lo_i[16];  // exp(sign i g r), r < 16
+    lo_r[0] = 1.0;
+    lo_i[0] = 0.0;
+    const double s1r = std::cos(g), s1i = sg * std::sin(g);
+    for (int r = 1; r < 16; ++r) {
+        lo_r[r] = lo_r[r - 1] * s1r - lo_i[r - 1] * s1i;
+        lo_i[r] = lo_r[r - 1] * s1i + lo_i[r - 1] * s1r;
+    }
+    const double s16r = std::cos(16.0 * g), s16i = sg * std::sin(16.0 * g);
+    double hr = scale.real(), hi = scale.imag();  // scale * exp(sign i g 16 q)
+    for (int q = 0; 16 * q <= m; ++q) {
+        if (q > 0 && q % 16 == 0) {  // re-anchor the high factor every 256 entries
+            const double a = 16.0 * g * q;
+            const double cr = std::cos(a), ci = sg * std::sin(a);
+            hr = scale.real() * cr - scale.imag() * ci;
+            hi = scale.real() * ci + scale.imag() * cr;
+        } else if (q > 0) {
+            const double t = hr * s16r - hi * s16i;
+            hi = hr * s16i + hi * s16r;
+            hr = t;
+        }
+        float* const row = (float*)(out + 16 * q);  // (re, im) pairs
+        const int rmax = std::min(15, m - 16 * q);
+        for (int r = 0; r <= rmax; ++r) {
+            row[2 * r] = (float)(hr * lo_r[r] - hi * lo_i[r]);
+            row[2 * r + 1] = (float)(hr * lo_i[r] + hi * lo_r[r]);
+        }
+    }
+}
+
 std::complex<double> build_tables_from(int n, int m, const double* gammas, const double* betas, int p,
                                        float2* tables, MixForm* forms, std::complex<double> first) {
     std::complex<double> prev = first;
     const int T = p > 0 ? p : 1;
-    // exp(-i g c) = exp(-i g 16 q) exp(-i g r) for c = 16 q + r: both factors
-    // come from short angle-addition recurrences (at most 15 FP64 products
-    // from a directly computed value), and every entry is then one
-    // independent product, instead of a sine and a cosine of a large argument
-    // per entry (the batched solves build tens of thousands of entries per
-    // call). The entries differ from a direct sine and cosine by at most about
-    // 1e-13 for m <= 255 and 1e-10 for m up to 65535 (the size of the rounding
-    // of g c itself there), far below the FP32 rounding of the entries.
-    // Products are written out: std::complex multiplication carries the
-    // infinity and NaN recovery of C99 Annex G, a library call per product.
     for (int l = 0; l < T; ++l) {
-        const double g = p > 0 ? gammas[l] : 0.0;
-        double lo_r[16], lo_i[16];  // exp(-i g r), r < 16
-        lo_r[0] = 1.0;
-        lo_i[0] = 0.0;
-        const double s1r = std::cos(g), s1i = -std::sin(g);
-        for (int r = 1; r < 16; ++r) {
-            lo_r[r] = lo_r[r - 1] * s1r - lo_i[r - 1] * s1i;
-            lo_i[r] = lo_r[r - 1] * s1i + lo_i[r - 1] * s1r;
-        }
-        const double s16r = std::cos(16.0 * g), s16i = -std::sin(16.0 * g);
-        double hr = prev.real(), hi = prev.imag();  // prev * exp(-i g 16 q)
-        for (int q = 0; 16 * q <= m; ++q) {
-            if (q > 0 && q % 16 == 0) {  // re-anchor the high factor every 256 entries
-                const double a = 16.0 * g * q;
-                const double cr = std::cos(a), ci = -std::sin(a);
-                hr = prev.real() * cr - prev.imag() * ci;
-                hi = prev.real() * ci + prev.imag() * cr;
-            } else if (q > 0) {
-                const double t = hr * s16r - hi * s16i;
-                hi = hr * s16i + hi * s16r;
-                hr = t;
-            }
-            float* const row = (float*)(tables + (size_t)l * (m + 1) + 16 * q);  // (re, im) pairs
-            const int rmax = std::min(15, m - 16 * q);
-            for (int r = 0; r <= rmax; ++r) {
-                row[2 * r] = (float)(hr * lo_r[r] - hi * lo_i[r]);
-                row[2 * r + 1] = (float)(hr * lo_i[r] + hi * lo_r[r]);
-            }
-        }
+        phase_row(p > 0 ? gammas[l] : 0.0, m, prev, -1, tables + (size_t)l * (m + 1));
         if (p > 0) {
             const Layer L = mixer_form(betas[l], n);
             forms[l] = L.form;

@@ -2,6 +2,8 @@
 // kernel, built with AddressSanitizer and UBSan for the host (no GPU call).
 // Exit status 0 when every check holds.
 #include <atomic>
+#include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -128,6 +130,29 @@ static void check_clause_records() {
 
 // The host worker pool runs every index exactly once per run, across many
 // runs of different sizes, and shuts down cleanly.
+// Phase rows: scale * exp(sign i g c) through the two-level angle addition
+// against a direct sine and cosine of g c per entry; both round to FP32 values
+// that lie within 1e-10 of each other, so entries differ by at most one FP32
+// rounding step.
+static void check_phase_rows() {
+    std::mt19937_64 rng(11);
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    for (int m : {0, 1, 15, 16, 17, 255, 256, 257, 300, 4097, 65535})
+        for (int sign : {-1, +1})
+            for (int trial = 0; trial < 4; ++trial) {
+                const double g = 7.0 * U(rng);
+                const std::complex<double> scale(U(rng), U(rng));
+                std::vector<float2> row((size_t)m + 1);
+                phase_row(g, m, scale, sign, row.data());
+                const double tol = 1.2e-7 * std::abs(scale) + 2e-10;
+                for (int c = 0; c <= m; ++c) {
+                    const std::complex<double> e =
+                        scale * std::complex<double>(std::cos(g * c), sign * std::sin(g * c));
+                    CHECK(std::fabs(row[c].x - e.real()) <= tol && std::fabs(row[c].y - e.imag()) <= tol);
+                }
+            }
+}
+
 static void check_worker_pool() {
     for (int workers : {1, 3, 7}) {
         qnae_host::WorkerPool pool(workers);
@@ -145,6 +170,7 @@ static void check_worker_pool() {
 int main() {
     check_groups_and_plans();
     check_clause_records();
+    check_phase_rows();
     check_worker_pool();
     std::printf("planner and clause records ok\n");
     return 0;
