@@ -5,15 +5,20 @@
 // satisfies the instance. A draw inverts the cumulative distribution in index
 // order: the outcome for a uniform u is the smallest x whose cumulative mass
 // exceeds u times the total. The cumulative distribution is never stored per
-// amplitude; it is kept at three levels, each a prefix sum that starts from
-// zero and is nondecreasing by construction:
+// amplitude; it is kept at three levels of prefix sums from zero:
 //   chunk level  C[i]: sequential sums of chunk masses (one thread);
 //   tile level   P[t] = C[i] + (sequential sum of the tile masses before t in
 //                its chunk), tiles of 4096 consecutive amplitudes;
 //   inside a tile: per-thread sums of 16 consecutive probabilities, their
 //                block-wide exclusive scan, then a walk over the 16.
-// A draw finds its tile by binary search over P, then its thread, then its
-// amplitude. Probabilities are FP32 |psi|^2, sums FP64.
+// The first two are nondecreasing by construction (sequential sums of
+// nonnegative terms, and FP64 addition of a fixed offset is monotone). The
+// in-tile scan is a shuffle tree whose rounding may differ from a sequential
+// sum, so a draw takes the highest thread with mass whose start is at or below
+// its remainder and, if rounding carries the remainder past that thread's
+// walk, the thread's last nonzero probability. A draw finds its tile by binary
+// search over P, then its thread, then its amplitude. Probabilities are FP32
+// |psi|^2, sums FP64.
 #include "internal.h"
 
 namespace qnae {
