@@ -49,7 +49,7 @@ enum { QNAE_U8 = 1, QNAE_U16 = 2 };
 enum {
     QNAE_OK = 0,
     QNAE_EINVAL = -1,   /* invalid argument; nothing was enqueued */
-    QNAE_ENOMEM = -2,   /* device or pinned host allocation failed */
+    QNAE_ENOMEM = -2,   /* device, pinned or host memory, or a host thread, could not be had */
     QNAE_EHIP = -3,     /* HIP runtime error (message has hipGetErrorString) */
     QNAE_EBUSY = -4,     /* server queue or pool full */
     QNAE_ETIMEDOUT = -5, /* server wait timed out */

@@ -22,7 +22,7 @@ using qnae::SweepArgs;
 
 extern "C" {
 
-int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, int32_t count, void* stream) {
+int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, int32_t count, void* stream) try {
     if (count < 0 || (count > 0 && !jobs)) return fail(QNAE_EINVAL, "bad job array (count=%d)", count);
     for (int i = 0; i < count; ++i) {
         const qnae_cost_job& j = jobs[i];
@@ -118,9 +118,11 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
             if (jobs[i].num_solutions) *jobs[i].num_solutions = z[i] * (jobs[i].half ? 2ull : 1ull);
     }
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t count, qnae_result* out, void* stream) {
+int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t count, qnae_result* out, void* stream) try {
     if (count < 0 || (count > 0 && (!inst || !out))) return fail(QNAE_EINVAL, "bad instance array (count=%d)", count);
     for (int i = 0; i < count; ++i) {
         const qnae_instance& q = inst[i];
@@ -378,6 +380,8 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         out[i].norm = r[3 * i + 2] * sc;
     }
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

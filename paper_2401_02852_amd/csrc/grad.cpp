@@ -21,7 +21,7 @@ extern "C" {
 
 int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
                    const double* gammas, const double* betas, int32_t p, double w_psucc, double w_energy,
-                   int32_t checkpoint_every, double* dgammas, double* dbetas, qnae_result* out, void* stream) {
+                   int32_t checkpoint_every, double* dgammas, double* dbetas, qnae_result* out, void* stream) try {
     if (int rc = check_run_args(n, m, cost_dtype, cost_dev, gammas, betas, p)) return rc;
     if (!out) return fail(QNAE_EINVAL, "null result pointer");
     if (p > 0 && (!dgammas || !dbetas)) return fail(QNAE_EINVAL, "null gradient arrays with p=%d", p);
@@ -230,10 +230,12 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     out->expected_cost = r[3 * total_aops + 1] * sc;
     out->norm = r[3 * total_aops + 2] * sc;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 int qnae_qaoa_grad_batched(qnae_ctx* ctx, const qnae_grad_job* jobs, int32_t count, double w_psucc, double w_energy,
-                           int32_t checkpoint_every, qnae_result* out, void* stream) {
+                           int32_t checkpoint_every, qnae_result* out, void* stream) try {
     if (count < 0 || (count > 0 && (!jobs || !out))) return fail(QNAE_EINVAL, "bad job array (count=%d)", count);
     if (checkpoint_every < 0) return fail(QNAE_EINVAL, "checkpoint_every=%d < 0", checkpoint_every);
     if (!std::isfinite(w_psucc) || !std::isfinite(w_energy)) return fail(QNAE_EINVAL, "non-finite weights");
@@ -333,6 +335,8 @@ int qnae_qaoa_grad_batched(qnae_ctx* ctx, const qnae_grad_job* jobs, int32_t cou
             return fail(rc, "job %d: %s", i, std::string(last_error()).c_str());
     }
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <complex>
 #include <condition_variable>
+#include <exception>
 #include <functional>
 #include <map>
 #include <memory>
@@ -25,6 +26,11 @@ namespace qnae_host {
 // Sets the calling thread's error message and returns `code`.
 int fail(int code, const char* fmt, ...);
 const char* last_error();
+// Inside a catch block: records the exception being handled as this thread's
+// last error and returns QNAE_ENOMEM (host memory or threads ran out; nothing
+// else throws here). Entry points end in it so that no exception leaves the
+// C ABI.
+int host_exception();
 
 #define HIP_TRY(expr)                                                                                  \
     do {                                                                                               \
@@ -96,6 +102,9 @@ public:
     ~WorkerPool();
     WorkerPool(const WorkerPool&) = delete;
     WorkerPool& operator=(const WorkerPool&) = delete;
+    // fn(0) .. fn(count - 1) over the workers and the caller. If a call
+    // throws, the items not yet started are skipped and the first exception
+    // is rethrown to the caller once every worker is idle again.
     void run(int count, const std::function<void(int)>& fn);
     int size() const { return (int)threads_.size() + 1; }
 
@@ -108,6 +117,7 @@ private:
     const std::function<void(int)>* fn_ = nullptr;
     int count_ = 0;
     std::atomic<int> next_{0};
+    std::exception_ptr error_;  // first exception of the current run
     int busy_ = 0;
     uint64_t generation_ = 0;
     bool stop_ = false;

@@ -15,7 +15,7 @@ extern "C" {
 
 const char* qnae_last_error(const qnae_ctx*) { return last_error(); }
 
-int qnae_create(qnae_ctx** out, int device) {
+int qnae_create(qnae_ctx** out, int device) try {
     if (!out) return fail(QNAE_EINVAL, "null output pointer");
     *out = nullptr;
     int count = 0;
@@ -43,9 +43,11 @@ int qnae_create(qnae_ctx** out, int device) {
     }
     *out = ctx;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_destroy(qnae_ctx* ctx) {
+int qnae_destroy(qnae_ctx* ctx) try {
     if (!ctx) return QNAE_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
@@ -66,12 +68,16 @@ int qnae_destroy(qnae_ctx* ctx) {
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     delete ctx;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 int qnae_build_cost_diagonal(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k, void* cost_dev,
-                             int32_t cost_dtype, uint64_t* num_solutions, void* stream) {
+                             int32_t cost_dtype, uint64_t* num_solutions, void* stream) try {
     return qnae_build_cost_diagonal_pred(ctx, clauses, m, n, k, QNAE_PRED_NAE, cost_dev, cost_dtype, num_solutions,
                                          stream);
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"
@@ -123,14 +129,18 @@ extern "C" {
 
 int qnae_build_cost_diagonal_pred(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k,
                                   int32_t predicate, void* cost_dev, int32_t cost_dtype, uint64_t* num_solutions,
-                                  void* stream) {
+                                  void* stream) try {
     return build_cost(ctx, clauses, m, n, k, predicate, cost_dev, cost_dtype, num_solutions, stream, false);
+} catch (...) {
+    return host_exception();
 }
 
 int qnae_build_cost_diagonal_z2(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int32_t k, void* cost_dev,
-                                int32_t cost_dtype, uint64_t* num_solutions, void* stream) {
+                                int32_t cost_dtype, uint64_t* num_solutions, void* stream) try {
     if (n < 2) return fail(QNAE_EINVAL, "n=%d below 2 for a half diagonal", n);
     return build_cost(ctx, clauses, m, n, k, QNAE_PRED_NAE, cost_dev, cost_dtype, num_solutions, stream, true);
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"
@@ -223,23 +233,29 @@ extern "C" {
 
 int qnae_qaoa_run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
                   const double* gammas, const double* betas, int32_t p, void* state_dev, qnae_result* out,
-                  void* stream) {
+                  void* stream) try {
     return run(ctx, cost_dev, cost_dtype, n, m, gammas, betas, p, state_dev, out, stream, false);
+} catch (...) {
+    return host_exception();
 }
 
 int qnae_qaoa_run_z2(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
                      const double* gammas, const double* betas, int32_t p, void* state_dev, qnae_result* out,
-                     void* stream) {
+                     void* stream) try {
     return run(ctx, cost_dev, cost_dtype, n, m, gammas, betas, p, state_dev, out, stream, true);
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_profile_enable(qnae_ctx* ctx, int on) {
+int qnae_profile_enable(qnae_ctx* ctx, int on) try {
     if (!ctx) return fail(QNAE_EINVAL, "null context");
     ctx->prof.on = on != 0;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_profile_read(qnae_ctx* ctx, qnae_kernel_stat* out, int32_t capacity, int32_t* count) {
+int qnae_profile_read(qnae_ctx* ctx, qnae_kernel_stat* out, int32_t capacity, int32_t* count) try {
     if (!ctx || !count || (capacity > 0 && !out)) return fail(QNAE_EINVAL, "null argument");
     HIP_TRY(hipSetDevice(ctx->device));
     Profiler& P = ctx->prof;
@@ -265,6 +281,8 @@ int qnae_profile_read(qnae_ctx* ctx, qnae_kernel_stat* out, int32_t capacity, in
     }
     *count = c;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

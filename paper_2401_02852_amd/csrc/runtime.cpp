@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 
 #include "host.h"
 
@@ -106,7 +107,17 @@ std::complex<double> build_tables_from(int n, int m, const double* gammas, const
 }
 
 WorkerPool::WorkerPool(int workers) {
-    for (int i = 0; i < workers; ++i) threads_.emplace_back([this] { work(); });
+    try {
+        for (int i = 0; i < workers; ++i) threads_.emplace_back([this] { work(); });
+    } catch (...) {  // no thread may be left joinable when construction fails
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        wake_.notify_all();
+        for (std::thread& t : threads_) t.join();
+        throw;
+    }
 }
 
 WorkerPool::~WorkerPool() {
@@ -119,7 +130,15 @@ WorkerPool::~WorkerPool() {
 }
 
 void WorkerPool::drain() {
-    for (int i = next_.fetch_add(1); i < count_; i = next_.fetch_add(1)) (*fn_)(i);
+    for (int i = next_.fetch_add(1); i < count_; i = next_.fetch_add(1)) {
+        try {
+            (*fn_)(i);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (!error_) error_ = std::current_exception();
+            next_.store(count_);  // hand out no further items
+        }
+    }
 }
 
 void WorkerPool::work() {
@@ -152,6 +171,10 @@ void WorkerPool::run(int count, const std::function<void(int)>& fn) {
     std::unique_lock<std::mutex> lk(mu_);
     done_.wait(lk, [&] { return busy_ == 0; });
     fn_ = nullptr;
+    std::exception_ptr e = error_;
+    error_ = nullptr;
+    lk.unlock();
+    if (e) std::rethrow_exception(e);
 }
 
 void parallel_for(qnae_ctx* ctx, int count, size_t items, const std::function<void(int)>& fn) {
@@ -179,6 +202,18 @@ int fail(int code, const char* fmt, ...) {
 }
 
 const char* last_error() { return g_err.c_str(); }
+
+int host_exception() {
+    try {
+        throw;
+    } catch (const std::bad_alloc&) {
+        return fail(QNAE_ENOMEM, "host memory allocation failed");
+    } catch (const std::exception& e) {
+        return fail(QNAE_ENOMEM, "host resources: %s", e.what());
+    } catch (...) {
+        return fail(QNAE_ENOMEM, "host resources: unknown exception");
+    }
+}
 
 hipError_t DevBuf::reserve(size_t need) {
     if (need <= bytes) return hipSuccess;

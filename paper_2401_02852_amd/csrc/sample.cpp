@@ -11,7 +11,7 @@ using namespace qnae_host;
 extern "C" {
 
 int qnae_sample(qnae_ctx* ctx, const void* state_dev, int32_t n, const void* cost_dev, int32_t cost_dtype,
-                const double* uniforms, int32_t count, uint64_t* samples, int32_t* sample_costs, void* stream) {
+                const double* uniforms, int32_t count, uint64_t* samples, int32_t* sample_costs, void* stream) try {
     if (n < 1 || n > QNAE_MAX_N) return fail(QNAE_EINVAL, "n=%d outside [1, %d]", n, QNAE_MAX_N);
     if (count < 0 || count > (1 << 24)) return fail(QNAE_EINVAL, "count=%d outside [0, 2^24]", count);
     if (!state_dev) return fail(QNAE_EINVAL, "null state_dev");
@@ -52,6 +52,8 @@ int qnae_sample(qnae_ctx* ctx, const void* state_dev, int32_t n, const void* cos
     std::memcpy(samples, o, sizeof(uint64_t) * (size_t)count);
     if (sample_costs) std::memcpy(sample_costs, h + (cost_at - u_at), sizeof(int32_t) * (size_t)count);
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

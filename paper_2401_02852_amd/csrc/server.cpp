@@ -183,7 +183,7 @@ int fail_server(qnae_server* S, int code) {
 // tick_bytes, so that a lightly loaded server does not pay one host
 // round trip per sweep, and a heavily loaded one still admits new requests
 // often.
-int qnae_server::tick(std::vector<Request*>& admitted) {
+int qnae_server::tick(std::vector<Request*>& admitted) try {
     hipStream_t s = stream;
     if (fault_tick && ticks + 1 == fault_tick) return fail(QNAE_EHIP, "injected fault at scheduler tick %llu",
                                                            (unsigned long long)fault_tick);
@@ -413,6 +413,8 @@ int qnae_server::tick(std::vector<Request*>& admitted) {
     }
     cv_done.notify_all();
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 void qnae_server::run() {
@@ -466,7 +468,12 @@ void qnae_server::run() {
                 admitted.push_back(&r);
             }
         }
-        const int rc = tick(admitted);
+        int rc;
+        try {
+            rc = tick(admitted);
+        } catch (...) {  // host memory ran out inside the tick: fail like a device error
+            rc = host_exception();
+        }
         if (rc != QNAE_OK) {
             fail_server(this, rc);
             std::lock_guard<std::mutex> g(mu);
@@ -485,7 +492,7 @@ void qnae_server::run() {
 
 extern "C" {
 
-int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qnae_server** out) {
+int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qnae_server** out) try {
     if (!out) return fail(QNAE_EINVAL, "null output pointer");
     *out = nullptr;
     if (!ctx) return fail(QNAE_EINVAL, "null context");
@@ -503,21 +510,30 @@ int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qn
     if (const char* e = std::getenv("QNAE_FAULT_INJECT"))
         if (std::strncmp(e, "server_tick:", 12) == 0) S->fault_tick = std::strtoull(e + 12, nullptr, 10);
     if (const char* e = std::getenv("QNAE_SERVER_TICK_BYTES")) S->tick_bytes = std::max(1.0, std::atof(e));
+    S->buddy.reset(new Buddy(order));  // host allocations before the device ones
     HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
     hipError_t e = hipMalloc((void**)&S->pool, S->pool_bytes);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(S->stream);
         return fail(QNAE_ENOMEM, "server pool of %llu bytes: %s", (unsigned long long)S->pool_bytes, hipGetErrorString(e));
     }
-    S->buddy.reset(new Buddy(order));
     qnae_server* raw = S.release();
-    raw->worker = std::thread([raw] { raw->run(); });
+    try {
+        raw->worker = std::thread([raw] { raw->run(); });
+    } catch (...) {  // no scheduler thread: release what was allocated
+        (void)hipFree(raw->pool);
+        (void)hipStreamDestroy(raw->stream);
+        delete raw;
+        throw;
+    }
     *out = raw;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 int qnae_server_submit(qnae_server* S, const int32_t* clauses, int32_t m, int32_t n, int32_t k, const double* gammas,
-                       const double* betas, int32_t p, uint64_t* ticket) {
+                       const double* betas, int32_t p, uint64_t* ticket) try {
     if (!S || !ticket) return fail(QNAE_EINVAL, "null argument");
     const int dtype = m <= 255 ? QNAE_U8 : QNAE_U16;
     if (int rc = check_cost_args(n, m, dtype)) return rc;
@@ -556,9 +572,11 @@ int qnae_server_submit(qnae_server* S, const int32_t* clauses, int32_t m, int32_
     S->all.emplace(r->ticket, std::move(r));
     S->cv_work.notify_one();
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_server_wait(qnae_server* S, uint64_t ticket, int32_t timeout_ms, qnae_result* out, double* latency_s) {
+int qnae_server_wait(qnae_server* S, uint64_t ticket, int32_t timeout_ms, qnae_result* out, double* latency_s) try {
     if (!S || !out) return fail(QNAE_EINVAL, "null argument");
     std::unique_lock<std::mutex> lk(S->mu);
     auto it = S->all.find(ticket);
@@ -583,9 +601,11 @@ int qnae_server_wait(qnae_server* S, uint64_t ticket, int32_t timeout_ms, qnae_r
     if (latency_s) *latency_s = r->t_done - r->t_submit;
     S->all.erase(it);
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_server_cancel(qnae_server* S, uint64_t ticket) {
+int qnae_server_cancel(qnae_server* S, uint64_t ticket) try {
     if (!S) return fail(QNAE_EINVAL, "null server");
     std::lock_guard<std::mutex> g(S->mu);
     auto it = S->all.find(ticket);
@@ -604,17 +624,21 @@ int qnae_server_cancel(qnae_server* S, uint64_t ticket) {
             return QNAE_OK;
         default: return QNAE_OK;  // failed or already cancelled: it will not complete
     }
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_server_pool_in_use(qnae_server* S, uint64_t* bytes) {
+int qnae_server_pool_in_use(qnae_server* S, uint64_t* bytes) try {
     if (!S || !bytes) return fail(QNAE_EINVAL, "null argument");
     std::lock_guard<std::mutex> g(S->mu);
     *bytes = S->buddy->used();
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 int qnae_server_stats(qnae_server* S, uint64_t* completed, uint64_t* ticks, uint64_t* launches,
-                      uint64_t* peak_pool_bytes, uint64_t* queued, uint64_t* active) {
+                      uint64_t* peak_pool_bytes, uint64_t* queued, uint64_t* active) try {
     if (!S) return fail(QNAE_EINVAL, "null server");
     std::lock_guard<std::mutex> g(S->mu);
     if (completed) *completed = S->completed;
@@ -624,9 +648,11 @@ int qnae_server_stats(qnae_server* S, uint64_t* completed, uint64_t* ticks, uint
     if (queued) *queued = S->queue.size();
     if (active) *active = S->active.size();
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_server_destroy(qnae_server* S) {
+int qnae_server_destroy(qnae_server* S) try {
     if (!S) return QNAE_OK;
     {
         std::lock_guard<std::mutex> g(S->mu);
@@ -642,6 +668,8 @@ int qnae_server_destroy(qnae_server* S) {
     (void)hipStreamDestroy(S->stream);
     delete S;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

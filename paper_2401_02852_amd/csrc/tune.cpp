@@ -42,7 +42,7 @@ int check_tune_target(int32_t n, int32_t dtype, int32_t lo) {
 
 extern "C" {
 
-int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qnae_tune* out, void* stream) {
+int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qnae_tune* out, void* stream) try {
     if (int rc = check_tune_target(n, cost_dtype, 1)) return rc;
     if (reps < 1 || reps > 1000) return fail(QNAE_EINVAL, "reps=%d outside [1, 1000]", reps);
     if (!out) return fail(QNAE_EINVAL, "null output pointer");
@@ -102,9 +102,11 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     ctx->tunes[{n, cost_dtype}] = best;
     *out = best;
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_set_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, const qnae_tune* tune) {
+int qnae_set_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, const qnae_tune* tune) try {
     if (!ctx) return fail(QNAE_EINVAL, "null context");
     if (int rc = check_tune_target(n, cost_dtype, kResidentMaxN + 1)) return rc;
     if (!tune) {
@@ -114,13 +116,17 @@ int qnae_set_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, const qnae_tune*
     if (int rc = check_shape(*tune)) return rc;
     ctx->tunes[{n, cost_dtype}] = qnae_tune{tune->tile_bits, tune->low_run_bits, tune->page_bit, tune->ms_per_layer};
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
-int qnae_get_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, qnae_tune* out) {
+int qnae_get_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, qnae_tune* out) try {
     if (!ctx || !out) return fail(QNAE_EINVAL, "null argument");
     if (int rc = check_tune_target(n, cost_dtype, kResidentMaxN + 1)) return rc;
     *out = tune_for(ctx, n, cost_dtype);
     return QNAE_OK;
+} catch (...) {
+    return host_exception();
 }
 
 }  // extern "C"

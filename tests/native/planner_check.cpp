@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <stdexcept>
 #include <vector>
 
 #include "../../paper_2401_02852_amd/csrc/host.h"
@@ -163,6 +164,29 @@ static void check_worker_pool() {
                 pool.run(count, [&](int i) { hits[i].fetch_add(1); });
                 for (int i = 0; i < count; ++i) CHECK(hits[i].load() == 1);
             }
+        }
+        // a throwing item: the caller sees the exception after every worker
+        // is idle, no item runs twice, and the pool serves the next run
+        for (int rep = 0; rep < 20; ++rep) {
+            const int count = 500;
+            std::vector<std::atomic<int>> hits(count);
+            for (auto& h : hits) h.store(0);
+            bool thrown = false;
+            try {
+                pool.run(count, [&](int i) {
+                    hits[i].fetch_add(1);
+                    if (i == 37 || i == 400) throw std::runtime_error("item failed");
+                });
+            } catch (const std::runtime_error&) {
+                thrown = true;
+            }
+            CHECK(thrown);
+            CHECK(hits[37].load() == 1);
+            for (int i = 0; i < count; ++i) CHECK(hits[i].load() <= 1);
+            std::vector<std::atomic<int>> again(64);
+            for (auto& h : again) h.store(0);
+            pool.run(64, [&](int i) { again[i].fetch_add(1); });
+            for (int i = 0; i < 64; ++i) CHECK(again[i].load() == 1);
         }
     }
 }
