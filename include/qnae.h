@@ -62,8 +62,12 @@ enum {
 
 /* Create a context on HIP device `device` (make it current first if the
  * caller uses several). The context owns reusable device scratch (the state
- * when the caller passes none, block partial sums, phase tables) and pinned
- * host staging. *out is set to NULL on failure. */
+ * when the caller passes none, block partial sums, phase tables), pinned
+ * host staging and a small host thread pool. Every call on a context uses
+ * that scratch, so calls on one context must not overlap: use one context per
+ * calling thread. A server made from a context keeps its own pool, stream and
+ * buffers and reads only the context's tile settings. *out is set to NULL on
+ * failure. */
 int qnae_create(qnae_ctx **out, int device);
 
 /* Release the context and everything it owns. Waits for its work. NULL is a

@@ -264,15 +264,21 @@ def _tune_dict(t) -> dict:
             "ms_per_layer": float(t.ms_per_layer)}
 
 
-_default = {}
+_default = threading.local()
 
 
 def default_context() -> Context:
+    """The calling thread's context on the current device: calls on one
+    context must not overlap, and ctypes releases the GIL during a call, so
+    each thread gets its own."""
     import torch
     dev = torch.cuda.current_device()
-    if dev not in _default:
-        _default[dev] = Context(dev)
-    return _default[dev]
+    ctxs = getattr(_default, "by_device", None)
+    if ctxs is None:
+        ctxs = _default.by_device = {}
+    if dev not in ctxs:
+        ctxs[dev] = Context(dev)
+    return ctxs[dev]
 
 
 def cost_dtype_for(m: int):

@@ -273,3 +273,42 @@ def test_ring_closed_form_at_scale(q, n):
         assert abs(r.norm - 1) < 1e-5
     del c
     torch.cuda.empty_cache()
+
+
+def test_default_context_per_thread(q):
+    """Calls on one context must not overlap, so each thread's default
+    context is its own: two threads solving at once (n = 18 and 20, tiled
+    path) give the same results as one thread solving both in turn."""
+    import threading
+    a = q.default_context()
+    assert q.default_context() is a
+    jobs = []
+    for n, seed in ((18, 1), (20, 2)):
+        m = inst.clause_count(n, 2.1)
+        cl = inst.instance(n, 3, m, seed)
+        g, b = inst.ramp_angles(6)
+        jobs.append((n, m, cl, g, -b))
+    c0 = q.Context()  # untuned, like the threads' new default contexts
+    alone = []
+    for n, m, cl, g, b in jobs:
+        alone.append(tuple(q.qaoa_run(q.build_cost_diagonal(cl, n, ctx=c0), n, m, g, b, ctx=c0)))
+    got, ctxs, errors = [None, None], [None, None], []
+
+    def worker(i):
+        try:
+            n, m, cl, g, b = jobs[i]
+            ctxs[i] = q.default_context()
+            for _ in range(5):
+                got[i] = tuple(q.qaoa_run(q.build_cost_diagonal(cl, n), n, m, g, b))
+        except Exception as e:  # reported on the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    assert ctxs[0] is not ctxs[1] and a not in ctxs
+    for g_, a_ in zip(got, alone):
+        assert g_ == a_
