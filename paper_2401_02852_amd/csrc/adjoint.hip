@@ -78,12 +78,14 @@ __device__ __forceinline__ void xpose2(float2* lds, float2 (&l)[32], float2 (&p)
     from_lds<TB, TO>(lds, p, lane, wave);
 }
 
-// The inverse-mixer-only kinds are register-allocated for two waves per SIMD
-// (a few spills, measured 5% faster per gradient at n = 22); the boundary
-// kind, which also carries the phase and the cost values, stays at one (at two
-// it spills heavily).
+// Every kind is register-allocated for two waves per SIMD: two states of 32
+// amplitudes per thread do not fit in 128 registers with the mixing's
+// temporaries, and the spills at two waves cost less than the latency left
+// unhidden at one (the inverse-mixer-only kinds 5% and the boundary kind,
+// after the fence before its inverse mixing, another 5% per gradient at
+// n = 22).
 template <typename CT, int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == AK_BOUNDARY ? 1 : 2))) void adjoint_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void adjoint_kernel(
     const AdjointArgs a) {
     constexpr int TB = kAdjointTileBits;
     constexpr int WB = TB - 11;
@@ -175,6 +177,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == AK_
             p[j] = cmul(p[j], e);
         }
     }
+    // No memory access moves across this point: without it the compiler
+    // interleaves the phase step's table reads with the inverse mixing below
+    // and the boundary kind needs 440 registers instead of 344 (172 rather
+    // than 252 spilled at two waves per SIMD). It orders nothing that
+    // another thread depends on.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (POST) {
         const uint32_t m = a.post_mask;
         adj_mix(l, p, L::sm2(m), a.post_c, a.post_s, acc_post);
