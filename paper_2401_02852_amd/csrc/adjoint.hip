@@ -113,7 +113,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
             if ((e >> i) & 1u) x |= bitval[i];
         return x;
     };
-    uint64_t w = ntiles >= 8 ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
+    // Tiles dealt to the 8 XCDs round-robin in chunks of 16 consecutive tiles
+    // (a bijection: ntiles is a power of two), so the XCDs work on
+    // neighbouring chunks at once: 1.3% per gradient at n = 22 against one
+    // contiguous eighth of the tiles per XCD (chunks of 32: 0.9%).
+    constexpr uint32_t kChunk = 16;
+    uint64_t w = ntiles >= 8 * kChunk
+        ? (uint64_t)((t >> 3) / kChunk) * (8 * kChunk) + (uint64_t)(t & 7u) * kChunk + ((t >> 3) % kChunk)
+        : ntiles >= 8 ? (uint64_t)(t & 7u) * (ntiles >> 3) + (t >> 3) : (uint64_t)t;
     uint64_t base = 0;
     for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull) {
         if (w & 1ull) base |= m & (~m + 1ull);
