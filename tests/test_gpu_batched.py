@@ -163,3 +163,19 @@ def test_batched_half_state_instances(q):
         small = [k for k, x in enumerate(batch) if x["n"] <= 14][0]
         q.qaoa_run_batched([costs[small][: 1 << (ns[small] - 1)]], [ns[small]], [ms[small]], [gs[small]], [bs[small]],
                            half=True)
+
+
+def test_empty_batches(q):
+    """Zero instances: every batched entry point returns empty results and
+    the context still serves the next call."""
+    assert q.build_cost_diagonals([], []) == []
+    costs, sols = q.build_cost_diagonals([], [], count_solutions=True)
+    assert costs == [] and len(sols) == 0
+    assert q.qaoa_run_batched([], [], [], [], []) == []
+    dgs, dbs, res = q.qaoa_grad_batched([], [], [], [], [])
+    assert dgs == [] and dbs == [] and res == []
+    cl = inst.instance(9, 3, 19, 3)
+    c = q.build_cost_diagonal(cl, 9)
+    g, b = inst.ramp_angles(3)
+    got = q.qaoa_run_batched([c], [9], [19], [g], [-b])
+    assert np.allclose(got[0], q.qaoa_run(c, 9, 19, g, -b), rtol=1e-12, atol=1e-15)
