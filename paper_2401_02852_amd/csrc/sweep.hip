@@ -424,9 +424,14 @@ __device__ __forceinline__ void mix16(float2 (&v)[16], int nb, float t) {
     if (nb > 3) bfly<16, 3>(v, t);
 }
 
+// LDS slot of amplitude x: one pad slot per 16, so that the threads of the
+// bits-0..3 pass, each holding 16 consecutive amplitudes, fall in different
+// banks instead of all in one (a stride of 16 float2 is 32 banks).
+__device__ __forceinline__ uint32_t rslot(uint32_t x) { return x + (x >> 4); }
+
 template <typename CT>
 __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
-    __shared__ float2 s[1 << 14];
+    __shared__ float2 s[(1 << 14) + (1 << 10)];
     __shared__ double red[3][4];
     const int n = a.n;
     const uint32_t N = 1u << n;
@@ -441,7 +446,7 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
         const float2* lut = a.luts + (size_t)l * a.lut_len;
         for (uint32_t x = tid; x < N; x += 256) {
             const float2 e = lut[min((uint32_t)cost[x ^ flip], last)];
-            s[x] = l > 0 ? cmul(s[x], e) : a.state_in ? cmul(a.state_in[x], e) : e;
+            s[rslot(x)] = l > 0 ? cmul(s[rslot(x)], e) : a.state_in ? cmul(a.state_in[x], e) : e;
         }
         __syncthreads();
         if (a.p == 0) break;
@@ -453,11 +458,12 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
                 const uint32_t bs = ((task >> g0) << (g0 + nb)) | (task & ((1u << g0) - 1u));
                 float2 v[16];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) v[i] = i < (1 << nb) ? s[bs | ((uint32_t)i << g0)] : make_float2(0.f, 0.f);
+                for (int i = 0; i < 16; ++i)
+                    v[i] = i < (1 << nb) ? s[rslot(bs | ((uint32_t)i << g0))] : make_float2(0.f, 0.f);
                 mix16(v, nb, f.t);
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
-                    if (i < (1 << nb)) s[bs | ((uint32_t)i << g0)] = v[i];
+                    if (i < (1 << nb)) s[rslot(bs | ((uint32_t)i << g0))] = v[i];
             }
             __syncthreads();
         }
@@ -465,7 +471,7 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
     }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
     for (uint32_t x = tid; x < N; x += 256) {
-        const float2 q = s[x];
+        const float2 q = s[rslot(x)];
         const float pr = fmaf(q.x, q.x, q.y * q.y);
         const uint32_t cx = cost[x ^ flip];
         s2 += pr;
