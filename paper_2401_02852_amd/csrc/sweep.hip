@@ -429,10 +429,15 @@ __device__ __forceinline__ void mix16(float2 (&v)[16], int nb, float t) {
 // banks instead of all in one (a stride of 16 float2 is 32 banks).
 __device__ __forceinline__ uint32_t rslot(uint32_t x) { return x + (x >> 4); }
 
+// 1024 threads: one workgroup's 136 KiB of LDS leaves room for no second one
+// on a CU, so its own waves (four per SIMD) hide the LDS latency.
+constexpr int kResidentThreads = 1024;
+
 template <typename CT>
 __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
+    constexpr uint32_t NT = kResidentThreads;
     __shared__ float2 s[(1 << 14) + (1 << 10)];
-    __shared__ double red[3][4];
+    __shared__ double red[3][NT / 64];
     const int n = a.n;
     const uint32_t N = 1u << n;
     const uint32_t tid = threadIdx.x;
@@ -444,7 +449,7 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
     uint32_t flip = 0u;
     for (int l = 0; l < layers; ++l) {
         const float2* lut = a.luts + (size_t)l * a.lut_len;
-        for (uint32_t x = tid; x < N; x += 256) {
+        for (uint32_t x = tid; x < N; x += NT) {
             const float2 e = lut[min((uint32_t)cost[x ^ flip], last)];
             s[rslot(x)] = l > 0 ? cmul(s[rslot(x)], e) : a.state_in ? cmul(a.state_in[x], e) : e;
         }
@@ -454,7 +459,7 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
         for (int g0 = 0; g0 < n; g0 += 4) {
             const int nb = n - g0 < 4 ? n - g0 : 4;
             const uint32_t tasks = N >> nb;
-            for (uint32_t task = tid; task < tasks; task += 256) {
+            for (uint32_t task = tid; task < tasks; task += NT) {
                 const uint32_t bs = ((task >> g0) << (g0 + nb)) | (task & ((1u << g0) - 1u));
                 float2 v[16];
 #pragma unroll
@@ -470,7 +475,7 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
         if (f.flip) flip ^= N - 1u;
     }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (uint32_t x = tid; x < N; x += 256) {
+    for (uint32_t x = tid; x < N; x += NT) {
         const float2 q = s[rslot(x)];
         const float pr = fmaf(q.x, q.x, q.y * q.y);
         const uint32_t cx = cost[x ^ flip];
@@ -491,17 +496,21 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
         red[2][tid >> 6] = d2;
     }
     __syncthreads();
-    if (tid < 3) a.out[tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+    if (tid < 3) {
+        double sum = 0.0;
+        for (uint32_t w = 0; w < NT / 64; ++w) sum += red[tid][w];
+        a.out[tid] = sum;
+    }
 }
 
 template <typename CT>
-__global__ __launch_bounds__(256) void resident_kernel(const ResidentArgs a) {
+__global__ __launch_bounds__(kResidentThreads) void resident_kernel(const ResidentArgs a) {
     resident_body<CT>(a);
 }
 
 // Many small instances, one workgroup each.
 template <typename CT>
-__global__ __launch_bounds__(256) void resident_batch_kernel(const ResidentArgs* args) {
+__global__ __launch_bounds__(kResidentThreads) void resident_batch_kernel(const ResidentArgs* args) {
     const ResidentArgs a = args[blockIdx.x];
     resident_body<CT>(a);
 }
@@ -619,17 +628,17 @@ hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s) {
 
 hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s) {
     if (dtype == 1)
-        hipLaunchKernelGGL((resident_kernel<uint8_t>), dim3(1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((resident_kernel<uint8_t>), dim3(1), dim3(kResidentThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((resident_kernel<uint16_t>), dim3(1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((resident_kernel<uint16_t>), dim3(1), dim3(kResidentThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_resident_batch(int dtype, const ResidentArgs* args, int count, hipStream_t s) {
     if (dtype == 1)
-        hipLaunchKernelGGL((resident_batch_kernel<uint8_t>), dim3(count), dim3(256), 0, s, args);
+        hipLaunchKernelGGL((resident_batch_kernel<uint8_t>), dim3(count), dim3(kResidentThreads), 0, s, args);
     else
-        hipLaunchKernelGGL((resident_batch_kernel<uint16_t>), dim3(count), dim3(256), 0, s, args);
+        hipLaunchKernelGGL((resident_batch_kernel<uint16_t>), dim3(count), dim3(kResidentThreads), 0, s, args);
     return hipGetLastError();
 }
 
