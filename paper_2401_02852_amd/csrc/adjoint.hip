@@ -252,12 +252,17 @@ __global__ __launch_bounds__(256) void weight_kernel(const CT* cost, const float
 // Whole gradient for n <= 13 in one workgroup.
 // ---------------------------------------------------------------------------
 
+// 1024 threads: the two resident states fill 128 KiB of a CU's LDS, so no
+// second workgroup fits and the workgroup's own waves (four per SIMD) hide
+// the LDS latency.
+constexpr int kResidentGradThreads = 1024;
+
 // Pairs (x, x | 2^j) of bit j over the resident states: first Im<l|X_j|p>
 // (when l != null) then a' = c a - i s b on every state given.
 __device__ __forceinline__ float resident_bit(float2* l, float2* p, uint32_t N, int j, float c, float s) {
     float acc = 0.f;
     const uint32_t bit = 1u << j;
-    for (uint32_t task = threadIdx.x; task < N / 2; task += 256) {
+    for (uint32_t task = threadIdx.x; task < N / 2; task += kResidentGradThreads) {
         const uint32_t x = ((task >> j) << (j + 1)) | (task & (bit - 1u));
         const uint32_t y = x | bit;
         const float2 pa = p[x], pb = p[y];
@@ -277,19 +282,23 @@ __device__ __forceinline__ float resident_bit(float2* l, float2* p, uint32_t N, 
     return acc;
 }
 
+// Sum over the workgroup: wave sums, then the wave totals in wave order.
 __device__ __forceinline__ double block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    double sum = 0.0;
+    for (int w = 0; w < kResidentGradThreads / 64; ++w) sum += red[w];
+    return sum;
 }
 
 template <typename CT>
 __device__ __forceinline__ void resident_grad_body(const ResidentGradArgs& a) {
     __shared__ float2 ls[1 << 13];
     __shared__ float2 ps[1 << 13];
-    __shared__ double red[4];
+    __shared__ double red[kResidentGradThreads / 64];
+    constexpr uint32_t NT = kResidentGradThreads;
     const int n = a.n;
     const uint32_t N = 1u << n;
     const uint32_t tid = threadIdx.x;
@@ -299,7 +308,7 @@ __device__ __forceinline__ void resident_grad_body(const ResidentGradArgs& a) {
     // forward
     for (int l = 0; l < a.p; ++l) {
         const float2* lut = a.luts + (size_t)l * a.lut_len;
-        for (uint32_t x = tid; x < N; x += 256) {
+        for (uint32_t x = tid; x < N; x += NT) {
             const float2 e = lut[min((uint32_t)cost[x], last)];
             ps[x] = l == 0 ? make_float2(amp * e.x, amp * e.y) : cmul(ps[x], e);
         }
@@ -308,15 +317,15 @@ __device__ __forceinline__ void resident_grad_body(const ResidentGradArgs& a) {
         for (int j = 0; j < n; ++j) resident_bit(nullptr, ps, N, j, cs.x, cs.y);
         if ((l + 1) % a.every == 0 && l + 1 < a.p) {
             float2* ck = a.ckpt + (size_t)((l + 1) / a.every - 1) * N;
-            for (uint32_t x = tid; x < N; x += 256) ck[x] = ps[x];
+            for (uint32_t x = tid; x < N; x += NT) ck[x] = ps[x];
         }
     }
     if (a.p == 0)
-        for (uint32_t x = tid; x < N; x += 256) ps[x] = make_float2(amp, 0.f);
+        for (uint32_t x = tid; x < N; x += NT) ps[x] = make_float2(amp, 0.f);
     __syncthreads();
     // readout and lam = W psi
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (uint32_t x = tid; x < N; x += 256) {
+    for (uint32_t x = tid; x < N; x += NT) {
         const float2 v = ps[x];
         const uint32_t c = cost[x];
         const float pr = fmaf(v.x, v.x, v.y * v.y);
@@ -342,7 +351,7 @@ __device__ __forceinline__ void resident_grad_body(const ResidentGradArgs& a) {
         for (int j = 0; j < n; ++j) accb += resident_bit(ls, ps, N, j, cs.x, -cs.y);
         const float2* lut = a.luts + (size_t)l * a.lut_len;
         float accg = 0.f;
-        for (uint32_t x = tid; x < N; x += 256) {
+        for (uint32_t x = tid; x < N; x += NT) {
             const uint32_t c = cost[x];
             const float2 lv = ls[x], pv = ps[x];
             accg = fmaf((float)c, fmaf(lv.x, pv.y, -lv.y * pv.x), accg);
@@ -359,20 +368,20 @@ __device__ __forceinline__ void resident_grad_body(const ResidentGradArgs& a) {
         }
         if (l % a.every == 0 && l > 0) {
             const float2* ck = a.ckpt + (size_t)(l / a.every - 1) * N;
-            for (uint32_t x = tid; x < N; x += 256) ps[x] = ck[x];
+            for (uint32_t x = tid; x < N; x += NT) ps[x] = ck[x];
         }
         __syncthreads();
     }
 }
 
 template <typename CT>
-__global__ __launch_bounds__(256) void resident_grad_kernel(const ResidentGradArgs a) {
+__global__ __launch_bounds__(kResidentGradThreads) void resident_grad_kernel(const ResidentGradArgs a) {
     resident_grad_body<CT>(a);
 }
 
 // Many small gradients, one workgroup each.
 template <typename CT>
-__global__ __launch_bounds__(256) void resident_grad_batch_kernel(const ResidentGradArgs* args) {
+__global__ __launch_bounds__(kResidentGradThreads) void resident_grad_batch_kernel(const ResidentGradArgs* args) {
     const ResidentGradArgs a = args[blockIdx.x];
     resident_grad_body<CT>(a);
 }
@@ -414,17 +423,19 @@ hipError_t launch_weight(int dtype, const void* cost, const float2* psi, float2*
 
 hipError_t launch_resident_grad_batch(int dtype, const ResidentGradArgs* args, int count, hipStream_t s) {
     if (dtype == 1)
-        hipLaunchKernelGGL(resident_grad_batch_kernel<uint8_t>, dim3((uint32_t)count), dim3(256), 0, s, args);
+        hipLaunchKernelGGL(resident_grad_batch_kernel<uint8_t>, dim3((uint32_t)count), dim3(kResidentGradThreads), 0, s,
+                           args);
     else
-        hipLaunchKernelGGL(resident_grad_batch_kernel<uint16_t>, dim3((uint32_t)count), dim3(256), 0, s, args);
+        hipLaunchKernelGGL(resident_grad_batch_kernel<uint16_t>, dim3((uint32_t)count), dim3(kResidentGradThreads), 0, s,
+                           args);
     return hipGetLastError();
 }
 
 hipError_t launch_resident_grad(int dtype, const ResidentGradArgs& a, hipStream_t s) {
     if (dtype == 1)
-        hipLaunchKernelGGL(resident_grad_kernel<uint8_t>, dim3(1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(resident_grad_kernel<uint8_t>, dim3(1), dim3(kResidentGradThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(resident_grad_kernel<uint16_t>, dim3(1), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(resident_grad_kernel<uint16_t>, dim3(1), dim3(kResidentGradThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -7,8 +7,10 @@
 // lam = W psi_p; then for each segment from the last, reverse sweeps take lam
 // and that segment's checkpoint (psi, uncomputed in place) through the inverse
 // layers, summing the inner products per tile.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "host.h"
@@ -273,9 +275,22 @@ int qnae_qaoa_grad_batched(qnae_ctx* ctx, const qnae_grad_job* jobs, int32_t cou
         HIP_TRY(ctx->g_states.reserve(C.size));
         char* h = (char*)ctx->h_blob.ptr;
         char* d = (char*)ctx->g_blob.ptr;
-        for (int g = 0; g < 2; ++g) {
-            qnae::ResidentGradArgs* args = (qnae::ResidentGradArgs*)(h + args_at[g]);
+        // Tables and arguments job by job, chunks of jobs over the context's
+        // host threads (each job writes only its own rows and argument slot).
+        std::vector<std::pair<int, int>> work;  // (cost type, position in its launch)
+        size_t entries = 0;
+        for (int g = 0; g < 2; ++g)
             for (size_t q = 0; q < small[g].size(); ++q) {
+                work.emplace_back(g, (int)q);
+                entries += (size_t)jobs[small[g][q]].p * (size_t)(jobs[small[g][q]].m + 1);
+            }
+        constexpr int kChunk = 16;
+        parallel_for(ctx, ((int)work.size() + kChunk - 1) / kChunk, entries, [&](int chunk) {
+            const int w_end = std::min((int)work.size(), (chunk + 1) * kChunk);
+            for (int w = chunk * kChunk; w < w_end; ++w) {
+                const int g = work[w].first;
+                const size_t q = (size_t)work[w].second;
+                qnae::ResidentGradArgs* args = (qnae::ResidentGradArgs*)(h + args_at[g]);
                 const int i = small[g][q];
                 const qnae_grad_job& j = jobs[i];
                 const int lut_len = j.m + 1;
@@ -298,7 +313,7 @@ int qnae_qaoa_grad_batched(qnae_ctx* ctx, const qnae_grad_job* jobs, int32_t cou
                 a.lut_len = lut_len;
                 a.every = every;
             }
-        }
+        });
         HIP_TRY(hipMemcpyAsync(d, h, B.size, hipMemcpyHostToDevice, s));
         for (int g = 0; g < 2; ++g) {
             if (small[g].empty()) continue;
