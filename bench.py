@@ -303,6 +303,33 @@ def sampling_bench(q, ctx, draws=100_000, ensemble=200):
     return out
 
 
+def latency_bench(q, ctx, reps=200):
+    """Launch-bound single solves: the n = 12, m = 25, p = 3 parity instance
+    (linear ramp), one synchronous call at a time, with the cost diagonal
+    resident and with its build included. Per-call wall time in microseconds."""
+    import numpy as np
+    import torch
+    rec, cl, g, b = load_workload("nae3_n12_p3")
+    n, m = rec["n"], rec["m"]
+    cost = q.build_cost_diagonal(cl, n, ctx=ctx)
+    torch.cuda.synchronize()
+
+    def times(fn):
+        for _ in range(10):
+            fn()
+        out = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            out.append((time.perf_counter() - t0) * 1e6)
+        return np.percentile(out, 50), np.percentile(out, 99)
+
+    run50, run99 = times(lambda: q.qaoa_run(cost, n, m, g, b, ctx=ctx))
+    both50, both99 = times(lambda: q.qaoa_run(q.build_cost_diagonal(cl, n, out=cost, ctx=ctx), n, m, g, b, ctx=ctx))
+    return {"workload": f"n={n} m={m} p=3 3-NAE-SAT (seed {rec['seed']}), linear ramp; {reps} calls",
+            "run_p50_us": run50, "run_p99_us": run99, "build_and_run_p50_us": both50, "build_and_run_p99_us": both99}
+
+
 def grad_bench(q, ctx, reps=10, adam_steps=200):
     """Differentiation workload: n = 22, m = 46, p = 12 from the linear ramp
     (beta negated), checkpoints every 4 layers. Time of one adjoint gradient
@@ -434,6 +461,7 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
@@ -448,7 +476,8 @@ def main():
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.headline_only:
-        for leg in ("cpu_baseline", "scale", "batched", "serving", "grad", "sampling", "z2", "pretrain", "autotune"):
+        for leg in ("cpu_baseline", "scale", "latency", "batched", "serving", "grad", "sampling", "z2", "pretrain",
+                    "autotune"):
             setattr(args, "no_" + leg, True)
     if args.calibrate_copy:
         import torch
@@ -532,6 +561,8 @@ def main():
     }
     if not args.no_scale:
         out["scale"] = scale_bench(q, ctx)
+    if not args.no_latency:
+        out["latency"] = latency_bench(q, ctx)
     if not args.no_batched:
         out["batched"] = batched_bench(q, ctx)
     if not args.no_grad:
