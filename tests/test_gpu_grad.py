@@ -87,6 +87,30 @@ def test_grad_special_cases(q, n):
     assert np.max(np.abs(db)) < tol
 
 
+def test_grad_three_groups_n23(q):
+    """n = 23 is the smallest size whose layers take three qubit groups at
+    13-bit tiles, so the reverse pass runs every adjoint kind, including the
+    inverse mixer alone in the middle of a layer; satisfiable instance (seed
+    124, 2 solutions), checkpoints every 2 of 3 layers, against the oracle's
+    adjoint."""
+    import torch
+    n, p = 23, 3
+    rng = np.random.default_rng(23)
+    m = inst.clause_count(n, 2.1)
+    cl = inst.instance(n, 3, m, 124)
+    g, b = rng.uniform(0, 1.5, p), rng.uniform(-1, 1, p)
+    c = q.build_cost_diagonal(cl, n)
+    cost = oracle.cost(cl, n)
+    assert int((cost == 0).sum()) == 2
+    for w in [(1.0, 0.0), (0.0, 1.0)]:
+        dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=2)
+        rg, rb, ro = oracle.qaoa_grad(cost, n, g, b, *w)
+        check(dg, db, rg, rb, w)
+        assert abs(r.p_success - ro[0]) <= 1e-5 and abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1]
+    del c
+    torch.cuda.empty_cache()
+
+
 def test_grad_workload_n22_p12(q, golden):
     """The differentiation workload: n = 22, m = 46, p = 12 from the linear
     ramp (beta negated), checkpoints every 4 layers, against the oracle's
