@@ -259,6 +259,32 @@ def test_workloads_vs_stored_oracle(q, golden, name):
     torch.cuda.empty_cache()
 
 
+def test_n30_workload_every_tile_shape(q, golden):
+    """The n = 30 workload (the benchmark's step) under every tile shape the
+    autotuner may choose, against the stored oracle values: the timed launch
+    configuration is covered whichever shape it keeps."""
+    import torch
+    rec = golden["nae3_n30_p10"]
+    n, k, m, p = rec["n"], rec["k"], rec["m"], rec["p"]
+    free, _ = torch.cuda.mem_get_info()
+    if free < (10 << 30):
+        pytest.skip("not enough device memory")
+    cl = inst.instance(n, k, m, rec["seed"])
+    ctx = q.Context()
+    c = q.build_cost_diagonal(cl, n, ctx=ctx)
+    ref = rec["results"]["ramp_min"]
+    g, b = inst.ramp_angles(p)
+    for tb in (12, 13, 14):
+        for low in (4, 5, 6):
+            for page in (18, 64):
+                ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": low, "page_bit": page})
+                r = q.qaoa_run(c, n, m, g, -b, ctx=ctx)
+                check_result(r, (ref["p_success"], ref["expected_cost"], ref["norm"]), f"shape {tb}/{low}/{page}")
+    ctx.close()
+    del c
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n", [24, 30])
 def test_ring_closed_form_at_scale(q, n):
     """k = 2 ring of all-positive clauses at p = 1:
