@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <string>
+#include <new>
 #include <stdexcept>
 #include <vector>
 
@@ -191,10 +193,35 @@ static void check_worker_pool() {
     }
 }
 
+// Entry points end in a catch-all that turns the exception being handled
+// into a status code and this thread's last error.
+static void check_host_exception() {
+    int rc = 0;
+    try {
+        throw std::bad_alloc();
+    } catch (...) {
+        rc = host_exception();
+    }
+    CHECK(rc == QNAE_ENOMEM && std::string(last_error()).find("allocation") != std::string::npos);
+    try {
+        throw std::runtime_error("thread limit");
+    } catch (...) {
+        rc = host_exception();
+    }
+    CHECK(rc == QNAE_ENOMEM && std::string(last_error()).find("thread limit") != std::string::npos);
+    try {
+        throw 7;
+    } catch (...) {
+        rc = host_exception();
+    }
+    CHECK(rc == QNAE_ENOMEM && std::string(last_error()).find("unknown") != std::string::npos);
+}
+
 int main() {
     check_groups_and_plans();
     check_clause_records();
     check_phase_rows();
+    check_host_exception();
     check_worker_pool();
     std::printf("planner and clause records ok\n");
     return 0;
