@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def load_workload(name):
-    from paper_2401_02852_amd import instances as inst
+    from workloads import instances as inst
     with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
         rec = json.load(f)[name]
     n, k, r, p, _ = inst.SINGLE_WORKLOADS[name]
@@ -43,7 +43,7 @@ def cpu_baseline(sample_n: int, single_n: int = 22):
     with sample_n variables and m = round(2.1 n), on all host threads; and the
     same at single_n variables on one thread."""
     import oracle
-    from paper_2401_02852_amd import instances as inst
+    from workloads import instances as inst
 
     def run(n):
         p = 10
@@ -129,7 +129,7 @@ def batched_bench(q, ctx, reps=5, count=512):
     instance-layers/s of the batched path and of the plain path (one
     qnae_build_cost_diagonal + qnae_qaoa_run per instance) on the same GPU."""
     import torch
-    from paper_2401_02852_amd import instances as inst
+    from workloads import instances as inst
     batch = inst.batched_workload(count=count)
     ns = [x["n"] for x in batch]
     ms = [x["m"] for x in batch]
@@ -256,7 +256,7 @@ def sampling_bench(q, ctx, draws=100_000, ensemble=200):
     running time against 1/mean(p_succ)."""
     import numpy as np
     import torch
-    from paper_2401_02852_amd import instances as inst
+    from workloads import instances as inst
     rec, cl, g, b = load_workload("nae3_n30_p10")
     n, m = rec["n"], rec["m"]
     cost = q.build_cost_diagonal(cl, n, ctx=ctx)
@@ -380,7 +380,7 @@ def serving_bench(q, ctx, count=2000, warm=100, rate=200.0):
     import threading
     import numpy as np
     import torch
-    from paper_2401_02852_amd import instances as inst
+    from workloads import instances as inst
     trace = inst.serving_workload(count=count, rate=rate)
     layers = sum(r["p"] for r in trace[warm:])
     pct = lambda a, x: float(np.percentile(np.asarray(a), x)) * 1e3

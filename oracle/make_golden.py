@@ -23,7 +23,7 @@ import time
 import numpy as np
 
 import oracle
-from paper_2401_02852_amd import instances as inst
+from workloads import instances as inst
 
 OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                    "tests", "golden", "workloads.json")

@@ -23,7 +23,7 @@ from ._binding import (  # noqa: F401
     qaoa_run,
     qaoa_run_batched,
     qaoa_run_z2,
-    running_time,
     sample,
 )
 from .autograd import QAOAFunction  # noqa: F401
+from .pretrain import running_time  # noqa: F401

@@ -581,13 +581,6 @@ def sample(state, n: int, uniforms, *, cost=None, ctx: Optional[Context] = None,
     return out, costs
 
 
-def running_time(sample_costs) -> int:
-    """Instance running time (Section 4.2): draws until the first satisfying
-    one (cost 0), counting it; 0 when none of the draws satisfies."""
-    hit = np.flatnonzero(np.asarray(sample_costs) == 0)
-    return int(hit[0]) + 1 if hit.size else 0
-
-
 class Server:
     """Continuous-batching solve server (qnae_server_*): submit instances,
     collect results; requests share GPU launches while they are active."""

@@ -20,9 +20,15 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
-from . import instances as inst
-from ._binding import (Context, build_cost_diagonals, default_context, qaoa_grad_batched, qaoa_run_batched,
-                       running_time, sample)
+from workloads import instances as inst
+from ._binding import Context, build_cost_diagonals, default_context, qaoa_grad_batched, qaoa_run_batched, sample
+
+
+def running_time(sample_costs) -> int:
+    """Instance running time (Section 4.2): draws until the first satisfying
+    one (cost 0), counting it; 0 when none of the draws satisfies."""
+    hit = np.flatnonzero(np.asarray(sample_costs) == 0)
+    return int(hit[0]) + 1 if hit.size else 0
 
 
 def r_hat(k: int) -> float:

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2401_02852_amd import instances as inst
+from workloads import instances as inst
 
 pytestmark = pytest.mark.gpu
 

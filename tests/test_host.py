@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from paper_2401_02852_amd import instances as inst
+from workloads import instances as inst
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -173,11 +173,11 @@ def test_sample_validation_without_gpu():
     assert b"aligned" in lib.qnae_last_error(None)
     assert lib.qnae_sample(None, ctypes.c_void_p(0x1000), 10, None, 0, u, 1, out, None, None) == -1
     assert b"null context" in lib.qnae_last_error(None)
-    assert b.running_time([3, 2, 0, 1, 0]) == 3 and b.running_time([1, 1]) == 0
 
 
 def test_pretrain_host_logic():
     from paper_2401_02852_amd import pretrain
+    assert pretrain.running_time([3, 2, 0, 1, 0]) == 3 and pretrain.running_time([1, 1]) == 0
     assert abs(pretrain.r_hat(3) - 2.1760) < 1e-4 and abs(pretrain.r_hat(5) - 10.4938) < 1e-4
     ns = np.arange(12, 20)
     c, d = pretrain.fit_exponent(ns, 2.0 ** (-0.31 * ns + 1.7))

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from oracle import dense
-from paper_2401_02852_amd import instances as inst
+from workloads import instances as inst
 
 
 def rand_instance(n, k, m, seed):
