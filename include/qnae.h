@@ -87,7 +87,8 @@ const char *qnae_last_error(const qnae_ctx *ctx);
  *   clauses      host, m * k int32 literals (read before the call returns;
  *                may be NULL when m = 0)
  *   m, n, k      0 <= m <= 65535, 1 <= n <= QNAE_MAX_N, 1 <= k <= 64
- *   cost_dev     caller-owned device buffer of 2^n elements of cost_dtype
+ *   cost_dev     caller-owned device buffer of 2^n elements of cost_dtype,
+ *                16-byte aligned (written with 16-byte stores)
  *   cost_dtype   QNAE_U8 (requires m <= 255) or QNAE_U16
  *   num_solutions  optional host pointer; if not NULL the call waits for the
  *                stream and stores #{x : C(x) = 0}
@@ -124,9 +125,9 @@ int qnae_build_cost_diagonal_pred(qnae_ctx *ctx, const int32_t *clauses, int32_t
  *                layer l applies exp(-i gammas[l] C) then
  *                prod_j exp(-i betas[l] X_j)
  *   p            0 <= p <= 100000; p = 0 reads out |+>
- *   state_dev    optional caller-owned device complex64[2^n]; if not NULL
- *                it receives the final state, otherwise context scratch is
- *                used and the state is not kept
+ *   state_dev    optional caller-owned device complex64[2^n], 16-byte
+ *                aligned; if not NULL it receives the final state, otherwise
+ *                context scratch is used and the state is not kept
  *   out          host result
  *   stream       hipStream_t the work is enqueued on
  *
@@ -168,7 +169,7 @@ int qnae_qaoa_grad(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype, int3
 typedef struct {
     const int32_t *clauses;   /* host, m * k literals (NULL when m = 0) */
     int32_t m, n, k;
-    void *cost_dev;           /* caller-owned device buffer, 2^n of cost_dtype */
+    void *cost_dev;           /* caller-owned device buffer, 2^n of cost_dtype, 16-byte aligned */
     int32_t cost_dtype;       /* QNAE_U8 (m <= 255) or QNAE_U16 */
     uint64_t *num_solutions;  /* optional host pointer (the call then waits) */
     int32_t predicate;        /* QNAE_PRED_NAE (0) or QNAE_PRED_SAT */
@@ -184,11 +185,11 @@ int qnae_build_cost_diagonal_batched(qnae_ctx *ctx, const qnae_cost_job *jobs, i
 
 /* One QAOA solve of a batch: the arguments of qnae_qaoa_run. */
 typedef struct {
-    const void *cost_dev;  /* device, 2^n of cost_dtype, values in [0, m] */
+    const void *cost_dev;  /* device, 2^n of cost_dtype, values in [0, m], 16-byte aligned */
     int32_t cost_dtype, n, m, p;
     const double *gammas;  /* host, p entries (layer 0 first) */
     const double *betas;   /* host, p entries */
-    void *state_dev;       /* optional device complex64[2^n] for the final state */
+    void *state_dev;       /* optional device complex64[2^n] for the final state, 16-byte aligned */
     int32_t half;          /* 1: half-state solve as qnae_qaoa_run_z2 (n > 14; cost_dev
                               and state_dev then hold 2^(n-1) entries) */
 } qnae_instance;

@@ -281,6 +281,49 @@ def default_context() -> Context:
     return ctxs[dev]
 
 
+def _device_buffer(t, name: str, ctx: "Context", dtypes, numel: int) -> int:
+    """Address of a tensor handed to the library as a device buffer, after
+    checking what the kernels assume of it: on this context's GPU,
+    contiguous, of one of `dtypes` and with exactly `numel` entries. A host
+    tensor would hand the kernels a host address, a short one would be
+    written past its end and a strided view would be read as dense, so each
+    is rejected here, before any call."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU, got device {t.device}")
+    if t.device.index != ctx.device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{ctx.device}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected " + " or ".join(str(d) for d in dtypes))
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _check_n(n):
+    if not 1 <= int(n) <= 34:
+        raise ValueError(f"n={n} outside [1, 34]")
+
+
+def _cost_types():
+    import torch
+    return (torch.uint8, torch.uint16)
+
+
+def _state_types():
+    import torch
+    return (torch.complex64,)
+
+
+def _cost_code(t) -> int:
+    import torch
+    return QNAE_U8 if t.dtype == torch.uint8 else QNAE_U16
+
+
 def cost_dtype_for(m: int):
     import torch
     return torch.uint8 if m <= 255 else torch.uint16
@@ -303,15 +346,15 @@ def build_cost_diagonal(clauses, n: int, *, out=None, count_solutions: bool = Fa
     if cl.ndim != 2:
         raise ValueError("clauses must be an [m, k] literal array")
     m, k = cl.shape
-    dtype = cost_dtype_for(m)
-    if out is None:
-        out = torch.empty(1 << n, dtype=dtype, device="cuda")
-    code = QNAE_U8 if out.dtype == torch.uint8 else QNAE_U16
+    _check_n(n)
     ctx = ctx or default_context()
+    if out is None:
+        out = torch.empty(1 << n, dtype=cost_dtype_for(m), device=f"cuda:{ctx.device}")
+    ptr = _device_buffer(out, "out", ctx, _cost_types(), 1 << n)
     sols = ctypes.c_uint64(0)
     _check(load_library().qnae_build_cost_diagonal_pred(
         ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1), _pred_code(predicate),
-        ctypes.c_void_p(out.data_ptr()), code,
+        ctypes.c_void_p(ptr), _cost_code(out),
         ctypes.byref(sols) if count_solutions else None, _stream(stream)))
     return (out, int(sols.value)) if count_solutions else out
 
@@ -321,23 +364,20 @@ def qaoa_run(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[C
     """Depth-p QAOA from |+> on the cost diagonal; returns (p_success,
     expected_cost, norm). ``state``, if given, is a complex64 device tensor of
     2^n entries that receives the final state."""
-    import torch
     g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
     b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
     if g.shape != b.shape or g.ndim != 1:
         raise ValueError("gammas and betas must be 1-D of equal length")
-    if cost.numel() != (1 << n):
-        raise ValueError(f"cost has {cost.numel()} entries, expected 2^{n}")
-    if state is not None and (state.dtype != torch.complex64 or state.numel() != (1 << n)):
-        raise ValueError("state must be complex64 with 2^n entries")
-    code = QNAE_U8 if cost.dtype == torch.uint8 else QNAE_U16
+    _check_n(n)
     ctx = ctx or default_context()
+    cptr = _device_buffer(cost, "cost", ctx, _cost_types(), 1 << n)
+    sptr = _device_buffer(state, "state", ctx, _state_types(), 1 << n) if state is not None else None
     res = _CResult()
     p = g.shape[0]
     _check(load_library().qnae_qaoa_run(
-        ctx.handle, ctypes.c_void_p(cost.data_ptr()), code, n, m,
+        ctx.handle, ctypes.c_void_p(cptr), _cost_code(cost), n, m,
         g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
-        ctypes.c_void_p(state.data_ptr()) if state is not None else None,
+        ctypes.c_void_p(sptr) if sptr is not None else None,
         ctypes.byref(res), _stream(stream)))
     return Result(res.p_success, res.expected_cost, res.norm)
 
@@ -361,9 +401,12 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     if len(arrs) != len(ns):
         raise ValueError("clause_sets and ns differ in length")
     halves = _per_item(half, len(arrs), "half")
+    ctx = ctx or default_context()
     if outs is None:
-        outs = [torch.empty(1 << (n - (1 if hf else 0)), dtype=cost_dtype_for(a.shape[0]), device="cuda")
+        outs = [torch.empty(1 << (n - (1 if hf else 0)), dtype=cost_dtype_for(a.shape[0]), device=f"cuda:{ctx.device}")
                 for a, n, hf in zip(arrs, ns, halves)]
+    if len(outs) != len(arrs):
+        raise ValueError("outs and clause_sets differ in length")
     count = len(arrs)
     preds = [predicate] * count if isinstance(predicate, str) else list(predicate)
     if len(preds) != count:
@@ -373,11 +416,12 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     mk = np.array([a.shape for a in arrs], dtype=np.int64).reshape(count, 2)
     hv = np.asarray(halves, dtype=bool)
     nv = np.asarray(ns, dtype=np.int64).reshape(count)
-    numel = np.fromiter((o.numel() for o in outs), dtype=np.int64, count=count)
-    bad = np.nonzero(numel != np.left_shift(np.int64(1), nv - hv))[0]
-    if bad.size:
-        i = int(bad[0])
-        raise ValueError(f"job {i}: cost has {int(numel[i])} entries, expected 2^{int(nv[i] - hv[i])}")
+    if np.any(nv < 1) or np.any(nv > 34):
+        i = int(np.nonzero((nv < 1) | (nv > 34))[0][0])
+        raise ValueError(f"job {i}: n={int(nv[i])} outside [1, 34]")
+    cost_types = _cost_types()
+    ptrs = np.fromiter((_device_buffer(o, f"outs[{i}]", ctx, cost_types, 1 << int(nv[i] - hv[i]))
+                        for i, o in enumerate(outs)), dtype=np.uint64, count=count)
     sols = np.zeros(max(count, 1), dtype=np.uint64)
     jobs = (_CCostJob * count)()
     v = _np_view(jobs, _CCostJob)
@@ -385,14 +429,12 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     v["m"] = mk[:, 0]
     v["n"] = nv
     v["k"] = np.maximum(mk[:, 1], 1)
-    v["cost_dev"] = np.fromiter((o.data_ptr() for o in outs), dtype=np.uint64, count=count)
-    v["cost_dtype"] = np.fromiter((QNAE_U8 if o.dtype == torch.uint8 else QNAE_U16 for o in outs), dtype=np.int32,
-                                  count=count)
+    v["cost_dev"] = ptrs
+    v["cost_dtype"] = np.fromiter((_cost_code(o) for o in outs), dtype=np.int32, count=count)
     v["num_solutions"] = (np.uint64(sols.ctypes.data) + np.uint64(8) * np.arange(count, dtype=np.uint64)
                           if count_solutions else np.uint64(0))
     v["predicate"] = np.fromiter((_pred_code(x) for x in preds), dtype=np.int32, count=count)
     v["half"] = hv
-    ctx = ctx or default_context()
     _check(load_library().qnae_build_cost_diagonal_batched(ctx.handle, jobs, count, _stream(stream)))
     return (outs, [int(x) for x in sols[:count]]) if count_solutions else outs
 
@@ -402,7 +444,6 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     """Batched qaoa_run over many instances; returns a list of Result.
     ``half`` (one flag or a list) solves an instance on the half state as
     qaoa_run_z2 (its cost and state then hold 2^(n-1) entries)."""
-    import torch
     count = len(costs)
     if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
         raise ValueError("argument lists differ in length")
@@ -413,25 +454,25 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     if bad.size:
         raise ValueError(f"instance {int(bad[0])}: gammas and betas must be 1-D of equal length")
     nv = np.asarray(ns, dtype=np.int64).reshape(count)
+    if np.any(nv < 1) or np.any(nv > 34):
+        i = int(np.nonzero((nv < 1) | (nv > 34))[0][0])
+        raise ValueError(f"instance {i}: n={int(nv[i])} outside [1, 34]")
     stored = nv - halves
-    numel = np.fromiter((c.numel() for c in costs), dtype=np.int64, count=count)
-    bad = np.nonzero(numel != np.left_shift(np.int64(1), stored))[0]
-    if bad.size:
-        i = int(bad[0])
-        raise ValueError(f"instance {i}: cost has {int(numel[i])} entries, expected 2^{int(stored[i])}")
+    ctx = ctx or default_context()
+    cost_types = _cost_types()
+    cost_ptr = np.fromiter((_device_buffer(c, f"costs[{i}]", ctx, cost_types, 1 << int(stored[i]))
+                            for i, c in enumerate(costs)), dtype=np.uint64, count=count)
     state_ptr = np.zeros(count, dtype=np.uint64)
     if states is not None:
+        if len(states) != count:
+            raise ValueError("states and costs differ in length")
         for i, st in enumerate(states):
-            if st is None:
-                continue
-            if st.dtype != torch.complex64 or st.numel() != (1 << int(stored[i])):
-                raise ValueError(f"instance {i}: state must be complex64 with 2^{int(stored[i])} entries")
-            state_ptr[i] = st.data_ptr()
+            if st is not None:
+                state_ptr[i] = _device_buffer(st, f"states[{i}]", ctx, _state_types(), 1 << int(stored[i]))
     inst = (_CInstance * count)()
     v = _np_view(inst, _CInstance)
-    v["cost_dev"] = np.fromiter((c.data_ptr() for c in costs), dtype=np.uint64, count=count)
-    v["cost_dtype"] = np.fromiter((QNAE_U8 if c.dtype == torch.uint8 else QNAE_U16 for c in costs), dtype=np.int32,
-                                  count=count)
+    v["cost_dev"] = cost_ptr
+    v["cost_dtype"] = np.fromiter((_cost_code(c) for c in costs), dtype=np.int32, count=count)
     v["n"] = nv
     v["m"] = np.asarray(ms, dtype=np.int64).reshape(count)
     v["p"] = gcnt
@@ -440,7 +481,6 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     v["state_dev"] = state_ptr
     v["half"] = halves
     res = (_CResult * count)()
-    ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))
     return list(map(Result._make, np.frombuffer(res, dtype=np.float64).reshape(count, 3).tolist()))
 
@@ -454,17 +494,15 @@ def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_en
     b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
     if g.shape != b.shape or g.ndim != 1:
         raise ValueError("gammas and betas must be 1-D of equal length")
-    if cost.numel() != (1 << n):
-        raise ValueError(f"cost has {cost.numel()} entries, expected 2^{n}")
-    import torch
-    code = QNAE_U8 if cost.dtype == torch.uint8 else QNAE_U16
+    _check_n(n)
+    ctx = ctx or default_context()
+    cptr = _device_buffer(cost, "cost", ctx, _cost_types(), 1 << n)
     p = g.shape[0]
     dg = np.zeros(p, dtype=np.float64)
     db = np.zeros(p, dtype=np.float64)
     res = _CResult()
-    ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_grad(
-        ctx.handle, ctypes.c_void_p(cost.data_ptr()), code, n, m,
+        ctx.handle, ctypes.c_void_p(cptr), _cost_code(cost), n, m,
         g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
         float(w_psucc), float(w_energy), int(checkpoint_every),
         dg.ctypes.data_as(_F64P) if p else None, db.ctypes.data_as(_F64P) if p else None,
@@ -476,10 +514,10 @@ def qaoa_grad_batched(costs, ns, ms, gammas, betas, *, w_psucc: float = 1.0, w_e
                       checkpoint_every: int = 4, ctx: Optional[Context] = None, stream=None):
     """qaoa_grad for many instances; returns (dgammas list, dbetas list,
     Result list). Instances with n <= 13 share one launch."""
-    import torch
     count = len(costs)
     if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
         raise ValueError("argument lists differ in length")
+    ctx = ctx or default_context()
     jobs = (_CGradJob * count)()
     keep, dgs, dbs = [], [], []
     for i in range(count):
@@ -487,21 +525,21 @@ def qaoa_grad_batched(costs, ns, ms, gammas, betas, *, w_psucc: float = 1.0, w_e
         b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas[i], dtype=np.float64)))
         if g.shape != b.shape or g.ndim != 1:
             raise ValueError(f"instance {i}: gammas and betas must be 1-D of equal length")
-        if costs[i].numel() != (1 << int(ns[i])):
-            raise ValueError(f"instance {i}: cost has {costs[i].numel()} entries, expected 2^{ns[i]}")
+        if not 1 <= int(ns[i]) <= 34:
+            raise ValueError(f"instance {i}: n={int(ns[i])} outside [1, 34]")
+        cptr = _device_buffer(costs[i], f"costs[{i}]", ctx, _cost_types(), 1 << int(ns[i]))
         p = g.shape[0]
         dg, db = np.zeros(p), np.zeros(p)
         keep += [g, b]
         dgs.append(dg)
         dbs.append(db)
-        jobs[i].cost_dev = costs[i].data_ptr()
-        jobs[i].cost_dtype = QNAE_U8 if costs[i].dtype == torch.uint8 else QNAE_U16
+        jobs[i].cost_dev = cptr
+        jobs[i].cost_dtype = _cost_code(costs[i])
         jobs[i].n, jobs[i].m, jobs[i].p = int(ns[i]), int(ms[i]), p
         if p:
             jobs[i].gammas, jobs[i].betas = g.ctypes.data_as(_F64P), b.ctypes.data_as(_F64P)
             jobs[i].dgammas, jobs[i].dbetas = dg.ctypes.data_as(_F64P), db.ctypes.data_as(_F64P)
     res = (_CResult * max(count, 1))()
-    ctx = ctx or default_context()
     _check(load_library().qnae_qaoa_grad_batched(ctx.handle, jobs, count, float(w_psucc), float(w_energy),
                                                  int(checkpoint_every), res, _stream(stream)))
     return dgs, dbs, [Result(r.p_success, r.expected_cost, r.norm) for r in res[:count]]
@@ -516,15 +554,15 @@ def build_cost_diagonal_z2(clauses, n: int, *, out=None, count_solutions: bool =
     if cl.ndim != 2:
         raise ValueError("clauses must be an [m, k] literal array")
     m, k = cl.shape
-    if out is None:
-        out = torch.empty(1 << (n - 1), dtype=cost_dtype_for(m), device="cuda")
-    if out.numel() != (1 << (n - 1)):
-        raise ValueError(f"out has {out.numel()} entries, expected 2^{n - 1}")
-    code = QNAE_U8 if out.dtype == torch.uint8 else QNAE_U16
+    if not 2 <= n <= 34:
+        raise ValueError(f"n={n} outside [2, 34] for a half diagonal")
     ctx = ctx or default_context()
+    if out is None:
+        out = torch.empty(1 << (n - 1), dtype=cost_dtype_for(m), device=f"cuda:{ctx.device}")
+    ptr = _device_buffer(out, "out", ctx, _cost_types(), 1 << (n - 1))
     sols = ctypes.c_uint64(0)
     _check(load_library().qnae_build_cost_diagonal_z2(
-        ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1), ctypes.c_void_p(out.data_ptr()), code,
+        ctx.handle, cl.ctypes.data_as(_I32P) if m else None, m, n, max(k, 1), ctypes.c_void_p(ptr), _cost_code(out),
         ctypes.byref(sols) if count_solutions else None, _stream(stream)))
     return (out, int(sols.value)) if count_solutions else out
 
@@ -534,23 +572,21 @@ def qaoa_run_z2(cost_half, n: int, m: int, gammas, betas, *, state=None, ctx: Op
     """qaoa_run on the half-state representation (NAE instances, n >= 15):
     ``cost_half`` from build_cost_diagonal_z2; ``state``, if given, receives
     the lower half of the final state (2^(n-1) complex64)."""
-    import torch
     g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
     b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
     if g.shape != b.shape or g.ndim != 1:
         raise ValueError("gammas and betas must be 1-D of equal length")
-    if cost_half.numel() != (1 << (n - 1)):
-        raise ValueError(f"cost has {cost_half.numel()} entries, expected 2^{n - 1}")
-    if state is not None and (state.dtype != torch.complex64 or state.numel() != (1 << (n - 1))):
-        raise ValueError("state must be complex64 with 2^(n-1) entries")
-    code = QNAE_U8 if cost_half.dtype == torch.uint8 else QNAE_U16
+    if not 2 <= n <= 34:
+        raise ValueError(f"n={n} outside [2, 34] for a half state")
     ctx = ctx or default_context()
+    cptr = _device_buffer(cost_half, "cost_half", ctx, _cost_types(), 1 << (n - 1))
+    sptr = _device_buffer(state, "state", ctx, _state_types(), 1 << (n - 1)) if state is not None else None
     res = _CResult()
     p = g.shape[0]
     _check(load_library().qnae_qaoa_run_z2(
-        ctx.handle, ctypes.c_void_p(cost_half.data_ptr()), code, n, m,
+        ctx.handle, ctypes.c_void_p(cptr), _cost_code(cost_half), n, m,
         g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
-        ctypes.c_void_p(state.data_ptr()) if state is not None else None, ctypes.byref(res), _stream(stream)))
+        ctypes.c_void_p(sptr) if sptr is not None else None, ctypes.byref(res), _stream(stream)))
     return Result(res.p_success, res.expected_cost, res.norm)
 
 
@@ -559,22 +595,18 @@ def sample(state, n: int, uniforms, *, cost=None, ctx: Optional[Context] = None,
     uniform in [0, 1): the smallest x whose cumulative |psi|^2 mass in index
     order exceeds u times the total. Returns (samples uint64, costs int32 or
     None); costs are C(sample) when the cost diagonal is given."""
-    import torch
-    if state.dtype != torch.complex64 or state.numel() != (1 << n):
-        raise ValueError("state must be complex64 with 2^n entries")
+    if not 1 <= n <= 34:
+        raise ValueError(f"n={n} outside [1, 34]")
+    ctx = ctx or default_context()
+    sptr = _device_buffer(state, "state", ctx, _state_types(), 1 << n)
+    cptr = _device_buffer(cost, "cost", ctx, _cost_types(), 1 << n) if cost is not None else None
     u = np.ascontiguousarray(np.atleast_1d(np.asarray(uniforms, dtype=np.float64)))
     count = u.shape[0]
     out = np.zeros(count, dtype=np.uint64)
     costs = np.zeros(count, dtype=np.int32) if cost is not None else None
-    code = 0
-    if cost is not None:
-        if cost.numel() != (1 << n):
-            raise ValueError(f"cost has {cost.numel()} entries, expected 2^{n}")
-        code = QNAE_U8 if cost.dtype == torch.uint8 else QNAE_U16
-    ctx = ctx or default_context()
     _check(load_library().qnae_sample(
-        ctx.handle, ctypes.c_void_p(state.data_ptr()), n,
-        ctypes.c_void_p(cost.data_ptr()) if cost is not None else None, code,
+        ctx.handle, ctypes.c_void_p(sptr), n,
+        ctypes.c_void_p(cptr) if cptr is not None else None, _cost_code(cost) if cost is not None else 0,
         u.ctypes.data_as(_F64P) if count else None, count,
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if count else None,
         costs.ctypes.data_as(_I32P) if costs is not None and count else None, _stream(stream)))

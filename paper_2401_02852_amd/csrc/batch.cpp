@@ -28,6 +28,7 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
         const qnae_cost_job& j = jobs[i];
         int rc = check_cost_args(j.n, j.m, j.cost_dtype);
         if (!rc && !j.cost_dev) rc = fail(QNAE_EINVAL, "null cost_dev");
+        if (!rc) rc = check_aligned(j.cost_dev, "cost_dev");
         if (!rc) rc = check_literals(j.clauses, j.m, j.n, j.k);
         if (!rc && j.predicate != QNAE_PRED_NAE && j.predicate != QNAE_PRED_SAT)
             rc = fail(QNAE_EINVAL, "predicate=%d is not QNAE_PRED_NAE/QNAE_PRED_SAT", j.predicate);
@@ -127,6 +128,8 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     for (int i = 0; i < count; ++i) {
         const qnae_instance& q = inst[i];
         if (int rc = check_run_args(q.n, q.m, q.cost_dtype, q.cost_dev, q.gammas, q.betas, q.p))
+            return fail(rc, "instance %d: %s", i, std::string(last_error()).c_str());
+        if (int rc = check_aligned(q.state_dev, "state_dev"))
             return fail(rc, "instance %d: %s", i, std::string(last_error()).c_str());
         if (q.half && q.n <= kResidentMaxN)
             return fail(QNAE_EINVAL, "instance %d: half-state solves need n > %d", i, kResidentMaxN);

@@ -162,6 +162,9 @@ int enter(qnae_ctx* ctx);
 // work is large enough to pay for the hand-off (`items` units of it).
 void parallel_for(qnae_ctx* ctx, int count, size_t items, const std::function<void(int)>& fn);
 int check_cost_args(int32_t n, int32_t m, int32_t dtype);
+// QNAE_EINVAL unless ptr (a device buffer the kernels access with 16-byte
+// loads and stores; NULL passes) is 16-byte aligned.
+int check_aligned(const void* ptr, const char* what);
 // Sweep tile shape at (n, cost type): the tuned one if set, else the context defaults.
 qnae_tune tune_for(const qnae_ctx* ctx, int n, int dtype);
 

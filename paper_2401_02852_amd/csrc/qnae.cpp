@@ -92,6 +92,7 @@ int build_cost(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int3
         return fail(QNAE_EINVAL, "predicate=%d is not QNAE_PRED_NAE/QNAE_PRED_SAT", predicate);
     if (int rc = check_cost_args(n, m, cost_dtype)) return rc;
     if (!cost_dev) return fail(QNAE_EINVAL, "null cost_dev");
+    if (int rc = check_aligned(cost_dev, "cost_dev")) return rc;
     if (int rc = check_literals(clauses, m, n, k)) return rc;
     if (int rc = enter(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -153,6 +154,7 @@ int run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int3
         const double* betas, int32_t p, void* state_dev, qnae_result* out, void* stream, bool half) {
     if (int rc = check_run_args(n, m, cost_dtype, cost_dev, gammas, betas, p)) return rc;
     if (!out) return fail(QNAE_EINVAL, "null result pointer");
+    if (int rc = check_aligned(state_dev, "state_dev")) return rc;
     if (half && n <= kResidentMaxN)
         return fail(QNAE_EINVAL, "n=%d: half-state runs need n > %d (smaller n: qnae_qaoa_run)", n, kResidentMaxN);
     if (int rc = enter(ctx)) return rc;

@@ -284,11 +284,16 @@ int check_cost_args(int32_t n, int32_t m, int32_t dtype) {
     return QNAE_OK;
 }
 
+int check_aligned(const void* ptr, const char* what) {
+    if ((uintptr_t)ptr & 15u) return fail(QNAE_EINVAL, "%s is not 16-byte aligned", what);
+    return QNAE_OK;
+}
+
 int check_run_args(int32_t n, int32_t m, int32_t dtype, const void* cost, const double* gammas, const double* betas,
                    int32_t p) {
     if (int rc = check_cost_args(n, m, dtype)) return rc;
     if (!cost) return fail(QNAE_EINVAL, "null cost_dev");
-    if ((uintptr_t)cost & 15u) return fail(QNAE_EINVAL, "cost_dev is not 16-byte aligned");
+    if (int rc = check_aligned(cost, "cost_dev")) return rc;
     if (p < 0 || p > 100000) return fail(QNAE_EINVAL, "p=%d outside [0, 100000]", p);
     if (p > 0 && (!gammas || !betas)) return fail(QNAE_EINVAL, "null angle arrays with p=%d", p);
     for (int l = 0; l < p; ++l)

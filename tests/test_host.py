@@ -95,17 +95,7 @@ class _NullCtx:
     arguments, then rejects the call, so the binding's marshalling runs without
     a GPU."""
     handle = ctypes.c_void_p(None)
-
-
-class _FakeTensor:
-    def __init__(self, numel, dtype):
-        self._n, self.dtype = numel, dtype
-
-    def numel(self):
-        return self._n
-
-    def data_ptr(self):
-        return 0x1000
+    device = 0
 
 
 def _lib_or_skip():
@@ -119,7 +109,7 @@ def test_binding_marshalling_without_gpu():
     import torch
     b = _lib_or_skip()
     cl = inst.instance(8, 3, 10, 0)
-    costs = [_FakeTensor(256, torch.uint8), _FakeTensor(512, torch.uint8)]
+    costs = [_fake_cuda(torch.zeros(256, dtype=torch.uint8)), _fake_cuda(torch.zeros(512, dtype=torch.uint8))]
     with pytest.raises(b.QNAEError, match="null context"):
         b.build_cost_diagonals([cl, cl], [8, 9], outs=costs, count_solutions=True, ctx=_NullCtx(), stream=0)
     with pytest.raises(b.QNAEError, match="null context"):
@@ -213,3 +203,107 @@ def test_server_cancel_and_pool_without_gpu():
     assert b"null server" in lib.qnae_last_error(None)
     assert lib.qnae_server_pool_in_use(None, None) == -1
     assert b._STATUS[-6] == "QNAE_ECANCELED"
+
+
+class _Ctx:
+    """Stands in for a Context: the binding's checks run before any call."""
+    device = 0
+    handle = None
+
+
+def _fake_cuda(t, index=0):
+    """A CPU tensor that reports itself as on cuda:index (the binding's
+    checks read these attributes only; nothing reaches the library)."""
+    import torch
+
+    class FakeCuda(torch.Tensor):
+        @property
+        def is_cuda(self):
+            return True
+
+        @property
+        def device(self):
+            return torch.device("cuda", index)
+
+    return torch.Tensor._make_subclass(FakeCuda, t)
+
+
+def test_binding_rejects_bad_device_buffers():
+    """Every wrapper checks a device buffer before the call: on the GPU, on
+    the context's device, contiguous, of the right dtype and with exactly
+    the entries the call reads or writes."""
+    import torch
+    from paper_2401_02852_amd import _binding as b
+    ctx = _Ctx()
+    n, m = 10, 5
+    g, bb = [0.1, 0.2], [0.3, 0.4]
+    good_cost = _fake_cuda(torch.zeros(1 << n, dtype=torch.uint8))
+    cases = [
+        (torch.zeros(1 << n, dtype=torch.uint8), "on the GPU"),
+        (_fake_cuda(torch.zeros(1 << n, dtype=torch.uint8), index=1), "cuda:1"),
+        (_fake_cuda(torch.zeros(1 << n, dtype=torch.int32)), "dtype"),
+        (_fake_cuda(torch.zeros(1 << n, dtype=torch.float32)), "dtype"),
+        (_fake_cuda(torch.zeros((1 << n) - 1, dtype=torch.uint8)), "entries"),
+        (_fake_cuda(torch.zeros(2 << n, dtype=torch.uint8)[::2]), "contiguous"),
+    ]
+    for cost, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            b.qaoa_run(cost, n, m, g, bb, ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.qaoa_grad(cost, n, m, g, bb, ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.build_cost_diagonal(np.ones((m, 3), dtype=np.int32), n, out=cost, ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.qaoa_run_batched([good_cost, cost], [n, n], [m, m], [g, g], [bb, bb], ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.build_cost_diagonals([np.ones((m, 3), dtype=np.int32)] * 2, [n, n], outs=[good_cost, cost], ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.qaoa_grad_batched([cost], [n], [m], [g], [bb], ctx=ctx)
+    states = [
+        (torch.zeros(1 << n, dtype=torch.complex64), "on the GPU"),
+        (_fake_cuda(torch.zeros(1 << n, dtype=torch.complex128)), "dtype"),
+        (_fake_cuda(torch.zeros(1 << (n - 1), dtype=torch.complex64)), "entries"),
+        (_fake_cuda(torch.zeros(2 << n, dtype=torch.complex64)[1::2]), "contiguous"),
+    ]
+    for st, msg in states:
+        with pytest.raises(ValueError, match=msg):
+            b.qaoa_run(good_cost, n, m, g, bb, state=st, ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.sample(st, n, [0.5], ctx=ctx)
+        with pytest.raises(ValueError, match=msg):
+            b.qaoa_run_batched([good_cost], [n], [m], [g], [bb], states=[st], ctx=ctx)
+    half = _fake_cuda(torch.zeros(1 << (n - 1), dtype=torch.uint8))
+    with pytest.raises(ValueError, match="entries"):
+        b.qaoa_run_z2(good_cost, n, m, g, bb, ctx=ctx)
+    with pytest.raises(ValueError, match="entries"):
+        b.build_cost_diagonal_z2(np.ones((m, 3), dtype=np.int32), n, out=good_cost, ctx=ctx)
+    with pytest.raises(ValueError, match="entries"):
+        b.qaoa_run_z2(half, n, m, g, bb, state=_fake_cuda(torch.zeros(1 << n, dtype=torch.complex64)), ctx=ctx)
+    with pytest.raises(ValueError, match="outside"):
+        b.qaoa_run(good_cost, 40, m, g, bb, ctx=ctx)
+
+
+def test_misaligned_device_buffers_rejected_without_gpu():
+    """The sweeps and the cost kernel access state and cost with 16-byte
+    loads and stores: every entry point rejects a misaligned buffer before
+    it touches the device."""
+    b = _lib_or_skip()
+    lib = b.load_library()
+    res = b._CResult()
+    g = (ctypes.c_double * 1)(0.1)
+    vp = ctypes.c_void_p
+    assert lib.qnae_qaoa_run(None, vp(0x1000), 1, 20, 5, g, g, 1, vp(0x2008), ctypes.byref(res), None) == -1
+    assert b"state_dev is not 16-byte aligned" in lib.qnae_last_error(None)
+    assert lib.qnae_qaoa_run_z2(None, vp(0x1000), 1, 20, 5, g, g, 1, vp(0x2004), ctypes.byref(res), None) == -1
+    assert b"state_dev is not 16-byte aligned" in lib.qnae_last_error(None)
+    assert lib.qnae_qaoa_run(None, vp(0x1001), 1, 20, 5, g, g, 1, None, ctypes.byref(res), None) == -1
+    assert b"cost_dev is not 16-byte aligned" in lib.qnae_last_error(None)
+    cl = (ctypes.c_int32 * 3)(1, 2, 3)
+    assert lib.qnae_build_cost_diagonal(None, cl, 1, 10, 3, vp(0x1008), 1, None, None) == -1
+    assert b"cost_dev is not 16-byte aligned" in lib.qnae_last_error(None)
+    job = b._CCostJob(cl, 1, 10, 3, 0x1004, 1, None, 0, 0)
+    assert lib.qnae_build_cost_diagonal_batched(None, ctypes.byref(job), 1, None) == -1
+    assert b"job 0: cost_dev is not 16-byte aligned" in lib.qnae_last_error(None)
+    inst_ = b._CInstance(0x1000, 1, 20, 5, 1, g, g, 0x3008, 0)
+    assert lib.qnae_qaoa_run_batched(None, ctypes.byref(inst_), 1, ctypes.byref(res), None) == -1
+    assert b"instance 0: state_dev is not 16-byte aligned" in lib.qnae_last_error(None)
