@@ -212,7 +212,55 @@ struct Op {
     int pre_layer, post_layer, lut_layer;  // -1 when unused
 };
 
+// The groups in fixed storage (at most kMaxGroups: n <= 34 with tiles of at
+// least 12 bits needs 4). make_group_specs allocates nothing; make_groups is
+// the same as vectors.
+constexpr int kMaxGroups = 8;
+struct GroupSpec {
+    uint8_t pos[16];  // global bit of each tile bit (TB entries)
+    uint32_t mask;    // tile bits this group mixes
+};
+int make_group_specs(int n, int TB, int cmin, int page, GroupSpec* out);
 std::vector<Group> make_groups(int n, int TB, int cmin, int page);
+
+// The sweeps of a depth-p solve over `ngroups` qubit groups, in order, handed
+// to fn(const Op&) one at a time (allocates nothing). Each layer mixes every
+// group once. The last group of a layer is fused with the next layer's phase
+// and with that layer's mixing of the same group, so every layer after the
+// first costs (number of groups - 1) sweeps. The first sweep starts from the
+// phase table (no load), or with from_state loads a given state and applies
+// phase 0 and the mixing of group 0; the last one only reads the state for
+// the readout unless the final state is kept.
+template <typename F>
+void for_each_op(int ngroups, int p, bool from_state, F&& fn) {
+    using namespace qnae;
+    if (p == 0) {
+        fn(Op{0, SK_P0, -1, -1, 0});
+        return;
+    }
+    fn(from_state ? Op{0, SK_BOUNDARY, -1, 0, 0} : Op{0, SK_FIRST, -1, 0, 0});
+    // groups not yet mixed for layer l, as a bit set (ascending order)
+    uint32_t pending = ((1u << ngroups) - 1u) & ~1u;
+    for (int l = 0;; ++l) {
+        if (pending == 0u) {  // one group: the previous sweep mixed it already
+            if (l == p - 1) {
+                fn(Op{0, SK_FINAL, -1, -1, -1});
+                return;
+            }
+            fn(Op{0, SK_BOUNDARY, -1, l + 1, l + 1});
+            continue;
+        }
+        const int last = 31 - __builtin_clz(pending);  // carries the phase of layer l + 1
+        for (uint32_t m = pending & ~(1u << last); m != 0u; m &= m - 1u)
+            fn(Op{__builtin_ctz(m), SK_MIDDLE, l, -1, -1});
+        if (l == p - 1) {
+            fn(Op{last, SK_FINAL, l, -1, -1});
+            return;
+        }
+        fn(Op{last, SK_BOUNDARY, l, l + 1, l + 1});
+        pending = ((1u << ngroups) - 1u) & ~(1u << last);
+    }
+}
 // from_state: the first sweep loads a given state instead of starting from |+>.
 std::vector<Op> make_plan(int ngroups, int p, bool from_state = false);
 
@@ -243,6 +291,17 @@ std::vector<AdjOp> make_adjoint_plan(int ngroups, int L);
 // Kernel arguments of one op.
 void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost, const float2* luts, double* partials,
                 qnae::SweepArgs* a);
+// The same from the plan's scalars and arrays (forms: p entries,
+// flips_before: p + 1) and the op's group (TB bit positions and mix mask).
+struct PlanRef {
+    int n, p, TB, lut_len;
+    bool keep, half;
+    const qnae::MixForm* forms;
+    const int* flips_before;
+    std::complex<double> final_scale;
+};
+void sweep_args_for(const PlanRef& P, const int* pos, uint32_t mask, const Op& op, float2* psi, const void* cost,
+                    const float2* luts, double* partials, qnae::SweepArgs* a);
 // Algorithmic bytes of one op and its profiling kind.
 double op_bytes(const SweepPlan& P, const Op& op);
 int op_profile_kind(const Op& op);

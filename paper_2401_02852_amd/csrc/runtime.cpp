@@ -365,106 +365,67 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
 // n = 30 (13-bit tiles): a tile that mixes index bits 14..17 together with
 // page bits streams slowest, least so beside bits 18..21; this arrangement
 // ran 3% faster than dealing the page bits out round-robin.
-std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
-    std::vector<Group> g;
-    Group A;
+int make_group_specs(int n, int TB, int cmin, int page, GroupSpec* out) {
+    GroupSpec& A = out[0];
+    A.mask = (1u << TB) - 1u;
     if (n <= TB) {
-        for (int i = 0; i < TB; ++i) A.pos.push_back(i);
-        A.mask = (1u << TB) - 1u;
-        g.push_back(A);
-        return g;
+        for (int i = 0; i < TB; ++i) A.pos[i] = (uint8_t)i;
+        return 1;
     }
     const int rest = n - TB;
     const int h = (rest + (TB - cmin) - 1) / (TB - cmin);
-    std::vector<int> P;
-    for (int b = std::max(page, TB); b < n; ++b) P.push_back(b);
-    const int target = ((int)P.size() + h) / (h + 1);
-    const int a = std::min(std::min(target, TB - cmin), (int)P.size());
+    // page bits: the consecutive run [max(page, TB), n); group A takes its top a
+    const int first_page = std::max(page, TB);
+    const int npage = std::max(0, n - first_page);
+    const int target = (npage + h) / (h + 1);
+    const int a = std::min(std::min(target, TB - cmin), npage);
     const int cA = TB - a;
-    std::vector<int> apage(P.end() - a, P.end());
-    for (int i = 0; i < cA; ++i) A.pos.push_back(i);
-    for (int b : apage) A.pos.push_back(b);
-    A.mask = (1u << TB) - 1u;
-    g.push_back(A);
-    // bits left for the other groups, page bits first
-    std::vector<int> RP, RN;
-    for (int b = cA; b < n; ++b) {
-        if (std::find(apage.begin(), apage.end(), b) != apage.end()) continue;
-        (b >= page ? RP : RN).push_back(b);
-    }
-    const int R = (int)(RP.size() + RN.size());
-    std::vector<std::vector<int>> piece(h);
-    std::vector<int> size(h);
-    for (int i = 0; i < h; ++i) size[i] = R / h + (i < R % h ? 1 : 0);
-    for (int i = 0, q = (int)RP.size(); i < h; ++i) {  // consecutive page runs, evenly, top run first
-        const int c = (int)RP.size() / h + (i < (int)RP.size() % h ? 1 : 0);
+    for (int i = 0; i < cA; ++i) A.pos[i] = (uint8_t)i;
+    for (int i = 0; i < a; ++i) A.pos[cA + i] = (uint8_t)(n - a + i);
+    // bits left for the other groups, page bits (RP) and the others (RN), ascending
+    int RP[64], RN[64], nrp = 0, nrn = 0;
+    for (int b = cA; b < n - a; ++b) (b >= page ? RP[nrp++] : RN[nrn++]) = b;
+    const int R = nrp + nrn;
+    int nx = 0;
+    for (int i = 0, q = nrp; i < h; ++i) {
+        // consecutive page runs, evenly, top run first; then the other bits in order
+        const int c = nrp / h + (i < nrp % h ? 1 : 0);
+        const int size = R / h + (i < R % h ? 1 : 0);
         q -= c;
-        for (int k = 0; k < c; ++k) piece[i].push_back(RP[q + k]);
-    }
-    size_t nx = 0;
-    for (int i = 0; i < h; ++i)
-        while ((int)piece[i].size() < size[i]) piece[i].push_back(RN[nx++]);
-    for (int i = 0; i < h; ++i) {
-        Group B;
-        std::vector<int> bits = piece[i];
+        uint64_t bits = 0;
+        for (int k = 0; k < c; ++k) bits |= 1ull << RP[q + k];
+        for (int k = c; k < size; ++k) bits |= 1ull << RN[nx++];
         // fill up to TB - cmin bits with unmixed bits just above the low run
-        std::vector<int> fill;
-        for (int b = cmin; (int)(bits.size() + fill.size()) < TB - cmin; ++b)
-            if (std::find(bits.begin(), bits.end(), b) == bits.end()) fill.push_back(b);
-        std::vector<int> all = fill;
-        all.insert(all.end(), bits.begin(), bits.end());
-        std::sort(all.begin(), all.end());
-        for (int b = 0; b < cmin; ++b) B.pos.push_back(b);
+        uint64_t all = bits;
+        for (int b = cmin; __builtin_popcountll(all) < TB - cmin; ++b) all |= 1ull << b;
+        GroupSpec& B = out[1 + i];
         B.mask = 0u;
-        for (int b : all) {
-            if (std::find(bits.begin(), bits.end(), b) != bits.end()) B.mask |= 1u << B.pos.size();
-            B.pos.push_back(b);
+        int np = 0;
+        for (int b = 0; b < cmin; ++b) B.pos[np++] = (uint8_t)b;
+        for (uint64_t m = all; m != 0ull; m &= m - 1ull) {
+            const int b = __builtin_ctzll(m);
+            if ((bits >> b) & 1ull) B.mask |= 1u << np;
+            B.pos[np++] = (uint8_t)b;
         }
-        g.push_back(B);
+    }
+    return 1 + h;
+}
+
+std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
+    GroupSpec spec[kMaxGroups];
+    const int count = make_group_specs(n, TB, cmin, page, spec);
+    std::vector<Group> g(count);
+    for (int i = 0; i < count; ++i) {
+        g[i].pos.assign(spec[i].pos, spec[i].pos + TB);
+        g[i].mask = spec[i].mask;
     }
     return g;
 }
 
-// Each layer mixes every group once. The last group of a layer is fused with
-// the next layer's phase and with that layer's mixing of the same group, so
-// every layer after the first costs (number of groups - 1) sweeps. The first
-// sweep starts from the phase table (no load) and the last one only reads the
-// state for the readout unless the final state is kept.
 std::vector<Op> make_plan(int ngroups, int p, bool from_state) {
-    using namespace qnae;
     std::vector<Op> ops;
-    if (p == 0) {
-        ops.push_back({0, SK_P0, -1, -1, 0});
-        return ops;
-    }
-    // from a given state: load, phase 0, mix group 0 (a boundary sweep with
-    // nothing to mix before the phase)
-    ops.push_back(from_state ? Op{0, SK_BOUNDARY, -1, 0, 0} : Op{0, SK_FIRST, -1, 0, 0});
-    std::vector<int> pending;  // groups not yet mixed for layer l
-    for (int g = 1; g < ngroups; ++g) pending.push_back(g);
-    for (int l = 0;; ++l) {
-        if (pending.empty()) {  // one group: the previous sweep mixed it already
-            if (l == p - 1) {
-                ops.push_back({0, SK_FINAL, -1, -1, -1});
-                return ops;
-            }
-            ops.push_back({0, SK_BOUNDARY, -1, l + 1, l + 1});
-            continue;
-        }
-        int last = pending.back();
-        for (int g : pending)
-            if (g != 0) last = g;
-        for (int g : pending)
-            if (g != last) ops.push_back({g, SK_MIDDLE, l, -1, -1});
-        if (l == p - 1) {
-            ops.push_back({last, SK_FINAL, l, -1, -1});
-            return ops;
-        }
-        ops.push_back({last, SK_BOUNDARY, l, l + 1, l + 1});
-        pending.clear();
-        for (int g = 0; g < ngroups; ++g)
-            if (g != last) pending.push_back(g);
-    }
+    for_each_op(ngroups, p, from_state, [&](const Op& op) { ops.push_back(op); });
+    return ops;
 }
 
 std::vector<AdjOp> make_adjoint_plan(int ngroups, int L) {
@@ -510,6 +471,12 @@ void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin,
 void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost, const float2* luts, double* partials,
                 qnae::SweepArgs* a) {
     const Group& g = P.groups[op.group];
+    const PlanRef ref{P.n, P.p, P.TB, P.lut_len, P.keep, P.half, P.forms.data(), P.flips_before.data(), P.final_scale};
+    sweep_args_for(ref, g.pos.data(), g.mask, op, psi, cost, luts, partials, a);
+}
+
+void sweep_args_for(const PlanRef& P, const int* pos, uint32_t mask, const Op& op, float2* psi, const void* cost,
+                    const float2* luts, double* partials, qnae::SweepArgs* a) {
     std::memset(a, 0, sizeof *a);
     a->psi = psi;
     a->psi_in = psi;
@@ -520,13 +487,13 @@ void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost,
     a->nw = P.n - P.TB;
     a->tile_bits = 0;
     for (int i = 0; i < P.TB; ++i) {
-        a->pos[i] = (uint8_t)g.pos[i];
-        a->tile_bits |= 1ull << g.pos[i];
+        a->pos[i] = (uint8_t)pos[i];
+        a->tile_bits |= 1ull << pos[i];
     }
     a->wmask = ((1ull << P.n) - 1ull) & ~a->tile_bits;
     a->lut_len = P.lut_len;
-    a->pre_mask = op.pre_layer >= 0 ? g.mask : 0u;
-    a->post_mask = op.post_layer >= 0 ? g.mask : 0u;
+    a->pre_mask = op.pre_layer >= 0 ? mask : 0u;
+    a->post_mask = op.post_layer >= 0 ? mask : 0u;
     a->pre_t = op.pre_layer >= 0 ? P.forms[op.pre_layer].t : 0.f;
     a->post_t = op.post_layer >= 0 ? P.forms[op.post_layer].t : 0.f;
     a->store_scale = make_float2((float)P.final_scale.real(), (float)P.final_scale.imag());
@@ -546,8 +513,8 @@ void sweep_args(const SweepPlan& P, const Op& op, float2* psi, const void* cost,
         const uint64_t stored = (1ull << (P.n - 1)) - 1ull;
         uint64_t unit = 0;
         for (int i = 0; i < P.TB; ++i) {
-            if (g.pos[i] == P.n - 1) a->vbit = i;
-            else unit |= 1ull << g.pos[i];
+            if (pos[i] == P.n - 1) a->vbit = i;
+            else unit |= 1ull << pos[i];
         }
         uint64_t wm = stored & ~unit;
         if (a->vbit >= 0) wm &= ~(1ull << (63 - __builtin_clzll(wm)));

@@ -11,6 +11,7 @@
 #include <string>
 #include <new>
 #include <stdexcept>
+#include <algorithm>
 #include <vector>
 
 #include "../../paper_2401_02852_amd/csrc/host.h"
@@ -217,7 +218,134 @@ static void check_host_exception() {
     CHECK(rc == QNAE_ENOMEM && std::string(last_error()).find("unknown") != std::string::npos);
 }
 
+// The planner as first written with growable vectors (kept here as the
+// reference for the fixed-storage planner the library uses, which must give
+// the same groups and the same sweeps).
+static std::vector<Group> vector_make_groups(int n, int TB, int cmin, int page) {
+    std::vector<Group> g;
+    Group A;
+    if (n <= TB) {
+        for (int i = 0; i < TB; ++i) A.pos.push_back(i);
+        A.mask = (1u << TB) - 1u;
+        g.push_back(A);
+        return g;
+    }
+    const int rest = n - TB;
+    const int h = (rest + (TB - cmin) - 1) / (TB - cmin);
+    std::vector<int> P;
+    for (int b = std::max(page, TB); b < n; ++b) P.push_back(b);
+    const int target = ((int)P.size() + h) / (h + 1);
+    const int a = std::min(std::min(target, TB - cmin), (int)P.size());
+    const int cA = TB - a;
+    std::vector<int> apage(P.end() - a, P.end());
+    for (int i = 0; i < cA; ++i) A.pos.push_back(i);
+    for (int b : apage) A.pos.push_back(b);
+    A.mask = (1u << TB) - 1u;
+    g.push_back(A);
+    // bits left for the other groups, page bits first
+    std::vector<int> RP, RN;
+    for (int b = cA; b < n; ++b) {
+        if (std::find(apage.begin(), apage.end(), b) != apage.end()) continue;
+        (b >= page ? RP : RN).push_back(b);
+    }
+    const int R = (int)(RP.size() + RN.size());
+    std::vector<std::vector<int>> piece(h);
+    std::vector<int> size(h);
+    for (int i = 0; i < h; ++i) size[i] = R / h + (i < R % h ? 1 : 0);
+    for (int i = 0, q = (int)RP.size(); i < h; ++i) {  // consecutive page runs, evenly, top run first
+        const int c = (int)RP.size() / h + (i < (int)RP.size() % h ? 1 : 0);
+        q -= c;
+        for (int k = 0; k < c; ++k) piece[i].push_back(RP[q + k]);
+    }
+    size_t nx = 0;
+    for (int i = 0; i < h; ++i)
+        while ((int)piece[i].size() < size[i]) piece[i].push_back(RN[nx++]);
+    for (int i = 0; i < h; ++i) {
+        Group B;
+        std::vector<int> bits = piece[i];
+        // fill up to TB - cmin bits with unmixed bits just above the low run
+        std::vector<int> fill;
+        for (int b = cmin; (int)(bits.size() + fill.size()) < TB - cmin; ++b)
+            if (std::find(bits.begin(), bits.end(), b) == bits.end()) fill.push_back(b);
+        std::vector<int> all = fill;
+        all.insert(all.end(), bits.begin(), bits.end());
+        std::sort(all.begin(), all.end());
+        for (int b = 0; b < cmin; ++b) B.pos.push_back(b);
+        B.mask = 0u;
+        for (int b : all) {
+            if (std::find(bits.begin(), bits.end(), b) != bits.end()) B.mask |= 1u << B.pos.size();
+            B.pos.push_back(b);
+        }
+        g.push_back(B);
+    }
+    return g;
+}
+
+static std::vector<Op> vector_make_plan(int ngroups, int p, bool from_state) {
+    using namespace qnae;
+    std::vector<Op> ops;
+    if (p == 0) {
+        ops.push_back({0, SK_P0, -1, -1, 0});
+        return ops;
+    }
+    // from a given state: load, phase 0, mix group 0 (a boundary sweep with
+    // nothing to mix before the phase)
+    ops.push_back(from_state ? Op{0, SK_BOUNDARY, -1, 0, 0} : Op{0, SK_FIRST, -1, 0, 0});
+    std::vector<int> pending;  // groups not yet mixed for layer l
+    for (int g = 1; g < ngroups; ++g) pending.push_back(g);
+    for (int l = 0;; ++l) {
+        if (pending.empty()) {  // one group: the previous sweep mixed it already
+            if (l == p - 1) {
+                ops.push_back({0, SK_FINAL, -1, -1, -1});
+                return ops;
+            }
+            ops.push_back({0, SK_BOUNDARY, -1, l + 1, l + 1});
+            continue;
+        }
+        int last = pending.back();
+        for (int g : pending)
+            if (g != 0) last = g;
+        for (int g : pending)
+            if (g != last) ops.push_back({g, SK_MIDDLE, l, -1, -1});
+        if (l == p - 1) {
+            ops.push_back({last, SK_FINAL, l, -1, -1});
+            return ops;
+        }
+        ops.push_back({last, SK_BOUNDARY, l, l + 1, l + 1});
+        pending.clear();
+        for (int g = 0; g < ngroups; ++g)
+            if (g != last) pending.push_back(g);
+    }
+}
+
+static void check_fixed_planner_matches_vectors() {
+    for (int TB = 12; TB <= 14; ++TB)
+        for (int cmin = 4; cmin <= 6; ++cmin)
+            for (int page : {4, 13, 18, 22, 64})
+                for (int n = TB + 1; n <= 34; ++n) {
+                    const std::vector<Group> want = vector_make_groups(n, TB, cmin, page);
+                    GroupSpec spec[kMaxGroups];
+                    const int count = make_group_specs(n, TB, cmin, page, spec);
+                    CHECK(count == (int)want.size() && count <= kMaxGroups);
+                    for (int i = 0; i < count; ++i) {
+                        CHECK(spec[i].mask == want[i].mask);
+                        for (int j = 0; j < TB; ++j) CHECK(spec[i].pos[j] == want[i].pos[j]);
+                    }
+                    for (int p : {0, 1, 2, 3, 7})
+                        for (bool from_state : {false, true}) {
+                            const std::vector<Op> a = vector_make_plan(count, p, from_state);
+                            const std::vector<Op> b = make_plan(count, p, from_state);
+                            CHECK(a.size() == b.size());
+                            for (size_t q = 0; q < a.size(); ++q)
+                                CHECK(a[q].group == b[q].group && a[q].kind == b[q].kind &&
+                                      a[q].pre_layer == b[q].pre_layer && a[q].post_layer == b[q].post_layer &&
+                                      a[q].lut_layer == b[q].lut_layer);
+                        }
+                }
+}
+
 int main() {
+    check_fixed_planner_matches_vectors();
     check_groups_and_plans();
     check_clause_records();
     check_phase_rows();
