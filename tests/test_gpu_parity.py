@@ -338,3 +338,42 @@ def test_default_context_per_thread(q):
     assert ctxs[0] is not ctxs[1] and a not in ctxs
     for g_, a_ in zip(got, alone):
         assert g_ == a_
+
+
+@pytest.mark.parametrize("case", ["gamma0_tan", "gamma0_cot", "gamma0_mixed", "beta0", "beta_half_pi"])
+def test_random_assignment_special_cases_n30(q, golden, case):
+    """App. B at full size: with every gamma = 0 the state stays |+> up to a
+    global phase (X_j |+> = |+>), and with every beta = 0 (or beta = pi/2,
+    where the mixer is a phase times the global flip, under which the NAE
+    cost is symmetric) only phases act. Either way |psi(x)|^2 = 2^-n, so
+    p_succ = #solutions / 2^n and E[C] = m 2^(1-k). The gamma = 0 cases run
+    the tan form (|tan beta| <= 1), the cot form (|tan beta| > 1, X tracked
+    as a relabelling with complemented cost reads) and both mixed."""
+    import torch
+    rec = golden["nae3_n30_p10"]
+    n, k, m = rec["n"], rec["k"], rec["m"]
+    free, _ = torch.cuda.mem_get_info()
+    if free < (10 << 30):
+        pytest.skip("not enough device memory")
+    rng = np.random.default_rng(7)
+    p = 6
+    if case == "gamma0_tan":
+        g, b = np.zeros(p), rng.uniform(-0.7, 0.7, p)
+    elif case == "gamma0_cot":
+        g, b = np.zeros(p), rng.uniform(0.9, 2.2, p) * rng.choice([-1, 1], p)
+    elif case == "gamma0_mixed":
+        g, b = np.zeros(p), np.array([0.3, 1.2, -0.9, 2.0, -0.2, 1.5])
+    elif case == "beta0":
+        g, b = rng.uniform(-3, 3, p), np.zeros(p)
+    else:
+        g, b = rng.uniform(-3, 3, p), np.array([np.pi / 2, 0.0, -np.pi / 2, np.pi / 2, 0.0, np.pi / 2])
+    cl = inst.instance(n, k, m, rec["seed"])
+    c = gpu_cost(q, cl, n)
+    r = q.qaoa_run(c, n, m, g, b)
+    want_p = rec["num_solutions"] / 2 ** n
+    want_e = m * 2.0 ** (1 - k)
+    assert abs(r.p_success - want_p) <= 1e-5 * want_p, (r, want_p)
+    assert abs(r.expected_cost - want_e) <= E_REL * want_e, (r, want_e)
+    assert abs(r.norm - 1.0) <= 1e-5
+    del c
+    torch.cuda.empty_cache()

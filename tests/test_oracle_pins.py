@@ -7,6 +7,7 @@ force written independently below.
 """
 import itertools
 import math
+import os
 
 import numpy as np
 import pytest
@@ -537,3 +538,37 @@ def test_oracle_threads_do_not_change_results():
     rn = oracle.qaoa(c, 12, g, b)
     assert np.array_equal(s1, sn)
     assert np.allclose(r1, rn, rtol=1e-13, atol=1e-16)
+
+
+def test_stored_cost_digests():
+    """The stored full-size diagonal digests against what the paper fixes:
+    each clause of k distinct variables is violated on 2^(n+1-k) states
+    under NAE (App. B) and on 2^(n-k) under k-SAT (Section 2.2), so the
+    stored sums are m times that; the zero counts equal the stored
+    workloads' solution counts and are even under NAE (global flip,
+    Section 2.2); and the n = 24 digests equal a hash of the whole diagonal
+    from the oracle's other entry point (the full-array routine)."""
+    import hashlib
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "tests", "golden", "cost_digests.json")) as f:
+        dig = json.load(f)
+    with open(os.path.join(root, "tests", "golden", "workloads.json")) as f:
+        work = json.load(f)
+    assert set(dig) == set(inst.DIGEST_WORKLOADS)
+    for name, rec in dig.items():
+        n, k, m = rec["n"], rec["k"], rec["m"]
+        assert (n, k, rec["r"], rec["predicate"]) == inst.DIGEST_WORKLOADS[name]
+        assert m == inst.clause_count(n, rec["r"])
+        assert rec["dtype"] == ("uint8" if m <= 255 else "uint16")
+        per_clause = 2 ** (n + 1 - k) if rec["predicate"] == "nae" else 2 ** (n - k)
+        assert rec["sum"] == m * per_clause, name
+        assert len(rec["chunks"]) == 2 ** (n - rec["chunk_log2"])
+        if rec["predicate"] == "nae":
+            assert rec["num_zeros"] % 2 == 0
+        if name in work:
+            assert rec["seed"] == work[name]["seed"] and rec["num_zeros"] == work[name]["num_solutions"]
+    rec = dig["nae3_n24_p10"]
+    c = oracle.cost(inst.instance(24, 3, rec["m"], rec["seed"]), 24).astype(np.uint8).tobytes()
+    assert hashlib.sha256(c).hexdigest() == rec["sha256"]
+    assert hashlib.sha256(c).hexdigest()[:16] == rec["chunks"][0]

@@ -127,3 +127,17 @@ def serving_workload(count: int = 2000, seed: int = 0, rate: float = 200.0,
         out.append({"arrival_s": float(t[i]), "n": n, "k": k, "m": m, "p": p,
                     "clauses": cl, "gammas": g, "betas": b})
     return out
+
+
+# Cost diagonals compared in full against the oracle, by chunk digests
+# (``oracle/make_digests.py`` writes ``tests/golden/cost_digests.json``):
+# name: (n, k, r, predicate). Names that are single workloads above use that
+# workload's satisfiable seed; the others use seed 0.
+DIGEST_WORKLOADS = {
+    "nae3_n24_p10": (24, 3, 2.1, "nae"),
+    "nae3_n28_p10": (28, 3, 2.1, "nae"),
+    "nae3_n30_p10": (30, 3, 2.1, "nae"),
+    "sat3_n30": (30, 3, 4.2, "sat"),        # k-SAT predicate, m = 126
+    "nae5_n30_u16": (30, 5, 9.0, "nae"),    # m = 270 > 255: uint16 diagonal
+    "nae3_n33": (33, 3, 2.1, "nae"),        # 64-bit basis indices (n > 32), 8 GiB
+}
