@@ -66,8 +66,8 @@ enum {
  * host staging and a small host thread pool. Every call on a context uses
  * that scratch, so calls on one context must not overlap: use one context per
  * calling thread. A server made from a context keeps its own pool, stream and
- * buffers and reads only the context's tile settings. *out is set to NULL on
- * failure. */
+ * buffers and copies the context's tile shapes (tuned and default) when it is
+ * made. *out is set to NULL on failure. */
 int qnae_create(qnae_ctx **out, int device);
 
 /* Release the context and everything it owns. Waits for its work. NULL is a
@@ -197,8 +197,12 @@ typedef struct {
 /* Runs `count` independent depth-p QAOA solves (Section 3.3) together and
  * writes out[i] for inst[i]: instances with n <= 14 each run whole in one
  * workgroup, larger ones advance one sweep per launch side by side with the
- * others (tiles of all instances in one grid). Results equal qnae_qaoa_run on
- * each instance alone up to FP32 rounding order. States the caller does not
+ * others (tiles of all instances in one grid), each with the tile shape in use
+ * for its n and cost type (qnae_autotune, qnae_autotune_batched,
+ * qnae_set_tune). Results equal qnae_qaoa_run on each instance alone up to
+ * FP32 rounding order. A batch of the same shape as one of the last 8 (the
+ * same sizes, cost types, tile shapes and buffers) reuses its plan and
+ * replays its captured launch sequence: only the angles' tables are rebuilt. States the caller does not
  * provide live in context scratch (sum of 2^n * 8 bytes). Synchronous.
  * Errors: QNAE_EINVAL (names the offending instance), QNAE_ENOMEM,
  * QNAE_EHIP. */
@@ -351,6 +355,20 @@ typedef struct {
  * all zeros. Synchronous. Errors: QNAE_EINVAL (n outside [1, QNAE_MAX_N], bad
  * cost_dtype, reps outside [1, 1000], null out), QNAE_ENOMEM, QNAE_EHIP. */
 int qnae_autotune(qnae_ctx *ctx, int32_t n, int32_t cost_dtype, int32_t reps, qnae_tune *out, void *stream);
+
+/* The tile shape of the batched path, tuned on the batch itself: runs
+ * qnae_qaoa_run_batched on `inst` under every candidate shape of
+ * qnae_autotune, applied to all of its instances with n > 14 (one warm-up
+ * run, then `reps` timed runs, wall clock, host preparation included), and
+ * keeps the fastest for every (n, cost type) among those instances on this
+ * context: later batched runs, single runs and servers made afterwards use
+ * it. *out receives it, with ms_per_layer the time per instance-layer of the
+ * whole batch (all zeros when no instance has n > 14). Cost diagonals are
+ * only read; state buffers the instances name hold a final state of one of
+ * the runs. Synchronous. Errors: those of qnae_qaoa_run_batched,
+ * QNAE_EINVAL for reps outside [1, 100] or a null out. */
+int qnae_autotune_batched(qnae_ctx *ctx, const qnae_instance *inst, int32_t count, int32_t reps, qnae_tune *out,
+                          void *stream);
 
 /* Sets (tune != NULL) or clears (NULL) the shape used at n and cost_dtype,
  * e.g. from a saved autotune result. qnae_get_tune writes the shape in use:

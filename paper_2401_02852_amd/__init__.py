@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     Context,
     Result,
     Server,
+    autotune_batched,
     build_cost_diagonal,
     build_cost_diagonal_z2,
     build_cost_diagonals,

@@ -151,6 +151,7 @@ def load_library():
         tp = ctypes.POINTER(_CTune)
         lib.qnae_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, tp, vp]
         lib.qnae_set_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, tp]
+        lib.qnae_autotune_batched.argtypes = [vp, ctypes.POINTER(_CInstance), ctypes.c_int32, ctypes.c_int32, tp, vp]
         lib.qnae_get_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, tp]
         lib.qnae_server_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(vp)]
         lib.qnae_server_submit.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
@@ -168,6 +169,7 @@ def load_library():
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
                    lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample, lib.qnae_build_cost_diagonal_z2,
                    lib.qnae_qaoa_run_z2, lib.qnae_qaoa_grad_batched, lib.qnae_server_cancel,
+                   lib.qnae_autotune_batched,
                    lib.qnae_server_pool_in_use):
             fn.restype = ctypes.c_int
         _lib = lib
@@ -304,6 +306,35 @@ def _device_buffer(t, name: str, ctx: "Context", dtypes, numel: int) -> int:
     return t.data_ptr()
 
 
+def _device_buffers(ts, name: str, ctx: "Context", dtypes, numels):
+    """_device_buffer over a list with one pass per property: (addresses,
+    cost type codes) as arrays. The first failing entry is reported by
+    _device_buffer itself."""
+    import torch
+    count = len(ts)
+    if count == 0:
+        return np.zeros(0, dtype=np.uint64), np.zeros(0, dtype=np.int32)
+    try:
+        dev = np.fromiter((t.get_device() for t in ts), dtype=np.int64, count=count)
+        typ = np.fromiter((_DTYPE_CODES.get(t.dtype, 0) for t in ts), dtype=np.int32, count=count)
+        num = np.fromiter((t.numel() for t in ts), dtype=np.int64, count=count)
+        con = np.fromiter((t.is_contiguous() for t in ts), dtype=bool, count=count)
+        ptr = np.fromiter((t.data_ptr() for t in ts), dtype=np.uint64, count=count)
+    except AttributeError:
+        dev = None
+    allowed = np.array([_DTYPE_CODES[d] for d in dtypes], dtype=np.int32)
+    if dev is None or not isinstance(ts[0], torch.Tensor):
+        bad = range(count)
+    else:
+        bad = np.nonzero((dev != ctx.device) | ~np.isin(typ, allowed) | (num != np.asarray(numels)) | ~con)[0]
+    for i in bad:
+        _device_buffer(ts[i], f"{name}[{i}]", ctx, dtypes, int(np.broadcast_to(numels, (count,))[i]))
+    return ptr, typ
+
+
+_DTYPE_CODES = {}
+
+
 def _check_n(n):
     if not 1 <= int(n) <= 34:
         raise ValueError(f"n={n} outside [1, 34]")
@@ -311,11 +342,14 @@ def _check_n(n):
 
 def _cost_types():
     import torch
+    if not _DTYPE_CODES:
+        _DTYPE_CODES.update({torch.uint8: QNAE_U8, torch.uint16: QNAE_U16, torch.complex64: 3})
     return (torch.uint8, torch.uint16)
 
 
 def _state_types():
     import torch
+    _cost_types()
     return (torch.complex64,)
 
 
@@ -419,9 +453,7 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     if np.any(nv < 1) or np.any(nv > 34):
         i = int(np.nonzero((nv < 1) | (nv > 34))[0][0])
         raise ValueError(f"job {i}: n={int(nv[i])} outside [1, 34]")
-    cost_types = _cost_types()
-    ptrs = np.fromiter((_device_buffer(o, f"outs[{i}]", ctx, cost_types, 1 << int(nv[i] - hv[i]))
-                        for i, o in enumerate(outs)), dtype=np.uint64, count=count)
+    ptrs, codes = _device_buffers(outs, "outs", ctx, _cost_types(), np.left_shift(np.int64(1), nv - hv))
     sols = np.zeros(max(count, 1), dtype=np.uint64)
     jobs = (_CCostJob * count)()
     v = _np_view(jobs, _CCostJob)
@@ -430,7 +462,7 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     v["n"] = nv
     v["k"] = np.maximum(mk[:, 1], 1)
     v["cost_dev"] = ptrs
-    v["cost_dtype"] = np.fromiter((_cost_code(o) for o in outs), dtype=np.int32, count=count)
+    v["cost_dtype"] = codes
     v["num_solutions"] = (np.uint64(sols.ctypes.data) + np.uint64(8) * np.arange(count, dtype=np.uint64)
                           if count_solutions else np.uint64(0))
     v["predicate"] = np.fromiter((_pred_code(x) for x in preds), dtype=np.int32, count=count)
@@ -439,11 +471,9 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     return (outs, [int(x) for x in sols[:count]]) if count_solutions else outs
 
 
-def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, ctx: Optional[Context] = None,
-                     stream=None):
-    """Batched qaoa_run over many instances; returns a list of Result.
-    ``half`` (one flag or a list) solves an instance on the half state as
-    qaoa_run_z2 (its cost and state then hold 2^(n-1) entries)."""
+def _instances(costs, ns, ms, gammas, betas, states, half, ctx):
+    """The qnae_instance array of a batch (and the angle arrays it points
+    into, which must outlive the call)."""
     count = len(costs)
     if not (len(ns) == len(ms) == len(gammas) == len(betas) == count):
         raise ValueError("argument lists differ in length")
@@ -458,10 +488,7 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
         i = int(np.nonzero((nv < 1) | (nv > 34))[0][0])
         raise ValueError(f"instance {i}: n={int(nv[i])} outside [1, 34]")
     stored = nv - halves
-    ctx = ctx or default_context()
-    cost_types = _cost_types()
-    cost_ptr = np.fromiter((_device_buffer(c, f"costs[{i}]", ctx, cost_types, 1 << int(stored[i]))
-                            for i, c in enumerate(costs)), dtype=np.uint64, count=count)
+    cost_ptr, codes = _device_buffers(costs, "costs", ctx, _cost_types(), np.left_shift(np.int64(1), stored))
     state_ptr = np.zeros(count, dtype=np.uint64)
     if states is not None:
         if len(states) != count:
@@ -472,7 +499,7 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     inst = (_CInstance * count)()
     v = _np_view(inst, _CInstance)
     v["cost_dev"] = cost_ptr
-    v["cost_dtype"] = np.fromiter((_cost_code(c) for c in costs), dtype=np.int32, count=count)
+    v["cost_dtype"] = codes
     v["n"] = nv
     v["m"] = np.asarray(ms, dtype=np.int64).reshape(count)
     v["p"] = gcnt
@@ -480,9 +507,34 @@ def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, c
     v["betas"] = np.where(gcnt > 0, np.uint64(B.ctypes.data) + np.uint64(8) * boff, np.uint64(0))
     v["state_dev"] = state_ptr
     v["half"] = halves
+    return inst, (G, B)
+
+
+def qaoa_run_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, ctx: Optional[Context] = None,
+                     stream=None):
+    """Batched qaoa_run over many instances; returns a list of Result.
+    ``half`` (one flag or a list) solves an instance on the half state as
+    qaoa_run_z2 (its cost and state then hold 2^(n-1) entries)."""
+    count = len(costs)
+    ctx = ctx or default_context()
+    inst, _keep = _instances(costs, ns, ms, gammas, betas, states, half, ctx)
     res = (_CResult * count)()
     _check(load_library().qnae_qaoa_run_batched(ctx.handle, inst, count, res, _stream(stream)))
     return list(map(Result._make, np.frombuffer(res, dtype=np.float64).reshape(count, 3).tolist()))
+
+
+def autotune_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, reps: int = 3,
+                     ctx: Optional[Context] = None, stream=None) -> dict:
+    """Tune the batched path's tile shape on this batch (every candidate
+    shape, `reps` timed runs each) and keep the fastest on the context for
+    every (n, cost type) of its instances with n > 14; returns it ({} when
+    there are none)."""
+    count = len(costs)
+    ctx = ctx or default_context()
+    inst, _keep = _instances(costs, ns, ms, gammas, betas, states, half, ctx)
+    t = _CTune()
+    _check(load_library().qnae_autotune_batched(ctx.handle, inst, count, int(reps), ctypes.byref(t), _stream(stream)))
+    return _tune_dict(t) if t.tile_bits else {}
 
 
 def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_energy: float = 0.0,

@@ -37,7 +37,11 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
         if (rc) return fail(rc, "job %d: %s", i, std::string(last_error()).c_str());
     }
     if (count == 0) return QNAE_OK;
-    if (int rc = enter(ctx)) return rc;
+    // Own staging (not the context's shared blob), so a batched run queued
+    // right after this build prepares its host work while these kernels run.
+    if (!ctx) return fail(QNAE_EINVAL, "null context");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipEventSynchronize(ctx->cost_staging_done));
     hipStream_t s = (hipStream_t)stream;
 
     // Layout: clause records | zero counters | per type: CostArgs[] and first[]
@@ -53,10 +57,10 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
         args_at[g] = B.take(sizeof(qnae::CostArgs) * groups[g].size());
         first_at[g] = B.take(sizeof(uint32_t) * (groups[g].size() + 1));
     }
-    HIP_TRY(ctx->h_blob.reserve(B.size));
-    HIP_TRY(ctx->b_blob.reserve(B.size));
-    char* h = (char*)ctx->h_blob.ptr;
-    char* d = (char*)ctx->b_blob.ptr;
+    HIP_TRY(ctx->h_cblob.reserve(B.size));
+    HIP_TRY(ctx->c_blob.reserve(B.size));
+    char* h = (char*)ctx->h_cblob.ptr;
+    char* d = (char*)ctx->c_blob.ptr;
     ClauseRec* recs = (ClauseRec*)(h + rec_at);
     // each job's records start at the sum of the clause counts before it
     std::vector<size_t> rec_off(count);
@@ -106,7 +110,7 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
                                            (g & 1) != 0, s);
         }));
     }
-    HIP_TRY(hipEventRecord(ctx->staging_done, s));
+    HIP_TRY(hipEventRecord(ctx->cost_staging_done, s));
     bool want = false;
     for (int i = 0; i < count; ++i) want |= jobs[i].num_solutions != nullptr;
     if (want) {
@@ -123,6 +127,200 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
     return host_exception();
 }
 
+}  // extern "C"
+
+namespace qnae_host {
+
+// Everything about a batch of solves that depends on its shape (instance
+// sizes, cost types, tile shapes and buffers) and not on its angles: the
+// sweep plans, the grouping of their steps into launches, the layout of the
+// uploaded blob with a host image of its angle-free part, and the captured
+// launch sequence. A repeated shape reuses it, so a call rebuilds only the
+// phase tables and the angle fields of the kernel arguments.
+struct BatchPlan {
+    struct Ident {
+        int32_t n, m, p, dtype, half, tb, low, page;
+        const void* cost;
+        void* state;
+        bool operator==(const Ident& o) const {
+            return n == o.n && m == o.m && p == o.p && dtype == o.dtype && half == o.half && tb == o.tb &&
+                   low == o.low && page == o.page && cost == o.cost && state == o.state;
+        }
+    };
+    struct Job {
+        bool resident = false;
+        int T = 1;
+        size_t lut_at = 0, form_at = 0;    // element offsets into the table / form areas
+        size_t state_at = 0, part_at = 0;  // element offsets into batch states / partials
+        uint32_t tiles = 0;
+        SweepPlan plan;
+    };
+    struct Launch {
+        int kind, dtype, step, tb;
+        bool half;
+        std::vector<int> members;
+        size_t args_at, first_at;
+        uint32_t blocks;
+        double bytes;
+    };
+    uint64_t key = 0;
+    std::vector<Ident> ident;
+    void *blob = nullptr, *states = nullptr, *parts = nullptr, *results = nullptr;  // buffers the arguments point into
+    std::vector<Job> jobs;
+    std::vector<Launch> launches;
+    std::vector<int> res_members[2], sweep_members;
+    size_t lut_elems = 0, form_elems = 0, state_elems = 0, part_elems = 0;
+    size_t lut_at = 0, form_at = 0, fixed_at = 0, res_at[2] = {0, 0};
+    size_t red_part_at = 0, red_blocks_at = 0, red_out_at = 0, size = 0;
+    std::vector<unsigned char> fixed;  // host image of the blob from fixed_at on (angle fields filled per call)
+    hipGraphExec_t exec = nullptr;
+    uint64_t exec_reverse = 0;  // the final-state reversals the captured sequence holds
+    ~BatchPlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+void free_batch_plan(BatchPlan* p) { delete p; }
+
+}  // namespace qnae_host
+
+namespace {
+
+using BatchPlan = qnae_host::BatchPlan;
+
+uint64_t fnv(uint64_t h, uint64_t v) { return (h ^ v) * 1099511628211ull; }
+
+// The plan of a new batch shape; reserves the context's batch buffers.
+int make_batch_plan(qnae_ctx* ctx, const qnae_instance* inst, int count, BatchPlan& P) {
+    P.jobs.resize(count);
+    int maxp = 1;
+    for (int i = 0; i < count; ++i) maxp = std::max(maxp, inst[i].p);
+    const std::vector<MixForm> no_forms((size_t)maxp, MixForm{0.f, 0});  // plans need no angles
+    int steps = 0;
+    for (int i = 0; i < count; ++i) {
+        const qnae_instance& q = inst[i];
+        const BatchPlan::Ident& id = P.ident[i];
+        BatchPlan::Job& J = P.jobs[i];
+        J.resident = q.n <= kResidentMaxN;
+        J.T = q.p > 0 ? q.p : 1;
+        J.lut_at = P.lut_elems;
+        P.lut_elems += (size_t)J.T * (q.m + 1);
+        J.form_at = P.form_elems;
+        P.form_elems += (size_t)J.T;
+        const int stored = q.n - (q.half ? 1 : 0);
+        J.tiles = J.resident ? 0u : 1u << (stored - id.tb);
+        J.part_at = P.part_elems;
+        P.part_elems += 3 * (size_t)J.tiles;
+        J.state_at = P.state_elems;
+        if (!J.resident && !q.state_dev) P.state_elems += (size_t)1 << stored;
+        if (!J.resident) {
+            plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, id.tb, id.low, id.page, q.state_dev != nullptr,
+                        no_forms.data(), std::complex<double>(1.0, 0.0));
+            J.plan.half = q.half != 0;
+            steps = std::max(steps, (int)J.plan.ops.size());
+        }
+    }
+    Blob B;
+    P.lut_at = B.take(sizeof(float2) * P.lut_elems);
+    P.form_at = B.take(sizeof(MixForm) * P.form_elems);
+    P.fixed_at = B.take(0);
+    // Sweep launches: step s, bucket (kind, cost type, half, tile bits).
+    for (int st = 0; st < steps; ++st) {
+        std::map<std::tuple<int, int, bool, int>, size_t> bucket;
+        for (int i = 0; i < count; ++i) {
+            const BatchPlan::Job& J = P.jobs[i];
+            if (J.resident || st >= (int)J.plan.ops.size()) continue;
+            const auto key = std::make_tuple(J.plan.ops[st].kind, inst[i].cost_dtype, J.plan.half, P.ident[i].tb);
+            auto it = bucket.find(key);
+            if (it == bucket.end()) {
+                it = bucket.emplace(key, P.launches.size()).first;
+                P.launches.push_back({std::get<0>(key), std::get<1>(key), st, std::get<3>(key), std::get<2>(key), {}, 0,
+                                      0, 0u, 0.0});
+            }
+            P.launches[it->second].members.push_back(i);
+        }
+    }
+    for (BatchPlan::Launch& L : P.launches) {
+        L.args_at = B.take(sizeof(SweepArgs) * L.members.size());
+        L.first_at = B.take(sizeof(uint32_t) * (L.members.size() + 1));
+    }
+    for (int i = 0; i < count; ++i) {
+        if (P.jobs[i].resident) P.res_members[inst[i].cost_dtype == QNAE_U16 ? 1 : 0].push_back(i);
+        else P.sweep_members.push_back(i);
+    }
+    for (int g = 0; g < 2; ++g) P.res_at[g] = B.take(sizeof(qnae::ResidentArgs) * P.res_members[g].size());
+    P.red_part_at = B.take(sizeof(double*) * P.sweep_members.size());
+    P.red_blocks_at = B.take(sizeof(uint32_t) * P.sweep_members.size());
+    P.red_out_at = B.take(sizeof(double*) * P.sweep_members.size());
+    P.size = B.size;
+
+    HIP_TRY(ctx->b_blob.reserve(P.size));
+    HIP_TRY(ctx->b_states.reserve(sizeof(float2) * (P.state_elems ? P.state_elems : 1)));
+    HIP_TRY(ctx->b_partials.reserve(sizeof(double) * (P.part_elems ? P.part_elems : 1)));
+    HIP_TRY(ctx->b_results.reserve(sizeof(double) * 3 * count));
+    P.blob = ctx->b_blob.ptr;
+    P.states = ctx->b_states.ptr;
+    P.parts = ctx->b_partials.ptr;
+    P.results = ctx->b_results.ptr;
+
+    // Host image of the argument area: everything but the angle fields.
+    P.fixed.assign(P.size - P.fixed_at, 0);
+    unsigned char* h = P.fixed.data() - P.fixed_at;  // blob offsets index it directly
+    char* d = (char*)P.blob;
+    const float2* d_luts = (const float2*)(d + P.lut_at);
+    const MixForm* d_forms = (const MixForm*)(d + P.form_at);
+    double* d_parts = (double*)P.parts;
+    double* d_results = (double*)ctx->b_results.ptr;
+    auto psi_of = [&](int i) -> float2* {
+        return inst[i].state_dev ? (float2*)inst[i].state_dev : (float2*)P.states + P.jobs[i].state_at;
+    };
+    for (BatchPlan::Launch& L : P.launches) {
+        SweepArgs* args = (SweepArgs*)(h + L.args_at);
+        uint32_t* first = (uint32_t*)(h + L.first_at);
+        for (size_t q = 0; q < L.members.size(); ++q) {
+            const int i = L.members[q];
+            const BatchPlan::Job& J = P.jobs[i];
+            const Op& op = J.plan.ops[L.step];
+            sweep_args(J.plan, op, psi_of(i), inst[i].cost_dev, d_luts + J.lut_at, d_parts + J.part_at, &args[q]);
+            first[q] = L.blocks;
+            if ((uint64_t)L.blocks + J.tiles > 0x7fffffffull) return fail(QNAE_EINVAL, "batch too large for one grid");
+            L.blocks += J.tiles;
+            L.bytes += op_bytes(J.plan, op);
+        }
+        first[L.members.size()] = L.blocks;
+    }
+    for (int g = 0; g < 2; ++g) {
+        qnae::ResidentArgs* ra = (qnae::ResidentArgs*)(h + P.res_at[g]);
+        for (size_t q = 0; q < P.res_members[g].size(); ++q) {
+            const int i = P.res_members[g][q];
+            const BatchPlan::Job& J = P.jobs[i];
+            ra[q].state_in = nullptr;
+            ra[q].cost = inst[i].cost_dev;
+            ra[q].luts = d_luts + J.lut_at;
+            ra[q].forms = d_forms + J.form_at;
+            ra[q].state_out = (float2*)inst[i].state_dev;
+            ra[q].out = d_results + 3 * (size_t)i;
+            ra[q].n = inst[i].n;
+            ra[q].p = inst[i].p;
+            ra[q].lut_len = inst[i].m + 1;
+        }
+    }
+    const double** rp = (const double**)(h + P.red_part_at);
+    uint32_t* rb = (uint32_t*)(h + P.red_blocks_at);
+    double** ro = (double**)(h + P.red_out_at);
+    for (size_t q = 0; q < P.sweep_members.size(); ++q) {
+        const int i = P.sweep_members[q];
+        rp[q] = d_parts + P.jobs[i].part_at;
+        rb[q] = P.jobs[i].tiles;
+        ro[q] = d_results + 3 * (size_t)i;
+    }
+    return QNAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t count, qnae_result* out, void* stream) try {
     if (count < 0 || (count > 0 && (!inst || !out))) return fail(QNAE_EINVAL, "bad instance array (count=%d)", count);
     for (int i = 0; i < count; ++i) {
@@ -137,193 +335,122 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     if (count == 0) return QNAE_OK;
     if (int rc = enter(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const int TB = qnae::kBatchTileBits;
 
-    // ---- host plan ---------------------------------------------------------
-    struct Job {
-        bool resident;
-        int T;
-        size_t lut_at, form_at;       // element offsets into the table / form areas
-        size_t state_at, part_at;     // element offsets into batch states / partials
-        uint32_t tiles;
-        SweepPlan plan;
-        std::complex<double> final_scale;
-    };
-    std::vector<Job> jobs(count);
-    size_t lut_elems = 0, form_elems = 0, state_elems = 0, part_elems = 0;
-    int steps = 0;
+    // ---- the batch's shape: a plan seen before, or a new one ----------------
+    std::vector<BatchPlan::Ident> ident(count);
+    uint64_t key = 1469598103934665603ull;
     for (int i = 0; i < count; ++i) {
         const qnae_instance& q = inst[i];
-        Job& J = jobs[i];
-        J.resident = q.n <= kResidentMaxN;
-        J.T = q.p > 0 ? q.p : 1;
-        J.lut_at = lut_elems;
-        lut_elems += (size_t)J.T * (q.m + 1);
-        J.form_at = form_elems;
-        form_elems += (size_t)J.T;
-        const int stored = q.n - (q.half ? 1 : 0);
-        J.tiles = J.resident ? 0u : 1u << (stored - TB);
-        J.part_at = part_elems;
-        part_elems += 3 * (size_t)J.tiles;
-        J.state_at = state_elems;
-        if (!J.resident && !q.state_dev) state_elems += (size_t)1 << stored;
+        const qnae_tune t = q.n <= kResidentMaxN ? qnae_tune{0, 0, 0, 0.0} : tune_for(ctx, q.n, q.cost_dtype);
+        ident[i] = {q.n, q.m, q.p, q.cost_dtype, q.half, t.tile_bits, t.low_run_bits, t.page_bit, q.cost_dev,
+                    q.state_dev};
+        key = fnv(key, (uint64_t)q.n | (uint64_t)q.m << 8 | (uint64_t)q.p << 24 | (uint64_t)t.tile_bits << 56);
+        key = fnv(key, (uint64_t)(uintptr_t)q.cost_dev ^ ((uint64_t)(uintptr_t)q.state_dev << 1) ^
+                           ((uint64_t)q.half << 63) ^ ((uint64_t)q.cost_dtype << 62) ^
+                           ((uint64_t)t.low_run_bits << 48) ^ ((uint64_t)t.page_bit << 40));
     }
-    std::vector<float2> tables(lut_elems);
-    std::vector<MixForm> forms(form_elems);
+    BatchPlan* P = nullptr;
+    auto& cache = ctx->batch_plans;
+    for (size_t c = 0; c < cache.size(); ++c) {
+        BatchPlan* e = cache[c].get();
+        if (e->key == key && e->blob == ctx->b_blob.ptr && e->states == ctx->b_states.ptr &&
+            e->parts == ctx->b_partials.ptr && e->results == ctx->b_results.ptr && e->ident == ident) {
+            P = e;
+            std::rotate(cache.begin() + c, cache.begin() + c + 1, cache.end());  // most recent last
+            break;
+        }
+    }
+    if (!P) {
+        std::unique_ptr<BatchPlan, BatchPlanFree> fresh(new BatchPlan());
+        fresh->key = key;
+        fresh->ident = std::move(ident);
+        if (int rc = make_batch_plan(ctx, inst, count, *fresh)) return rc;
+        if (cache.size() >= 8) cache.erase(cache.begin());
+        cache.push_back(std::move(fresh));
+        P = cache.back().get();
+    }
+
+    // ---- per call: tables, forms and the angle fields of the arguments --------
+    HIP_TRY(ctx->h_blob.reserve(P->size));
+    HIP_TRY(ctx->h_results.reserve(sizeof(double) * 3 * count));
+    char* h = (char*)ctx->h_blob.ptr;
+    float2* tables = (float2*)(h + P->lut_at);
+    MixForm* forms = (MixForm*)(h + P->form_at);
+    std::vector<std::complex<double>> scale(count);
     constexpr int kChunk = 16;  // instances per host task
-    parallel_for(ctx, (count + kChunk - 1) / kChunk, lut_elems, [&](int c) {
+    parallel_for(ctx, (count + kChunk - 1) / kChunk, P->lut_elems, [&](int c) {
         for (int i = c * kChunk; i < std::min(count, (c + 1) * kChunk); ++i) {
             const qnae_instance& q = inst[i];
-            Job& J = jobs[i];
-            J.final_scale =
-                build_tables(q.n, q.m, q.gammas, q.betas, q.p, tables.data() + J.lut_at, forms.data() + J.form_at);
+            BatchPlan::Job& J = P->jobs[i];
+            scale[i] = build_tables(q.n, q.m, q.gammas, q.betas, q.p, tables + J.lut_at, forms + J.form_at);
             if (!J.resident) {
-                plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, TB, ctx->min_low_run, ctx->page_bit,
-                            q.state_dev != nullptr, forms.data() + J.form_at, J.final_scale);
-                J.plan.half = q.half != 0;
+                SweepPlan& S = J.plan;
+                S.forms.assign(forms + J.form_at, forms + J.form_at + q.p);
+                for (int l = 0; l < q.p; ++l) S.flips_before[l + 1] = S.flips_before[l] ^ S.forms[l].flip;
+                S.final_scale = scale[i];
             }
         }
     });
-    for (int i = 0; i < count; ++i)
-        if (!jobs[i].resident) steps = std::max(steps, (int)jobs[i].plan.ops.size());
-    Blob B;
-    const size_t lut_at = B.take(sizeof(float2) * lut_elems);
-    const size_t form_at = B.take(sizeof(MixForm) * form_elems);
-    // Sweep launches: step s, bucket (kind, cost type).
-    struct Launch {
-        int kind, dtype, step;
-        bool half;
-        std::vector<int> members;
-        size_t args_at, first_at;
-        uint32_t blocks;
-        double bytes;
-    };
-    std::vector<Launch> launches;
-    for (int st = 0; st < steps; ++st) {
-        std::map<std::tuple<int, int, bool>, size_t> bucket;
-        for (int i = 0; i < count; ++i) {
-            const Job& J = jobs[i];
-            if (J.resident || st >= (int)J.plan.ops.size()) continue;
-            const auto key = std::make_tuple(J.plan.ops[st].kind, inst[i].cost_dtype, J.plan.half);
-            auto it = bucket.find(key);
-            if (it == bucket.end()) {
-                it = bucket.emplace(key, launches.size()).first;
-                launches.push_back({std::get<0>(key), std::get<1>(key), st, std::get<2>(key), {}, 0, 0, 0u, 0.0});
-            }
-            launches[it->second].members.push_back(i);
-        }
-    }
-    for (Launch& L : launches) {
-        L.args_at = B.take(sizeof(SweepArgs) * L.members.size());
-        L.first_at = B.take(sizeof(uint32_t) * (L.members.size() + 1));
-    }
-    std::vector<int> res_members[2], sweep_members;
-    for (int i = 0; i < count; ++i) {
-        if (jobs[i].resident) res_members[inst[i].cost_dtype == QNAE_U16 ? 1 : 0].push_back(i);
-        else sweep_members.push_back(i);
-    }
-    size_t res_at[2];
-    for (int g = 0; g < 2; ++g) res_at[g] = B.take(sizeof(qnae::ResidentArgs) * res_members[g].size());
-    const size_t red_part_at = B.take(sizeof(double*) * sweep_members.size());
-    const size_t red_blocks_at = B.take(sizeof(uint32_t) * sweep_members.size());
-    const size_t red_out_at = B.take(sizeof(double*) * sweep_members.size());
-
-    // ---- device buffers ------------------------------------------------------
-    HIP_TRY(ctx->h_blob.reserve(B.size));
-    std::memcpy((char*)ctx->h_blob.ptr + lut_at, tables.data(), sizeof(float2) * lut_elems);
-    std::memcpy((char*)ctx->h_blob.ptr + form_at, forms.data(), sizeof(MixForm) * form_elems);
-    HIP_TRY(ctx->b_blob.reserve(B.size));
-    HIP_TRY(ctx->b_states.reserve(sizeof(float2) * (state_elems ? state_elems : 1)));
-    HIP_TRY(ctx->b_partials.reserve(sizeof(double) * (part_elems ? part_elems : 1)));
-    HIP_TRY(ctx->b_results.reserve(sizeof(double) * 3 * count));
-    HIP_TRY(ctx->h_results.reserve(sizeof(double) * 3 * count));
-    char* h = (char*)ctx->h_blob.ptr;
-    char* d = (char*)ctx->b_blob.ptr;
-    const float2* d_luts = (const float2*)(d + lut_at);
-    const MixForm* d_forms = (const MixForm*)(d + form_at);
-    float2* d_states = (float2*)ctx->b_states.ptr;
-    double* d_parts = (double*)ctx->b_partials.ptr;
-    double* d_results = (double*)ctx->b_results.ptr;
-
-    auto psi_of = [&](int i) -> float2* {
-        return inst[i].state_dev ? (float2*)inst[i].state_dev : d_states + jobs[i].state_at;
-    };
-    for (Launch& L : launches) {
+    std::memcpy(h + P->fixed_at, P->fixed.data(), P->fixed.size());
+    for (const BatchPlan::Launch& L : P->launches) {
         SweepArgs* args = (SweepArgs*)(h + L.args_at);
-        uint32_t* first = (uint32_t*)(h + L.first_at);
         for (size_t q = 0; q < L.members.size(); ++q) {
-            const int i = L.members[q];
-            const Job& J = jobs[i];
-            const Op& op = J.plan.ops[L.step];
-            sweep_args(J.plan, op, psi_of(i), inst[i].cost_dev, d_luts + J.lut_at, d_parts + J.part_at, &args[q]);
-            first[q] = L.blocks;
-            L.blocks += J.tiles;
-            L.bytes += op_bytes(J.plan, op);
+            const SweepPlan& S = P->jobs[L.members[q]].plan;
+            sweep_args_angles(S, S.ops[L.step], &args[q]);
         }
-        first[L.members.size()] = L.blocks;
     }
     for (int g = 0; g < 2; ++g) {
-        qnae::ResidentArgs* ra = (qnae::ResidentArgs*)(h + res_at[g]);
-        for (size_t q = 0; q < res_members[g].size(); ++q) {
-            const int i = res_members[g][q];
-            const Job& J = jobs[i];
-            ra[q].state_in = nullptr;
-            ra[q].cost = inst[i].cost_dev;
-            ra[q].luts = d_luts + J.lut_at;
-            ra[q].forms = d_forms + J.form_at;
-            ra[q].state_out = (float2*)inst[i].state_dev;
-            ra[q].out = d_results + 3 * (size_t)i;
-            ra[q].store_scale = make_float2((float)J.final_scale.real(), (float)J.final_scale.imag());
-            ra[q].n = inst[i].n;
-            ra[q].p = inst[i].p;
-            ra[q].lut_len = inst[i].m + 1;
+        qnae::ResidentArgs* ra = (qnae::ResidentArgs*)(h + P->res_at[g]);
+        for (size_t q = 0; q < P->res_members[g].size(); ++q) {
+            const std::complex<double> sc = scale[P->res_members[g][q]];
+            ra[q].store_scale = make_float2((float)sc.real(), (float)sc.imag());
         }
     }
-    {
-        const double** rp = (const double**)(h + red_part_at);
-        uint32_t* rb = (uint32_t*)(h + red_blocks_at);
-        double** ro = (double**)(h + red_out_at);
-        for (size_t q = 0; q < sweep_members.size(); ++q) {
-            const int i = sweep_members[q];
-            rp[q] = d_parts + jobs[i].part_at;
-            rb[q] = jobs[i].tiles;
-            ro[q] = d_results + 3 * (size_t)i;
-        }
+    // final states of cot-form runs are stored flipped: those get a reversal
+    uint64_t reverse = 0;
+    for (int i : P->sweep_members) {
+        const SweepPlan& S = P->jobs[i].plan;
+        if (S.keep && !S.half && S.p > 0 && S.flips_before[S.p]) reverse = fnv(reverse ? reverse : 1, (uint64_t)i + 1);
     }
 
     // ---- upload and launch ---------------------------------------------------
-    HIP_TRY(hipMemcpyAsync(d, h, B.size, hipMemcpyHostToDevice, s));
+    char* d = (char*)P->blob;
+    HIP_TRY(hipMemcpyAsync(d, h, P->size, hipMemcpyHostToDevice, s));
+    auto psi_of = [&](int i) -> float2* {
+        return inst[i].state_dev ? (float2*)inst[i].state_dev : (float2*)P->states + P->jobs[i].state_at;
+    };
     // All launches of the batch; `prof` brackets each with timing events.
     auto enqueue = [&](hipStream_t st, bool prof) -> int {
         auto run = [&](int kind, double bytes, auto&& fn) -> hipError_t {
             return prof ? timed(ctx, kind, bytes, st, fn) : fn();
         };
         for (int g = 0; g < 2; ++g) {
-            if (res_members[g].empty()) continue;
+            if (P->res_members[g].empty()) continue;
             double rbytes = 0.0;
-            for (int i : res_members[g]) rbytes += std::ldexp((g ? 2.0 : 1.0) * jobs[i].T, inst[i].n);
+            for (int i : P->res_members[g]) rbytes += std::ldexp((g ? 2.0 : 1.0) * P->jobs[i].T, inst[i].n);
             HIP_TRY(run(K_BATCH_RESIDENT, rbytes, [&] {
-                return qnae::launch_resident_batch(g ? QNAE_U16 : QNAE_U8, (const qnae::ResidentArgs*)(d + res_at[g]),
-                                                   (int)res_members[g].size(), st);
+                return qnae::launch_resident_batch(g ? QNAE_U16 : QNAE_U8, (const qnae::ResidentArgs*)(d + P->res_at[g]),
+                                                   (int)P->res_members[g].size(), st);
             }));
         }
-        for (const Launch& L : launches) {
+        for (const BatchPlan::Launch& L : P->launches) {
             HIP_TRY(run(K_BATCH_SWEEP, L.bytes, [&] {
-                return qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
+                return qnae::launch_sweep_batch(L.tb, L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
                                                 (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, st,
                                                 L.half);
             }));
         }
-        for (int i : sweep_members) {
-            const SweepPlan& P = jobs[i].plan;
-            if (P.keep && !P.half && P.p > 0 && P.flips_before[P.p])
+        for (int i : P->sweep_members) {
+            const SweepPlan& S = P->jobs[i].plan;
+            if (S.keep && !S.half && S.p > 0 && S.flips_before[S.p])
                 HIP_TRY(qnae::launch_reverse(psi_of(i), 1ull << inst[i].n, st));
         }
-        if (!sweep_members.empty()) {
-            HIP_TRY(run(K_BATCH_REDUCE, 24.0 * part_elems / 3, [&] {
-                return qnae::launch_final_reduce_batch((const double* const*)(d + red_part_at),
-                                                       (const uint32_t*)(d + red_blocks_at),
-                                                       (double* const*)(d + red_out_at), (int)sweep_members.size(), st);
+        if (!P->sweep_members.empty()) {
+            HIP_TRY(run(K_BATCH_REDUCE, 24.0 * P->part_elems / 3, [&] {
+                return qnae::launch_final_reduce_batch((const double* const*)(d + P->red_part_at),
+                                                       (const uint32_t*)(d + P->red_blocks_at),
+                                                       (double* const*)(d + P->red_out_at),
+                                                       (int)P->sweep_members.size(), st);
             }));
         }
         return QNAE_OK;
@@ -331,27 +458,14 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     if (ctx->prof.on || !ctx->use_graphs) {
         if (int rc = enqueue(s, ctx->prof.on)) return rc;
     } else {
-        // The launch sequence depends only on the batch's shape and on where
-        // its arguments live, so a captured graph is replayed for a repeated
-        // shape (the arguments themselves were just uploaded).
-        uint64_t key = 1469598103934665603ull;
-        auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
-        mix((uint64_t)(uintptr_t)d);
-        mix(B.size);
-        for (int g = 0; g < 2; ++g) mix(res_members[g].size());
-        for (const Launch& L : launches) {
-            mix((uint64_t)L.half << 48 | (uint64_t)L.kind << 40 | (uint64_t)L.dtype << 32 | L.blocks);
-            mix(L.members.size() << 32 | L.args_at);
+        // The launch sequence depends only on the plan (the arguments were just
+        // uploaded to where it reads them) and on which final states are
+        // reversed, so its capture is replayed while those stay the same.
+        if (P->exec && P->exec_reverse != reverse) {
+            (void)hipGraphExecDestroy(P->exec);
+            P->exec = nullptr;
         }
-        for (int i : sweep_members) {
-            const SweepPlan& P = jobs[i].plan;
-            if (P.keep && !P.half && P.p > 0 && P.flips_before[P.p]) mix((uint64_t)(uintptr_t)psi_of(i) ^ inst[i].n);
-        }
-        mix(sweep_members.size());
-        hipGraphExec_t exec = nullptr;
-        for (auto& e : ctx->graphs)
-            if (e.first == key) exec = e.second;
-        if (!exec) {
+        if (!P->exec) {
             HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
             const int rc = enqueue(ctx->capture_stream, false);
             hipGraph_t graph = nullptr;
@@ -361,23 +475,22 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
                 return rc;
             }
             HIP_TRY(ec);
+            hipGraphExec_t exec = nullptr;
             const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             HIP_TRY(ei);
-            if (ctx->graphs.size() >= 16) {
-                (void)hipGraphExecDestroy(ctx->graphs.front().second);
-                ctx->graphs.erase(ctx->graphs.begin());
-            }
-            ctx->graphs.emplace_back(key, exec);
+            P->exec = exec;
+            P->exec_reverse = reverse;
         }
-        HIP_TRY(hipGraphLaunch(exec, s));
+        HIP_TRY(hipGraphLaunch(P->exec, s));
     }
+    double* d_results = (double*)ctx->b_results.ptr;
     HIP_TRY(hipMemcpyAsync(ctx->h_results.ptr, d_results, sizeof(double) * 3 * count, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ctx->staging_done, s));
     HIP_TRY(hipStreamSynchronize(s));
     const double* r = (const double*)ctx->h_results.ptr;
     for (int i = 0; i < count; ++i) {
-        const double sc = std::norm(jobs[i].final_scale) * (inst[i].half ? 2.0 : 1.0);
+        const double sc = std::norm(scale[i]) * (inst[i].half ? 2.0 : 1.0);
         out[i].p_success = r[3 * i] * sc;
         out[i].expected_cost = r[3 * i + 1] * sc;
         out[i].norm = r[3 * i + 2] * sc;

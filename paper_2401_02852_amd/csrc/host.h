@@ -123,6 +123,13 @@ private:
     bool stop_ = false;
 };
 
+// The plan of a batch shape (batch.cpp).
+struct BatchPlan;
+void free_batch_plan(BatchPlan* p);
+struct BatchPlanFree {
+    void operator()(BatchPlan* p) const { free_batch_plan(p); }
+};
+
 }  // namespace qnae_host
 
 struct qnae_ctx {
@@ -137,10 +144,14 @@ struct qnae_ctx {
     qnae_host::DevBuf g_states, g_blob, g_partials;
     qnae_host::HostBuf h_blob, h_results;
     hipEvent_t staging_done = nullptr;  // last async copy out of pinned staging
-    // captured batch launch sequences (hash of shape and argument addresses)
+    // plans of recent batch shapes, with their captured launch sequences (most recent last)
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;
-    std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
+    std::vector<std::unique_ptr<qnae_host::BatchPlan, qnae_host::BatchPlanFree>> batch_plans;
+    // batched cost builds: their own staging, so a run's host work can overlap their kernels
+    qnae_host::DevBuf c_blob;
+    qnae_host::HostBuf h_cblob;
+    hipEvent_t cost_staging_done = nullptr;
     // sweep tile shapes chosen per (n, cost type), by qnae_autotune or qnae_set_tune
     std::map<std::pair<int, int>, qnae_tune> tunes;
     qnae_host::DevBuf tune_cost;
@@ -302,6 +313,11 @@ struct PlanRef {
 };
 void sweep_args_for(const PlanRef& P, const int* pos, uint32_t mask, const Op& op, float2* psi, const void* cost,
                     const float2* luts, double* partials, qnae::SweepArgs* a);
+// Only the fields that depend on the angles (butterfly parameters, the
+// final scalar factor, complemented cost reads): arguments of a plan whose
+// angles changed.
+void sweep_args_angles(const PlanRef& P, const Op& op, qnae::SweepArgs* a);
+void sweep_args_angles(const SweepPlan& P, const Op& op, qnae::SweepArgs* a);
 // Algorithmic bytes of one op and its profiling kind.
 double op_bytes(const SweepPlan& P, const Op& op);
 int op_profile_kind(const Op& op);

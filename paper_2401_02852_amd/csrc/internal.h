@@ -100,15 +100,12 @@ struct SweepArgs {
 
 hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s);
 
-// Tile size of batched sweeps (log2 amplitudes).
-constexpr int kBatchTileBits = 13;
-
 // One sweep step over `count` states at once. Instance i owns blocks
 // first[i] .. first[i+1]-1 (first has count+1 entries, first[count] =
 // blocks), one per tile of its own geometry; args[i].partials receives 3
-// doubles per tile for readout kinds. Every instance must use
-// kBatchTileBits. half: every instance is a half-state sweep (args[i].half).
-hipError_t launch_sweep_batch(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
+// doubles per tile for readout kinds. Every instance uses tiles of tb bits
+// (12, 13 or 14). half: every instance is a half-state sweep (args[i].half).
+hipError_t launch_sweep_batch(int tb, int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
                               uint32_t blocks, hipStream_t s, bool half = false);
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s);
 

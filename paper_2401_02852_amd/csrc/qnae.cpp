@@ -25,6 +25,7 @@ int qnae_create(qnae_ctx** out, int device) try {
     qnae_ctx* ctx = new qnae_ctx();
     ctx->device = device;
     hipError_t e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->cost_staging_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = ctx->small.reserve(64);
     if (e == hipSuccess) e = ctx->h_small.reserve(64);
@@ -52,14 +53,16 @@ int qnae_destroy(qnae_ctx* ctx) try {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->state, &ctx->partials, &ctx->luts, &ctx->clauses, &ctx->forms, &ctx->small, &ctx->b_blob,
+                      &ctx->c_blob,
                       &ctx->b_states, &ctx->b_partials, &ctx->b_results, &ctx->g_states, &ctx->g_blob,
                       &ctx->g_partials, &ctx->tune_cost, &ctx->s_dev})
         b->release();
     for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results,
-                       &ctx->h_sample})
+                       &ctx->h_sample, &ctx->h_cblob})
         b->release();
     if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
-    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->batch_plans.clear();  // destroys their captured launch sequences
+    if (ctx->cost_staging_done) (void)hipEventDestroy(ctx->cost_staging_done);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto& r : ctx->prof.pending) {
         (void)hipEventDestroy(r.start);

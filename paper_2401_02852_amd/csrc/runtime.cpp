@@ -339,14 +339,20 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
         r.mask_hi_hi = (uint32_t)(mh >> 32);
         r.pat_lo = (uint32_t)pat;
         r.pat_hi = (uint32_t)(pat >> 32);
-        const uint32_t lm = (uint32_t)(mask & 31u), lp = (uint32_t)(pat & 31u);
-        r.zero_tab = 0u;
-        r.full_tab = 0u;
-        for (uint32_t j = 0; j < 32; ++j) {
-            const uint32_t y = (j ^ lp) & lm;
-            if (y == 0u) r.zero_tab |= 1u << j;
-            if (y == lm && predicate == QNAE_PRED_NAE) r.full_tab |= 1u << j;
+        // Over the positions j of a 32-state run, the literal on low variable
+        // v is false where bit v of j equals its negation flag: zero_tab is
+        // the AND of those sets over the clause's low variables, full_tab
+        // (every low literal true) the AND of their complements.
+        static constexpr uint32_t kBitSet[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u, 0xFFFF0000u};
+        uint32_t zero = ~0u, full = ~0u;
+        for (int v = 0; v < 5; ++v) {
+            if (!((mask >> v) & 1u)) continue;
+            const uint32_t ones = kBitSet[v];  // positions j with bit v of j set
+            zero &= ((pat >> v) & 1u) ? ones : ~ones;
+            full &= ((pat >> v) & 1u) ? ~ones : ones;
         }
+        r.zero_tab = zero;
+        r.full_tab = predicate == QNAE_PRED_NAE ? full : 0u;
         recs[nrec++] = r;
     }
     return nrec;
@@ -494,13 +500,7 @@ void sweep_args_for(const PlanRef& P, const int* pos, uint32_t mask, const Op& o
     a->lut_len = P.lut_len;
     a->pre_mask = op.pre_layer >= 0 ? mask : 0u;
     a->post_mask = op.post_layer >= 0 ? mask : 0u;
-    a->pre_t = op.pre_layer >= 0 ? P.forms[op.pre_layer].t : 0.f;
-    a->post_t = op.post_layer >= 0 ? P.forms[op.post_layer].t : 0.f;
-    a->store_scale = make_float2((float)P.final_scale.real(), (float)P.final_scale.imag());
     a->store = P.keep ? 1 : 0;
-    a->cflip = op.kind == qnae::SK_BOUNDARY ? P.flips_before[op.lut_layer]
-               : op.kind == qnae::SK_FINAL  ? P.flips_before[P.p]
-                                            : 0;
     a->half = 0;
     a->vbit = -1;
     a->mir = 0;
@@ -523,8 +523,24 @@ void sweep_args_for(const PlanRef& P, const int* pos, uint32_t mask, const Op& o
         a->tile_bits = unit;
         a->nw = P.n - 1 - P.TB;
         a->mir = stored;
-        a->cflip = 0;  // the stored state is flip-symmetric: flipped reads are the same
     }
+    sweep_args_angles(P, op, a);
+}
+
+void sweep_args_angles(const PlanRef& P, const Op& op, qnae::SweepArgs* a) {
+    a->pre_t = op.pre_layer >= 0 ? P.forms[op.pre_layer].t : 0.f;
+    a->post_t = op.post_layer >= 0 ? P.forms[op.post_layer].t : 0.f;
+    a->store_scale = make_float2((float)P.final_scale.real(), (float)P.final_scale.imag());
+    // half: the stored state is flip-symmetric, so flipped reads are the same
+    a->cflip = P.half                         ? 0
+               : op.kind == qnae::SK_BOUNDARY ? P.flips_before[op.lut_layer]
+               : op.kind == qnae::SK_FINAL    ? P.flips_before[P.p]
+                                              : 0;
+}
+
+void sweep_args_angles(const SweepPlan& P, const Op& op, qnae::SweepArgs* a) {
+    const PlanRef ref{P.n, P.p, P.TB, P.lut_len, P.keep, P.half, P.forms.data(), P.flips_before.data(), P.final_scale};
+    sweep_args_angles(ref, op, a);
 }
 
 double op_bytes(const SweepPlan& P, const Op& op) {

@@ -105,6 +105,7 @@ struct Request {
     int state_order = -1, cost_order = -1, aux_order = -1;
     size_t form_off = 0, part_off = 0;  // inside the aux block (tables at 0)
     uint32_t tiles = 0;
+    qnae_tune shape{};  // tile shape of its sweeps (the context's tuned shape for its n)
     SweepPlan plan;
     std::complex<double> final_scale;
     size_t next_op = 0;
@@ -118,6 +119,10 @@ uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 struct qnae_server {
     qnae_ctx* ctx = nullptr;
     int device = 0;
+    // the context's tile shapes when the server was made: tuned shapes per
+    // (n, cost type) and the default (read on the scheduler thread, so a copy)
+    std::map<std::pair<int, int>, qnae_tune> tunes;
+    qnae_tune default_shape{};
     int max_slots = 1;
     hipStream_t stream = nullptr;
     char* pool = nullptr;
@@ -213,7 +218,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
         r.final_scale = build_tables(r.n, r.m, r.gammas.data(), r.betas.data(), r.p, w.tabs.data(), w.forms.data());
         w.tab_at = B.take(r.part_off);  // same layout as the aux block: tables, then forms
         if (!r.resident) {
-            plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, qnae::kBatchTileBits, ctx->min_low_run, ctx->page_bit, false,
+            plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, r.shape.tile_bits, r.shape.low_run_bits, r.shape.page_bit, false,
                         w.forms.data(), r.final_scale);
             r.plan.half = r.half;
         }
@@ -247,19 +252,21 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
     struct Launch {
         int kind, dtype;
         bool half;
+        int tb;
         std::vector<Request*> members;
         size_t args_at, first_at;
         uint32_t blocks;
     };
-    std::vector<std::map<std::tuple<int, int, bool>, Launch>> sweeps(rounds);
+    std::vector<std::map<std::tuple<int, int, bool, int>, Launch>> sweeps(rounds);
     std::vector<Request*> finishing;
     for (Request* r : large) {
         for (size_t k = 0; k < rounds && r->next_op + k < r->plan.ops.size(); ++k) {
             const Op& op = r->plan.ops[r->next_op + k];
-            Launch& L = sweeps[k][std::make_tuple(op.kind, r->dtype, r->half)];
+            Launch& L = sweeps[k][std::make_tuple(op.kind, r->dtype, r->half, r->shape.tile_bits)];
             L.kind = op.kind;
             L.dtype = r->dtype;
             L.half = r->half;
+            L.tb = r->shape.tile_bits;
             L.members.push_back(r);
         }
         if (r->next_op + rounds >= r->plan.ops.size()) finishing.push_back(r);
@@ -375,7 +382,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
     for (size_t k = 0; k < rounds; ++k)
         for (auto& kv : sweeps[k]) {
             const Launch& L = kv.second;
-            HIP_TRY(qnae::launch_sweep_batch(L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
+            HIP_TRY(qnae::launch_sweep_batch(L.tb, L.dtype, L.kind, (const SweepArgs*)(d + L.args_at),
                                              (const uint32_t*)(d + L.first_at), (int)L.members.size(), L.blocks, s,
                                              L.half));
             ++launches;
@@ -504,6 +511,8 @@ int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qn
     std::unique_ptr<qnae_server> S(new qnae_server());
     S->ctx = ctx;
     S->device = ctx->device;
+    S->tunes = ctx->tunes;
+    S->default_shape = qnae_tune{ctx->tile_bits, ctx->min_low_run, ctx->page_bit, 0.0};
     S->max_slots = max_slots;
     S->pool_bytes = 1ull << order;
     if (const char* e = std::getenv("QNAE_SERVER_HALF")) S->use_half = std::atoi(e) != 0;
@@ -556,7 +565,11 @@ int qnae_server_submit(qnae_server* S, const int32_t* clauses, int32_t m, int32_
     }
     r->resident = n <= kResidentMaxN;
     r->half = !r->resident && S->use_half;
-    r->tiles = r->resident ? 0u : 1u << (n - (r->half ? 1 : 0) - qnae::kBatchTileBits);
+    {
+        auto it = S->tunes.find({n, dtype});
+        r->shape = it != S->tunes.end() ? it->second : S->default_shape;
+    }
+    r->tiles = r->resident ? 0u : 1u << (n - (r->half ? 1 : 0) - r->shape.tile_bits);
     int so, co, ao;
     if (!S->plan_blocks(*r, &so, &co, &ao))
         return fail(QNAE_EINVAL, "request with n=%d does not fit a pool of %llu bytes", n,

@@ -584,10 +584,9 @@ hipError_t launch_tb(int kind, const SweepArgs& a, hipStream_t s) {
     }
 }
 
-template <typename CT>
+template <int TB, typename CT>
 hipError_t launch_batch_ct(int kind, const SweepArgs* args, const uint32_t* first, int count, uint32_t blocks,
                            bool half, hipStream_t s) {
-    constexpr int TB = kBatchTileBits;
     switch (kind) {
         case SK_FIRST: return launch_batch_kind<TB, CT, SK_FIRST>(args, first, count, blocks, half, s);
         case SK_MIDDLE: return launch_batch_kind<TB, CT, SK_MIDDLE>(args, first, count, blocks, half, s);
@@ -614,10 +613,21 @@ hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStre
     }
 }
 
-hipError_t launch_sweep_batch(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
+template <int TB>
+hipError_t launch_batch_tb(int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
+                           uint32_t blocks, hipStream_t s, bool half) {
+    return dtype == 1 ? launch_batch_ct<TB, uint8_t>(kind, args, first, count, blocks, half, s)
+                      : launch_batch_ct<TB, uint16_t>(kind, args, first, count, blocks, half, s);
+}
+
+hipError_t launch_sweep_batch(int tb, int dtype, int kind, const SweepArgs* args, const uint32_t* first, int count,
                               uint32_t blocks, hipStream_t s, bool half) {
-    return dtype == 1 ? launch_batch_ct<uint8_t>(kind, args, first, count, blocks, half, s)
-                      : launch_batch_ct<uint16_t>(kind, args, first, count, blocks, half, s);
+    switch (tb) {
+        case 12: return launch_batch_tb<12>(dtype, kind, args, first, count, blocks, s, half);
+        case 13: return launch_batch_tb<13>(dtype, kind, args, first, count, blocks, s, half);
+        case 14: return launch_batch_tb<14>(dtype, kind, args, first, count, blocks, s, half);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s) {

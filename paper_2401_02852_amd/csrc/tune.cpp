@@ -4,6 +4,9 @@
 // entries, angles away from the special values, so every sweep kind of a
 // p >= 2 plan runs (first, middle, boundary, final).
 #include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
 #include <cmath>
 
 #include "host.h"
@@ -115,6 +118,52 @@ int qnae_set_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, const qnae_tune*
     }
     if (int rc = check_shape(*tune)) return rc;
     ctx->tunes[{n, cost_dtype}] = qnae_tune{tune->tile_bits, tune->low_run_bits, tune->page_bit, tune->ms_per_layer};
+    return QNAE_OK;
+} catch (...) {
+    return host_exception();
+}
+
+int qnae_autotune_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t count, int32_t reps, qnae_tune* out,
+                          void* stream) try {
+    if (reps < 1 || reps > 100) return fail(QNAE_EINVAL, "reps=%d outside [1, 100]", reps);
+    if (!out) return fail(QNAE_EINVAL, "null output pointer");
+    if (count < 0 || (count > 0 && !inst)) return fail(QNAE_EINVAL, "bad instance array (count=%d)", count);
+    if (!ctx) return fail(QNAE_EINVAL, "null context");
+    *out = qnae_tune{0, 0, 0, 0.0};
+    // the (n, cost type) classes the shape applies to: instances on the sweep path
+    std::vector<std::pair<int, int>> classes;
+    int layers = 0;
+    for (int i = 0; i < count; ++i) {
+        layers += inst[i].p;
+        if (inst[i].n <= kResidentMaxN) continue;
+        const std::pair<int, int> c{inst[i].n, inst[i].cost_dtype};
+        if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+    }
+    if (classes.empty()) return QNAE_OK;
+    std::vector<qnae_result> res((size_t)count);
+    const auto saved = ctx->tunes;
+    qnae_tune best{0, 0, 0, 1e300};
+    for (int TB = 12; TB <= 14; ++TB)
+        for (int low = 4; low <= 5; ++low)
+            for (int page : {18, 64}) {
+                const qnae_tune shape{TB, low, page, 0.0};
+                for (const auto& c : classes) ctx->tunes[c] = shape;
+                // one warm-up run plans the shape and captures its launches
+                int rc = qnae_qaoa_run_batched(ctx, inst, count, res.data(), stream);
+                const auto t0 = std::chrono::steady_clock::now();
+                for (int r = 0; r < reps && !rc; ++r) rc = qnae_qaoa_run_batched(ctx, inst, count, res.data(), stream);
+                if (rc) {
+                    const std::string msg = last_error();
+                    ctx->tunes = saved;
+                    return fail(rc, "autotune_batched: %s", msg.c_str());
+                }
+                const double ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+                const double per_layer = ms / std::max(layers, 1);
+                if (per_layer < best.ms_per_layer) best = qnae_tune{TB, low, page, per_layer};
+            }
+    for (const auto& c : classes) ctx->tunes[c] = best;
+    *out = best;
     return QNAE_OK;
 } catch (...) {
     return host_exception();

@@ -318,6 +318,51 @@ static std::vector<Op> vector_make_plan(int ngroups, int p, bool from_state) {
     }
 }
 
+// Half-state addressing as the sweep kernels compute it: every stored index
+// y < 2^(n-1) is reached by exactly one element of one tile per sweep, for
+// every tile shape, including tiles as large as the stored half (n - 1 = TB).
+static void check_half_addressing() {
+    std::vector<qnae::MixForm> forms(2, qnae::MixForm{0.5f, 0});
+    for (int TB = 12; TB <= 14; ++TB)
+        for (int cmin = 4; cmin <= 6; ++cmin)
+            for (int page : {13, 64})
+                for (int n = std::max(15, TB + 1); n <= 17; ++n) {
+                    SweepPlan P;
+                    plan_sweeps(P, n, 10, 2, QNAE_U8, TB, cmin, page, false, forms.data(),
+                                std::complex<double>(1.0, 0.0));
+                    P.half = true;
+                    const uint64_t N = 1ull << (n - 1);
+                    std::vector<uint8_t> hits(N);
+                    for (const Op& op : P.ops) {
+                        qnae::SweepArgs a;
+                        sweep_args(P, op, nullptr, nullptr, nullptr, nullptr, &a);
+                        CHECK(a.nw == n - 1 - TB && popcount64(a.wmask) == a.nw);
+                        std::fill(hits.begin(), hits.end(), 0);
+                        for (uint64_t t = 0; t < (1ull << a.nw); ++t) {
+                            uint64_t base = 0, w = t;
+                            for (uint64_t m = a.wmask; m != 0ull; m &= m - 1ull, w >>= 1)
+                                if (w & 1ull) base |= m & (~m + 1ull);
+                            for (uint32_t e = 0; e < (1u << TB); ++e) {
+                                uint64_t x = 0;
+                                bool mirrored = false;
+                                for (int i = 0; i < TB; ++i) {
+                                    if (!((e >> i) & 1u)) continue;
+                                    if (i == a.vbit) mirrored = true;
+                                    else x |= 1ull << a.pos[i];
+                                }
+                                const uint64_t y = mirrored ? a.mir - (base + x) : base + x;
+                                CHECK(y < N);
+                                CHECK(hits[y] == 0);
+                                hits[y] = 1;
+                                // pairs along tile bit 0 are 16-byte aligned (mirrored ones one slot lower)
+                                if (!(e & 1u)) CHECK(((mirrored ? y - 1 : y) & 1ull) == 0ull);
+                            }
+                        }
+                        for (uint64_t y = 0; y < N; ++y) CHECK(hits[y] == 1);
+                    }
+                }
+}
+
 static void check_fixed_planner_matches_vectors() {
     for (int TB = 12; TB <= 14; ++TB)
         for (int cmin = 4; cmin <= 6; ++cmin)
@@ -346,6 +391,7 @@ static void check_fixed_planner_matches_vectors() {
 
 int main() {
     check_fixed_planner_matches_vectors();
+    check_half_addressing();
     check_groups_and_plans();
     check_clause_records();
     check_phase_rows();

@@ -179,3 +179,93 @@ def test_empty_batches(q):
     g, b = inst.ramp_angles(3)
     got = q.qaoa_run_batched([c], [9], [19], [g], [-b])
     assert np.allclose(got[0], q.qaoa_run(c, 9, 19, g, -b), rtol=1e-12, atol=1e-15)
+
+
+SHAPES = [{"tile_bits": tb, "low_run_bits": low, "page_bit": page}
+          for tb in (12, 13, 14) for low in (4, 5) for page in (18, 64)]
+
+
+def test_batched_under_every_tile_shape(q):
+    """Every tile shape the autotuners may keep, set for the batch's sizes:
+    each batched result equals the single-instance path under the same
+    shape (same plan, same rounding), and a sample matches the oracle."""
+    jobs = [j for j in ragged(60, 6, n_lo=12, n_hi=20)]
+    ns = [j[0] for j in jobs]
+    costs = q.build_cost_diagonals([j[3] for j in jobs], ns)
+    classes = {(n, "u16" if c.dtype.itemsize == 2 else "u8") for n, c in zip(ns, costs) if n > 14}
+    for shape in SHAPES:
+        ctx = q.Context()
+        for n, dt in classes:
+            ctx.set_tune(n, shape, cost_dtype=dt)
+        res = q.qaoa_run_batched(costs, ns, [j[2] for j in jobs], [j[4] for j in jobs], [j[5] for j in jobs],
+                                 ctx=ctx)
+        for (n, k, m, cl, g, b), c, r in zip(jobs, costs, res):
+            alone = q.qaoa_run(c, n, m, g, b, ctx=ctx)
+            assert np.allclose(r, alone, rtol=1e-12, atol=1e-15), (shape, n, m, r, alone)
+        for i in range(0, len(jobs), 13):
+            n, k, m, cl, g, b = jobs[i]
+            ref = oracle.qaoa(oracle.cost(cl, n), n, g, b)
+            assert abs(res[i].p_success - ref[0]) <= 1e-5 and abs(res[i].norm - 1) <= 1e-5, shape
+            assert abs(res[i].expected_cost - ref[1]) <= 1e-5 * max(ref[1], 1e-12) + 1e-9, shape
+        ctx.close()
+
+
+def test_autotune_batched_keeps_a_candidate(q):
+    """The batch-level tuner keeps one of the candidate shapes for every
+    (n, cost type) of the batch's tiled instances; afterwards batched and
+    single runs on that context agree."""
+    batch = inst.batched_workload(count=96, seed=3)
+    ns = [x["n"] for x in batch]
+    ms = [x["m"] for x in batch]
+    gs = [x["gammas"] for x in batch]
+    bs = [x["betas"] for x in batch]
+    costs = q.build_cost_diagonals([x["clauses"] for x in batch], ns)
+    ctx = q.Context()
+    best = q.autotune_batched(costs, ns, ms, gs, bs, reps=1, ctx=ctx)
+    assert {k: best[k] for k in ("tile_bits", "low_run_bits", "page_bit")} in SHAPES
+    assert best["ms_per_layer"] > 0
+    for n in sorted({n for n in ns if n > 14}):
+        got = ctx.get_tune(n)
+        assert (got["tile_bits"], got["low_run_bits"], got["page_bit"]) == \
+            (best["tile_bits"], best["low_run_bits"], best["page_bit"]), n
+    res = q.qaoa_run_batched(costs, ns, ms, gs, bs, ctx=ctx)
+    for x, c, r in zip(batch, costs, res):
+        assert np.allclose(r, q.qaoa_run(c, x["n"], x["m"], x["gammas"], x["betas"], ctx=ctx), rtol=1e-12,
+                           atol=1e-15)
+    small = [i for i, n in enumerate(ns) if n <= 14]
+    assert q.autotune_batched([costs[i] for i in small], [ns[i] for i in small], [ms[i] for i in small],
+                              [gs[i] for i in small], [bs[i] for i in small], ctx=ctx) == {}
+    ctx.close()
+
+
+def test_cached_plan_with_kept_states_and_changing_flips(q, monkeypatch):
+    """A repeated batch shape reuses its plan and its captured launches while
+    the angles change, including whether each final state must be reversed
+    (an odd number of cot-form layers): every replay's results and kept
+    states equal an eager context's."""
+    import torch
+    jobs = ragged(24, 7, n_lo=15, n_hi=19)
+    ns = [j[0] for j in jobs]
+    ms = [j[2] for j in jobs]
+    costs = q.build_cost_diagonals([j[3] for j in jobs], ns)
+    monkeypatch.setenv("QNAE_GRAPHS", "0")
+    eager = q.Context()
+    monkeypatch.setenv("QNAE_GRAPHS", "1")
+    graph = q.Context()
+    se = [torch.empty(1 << n, dtype=torch.complex64, device="cuda") for n in ns]
+    sg = [torch.empty(1 << n, dtype=torch.complex64, device="cuda") for n in ns]
+    rng = np.random.default_rng(17)
+    for rep in range(6):
+        # rep 0, 2, 4: every beta in the tan form; 1, 3, 5: one cot-form layer each
+        g = [rng.uniform(-2, 2, 3) for _ in jobs]
+        b = [rng.uniform(-0.6, 0.6, 3) for _ in jobs]
+        if rep % 2:
+            for bb in b:
+                bb[1] = rng.uniform(1.0, 2.0)
+        ref = q.qaoa_run_batched(costs, ns, ms, g, b, states=se, ctx=eager)
+        got = q.qaoa_run_batched(costs, ns, ms, g, b, states=sg, ctx=graph)
+        assert got == ref, rep
+        for a, c in zip(sg, se):
+            assert torch.equal(a, c), rep
+    eager.close()
+    graph.close()

@@ -219,3 +219,28 @@ def test_injected_fault_fails_cleanly(q, monkeypatch):
     with pytest.raises(q.QNAEError, match="injected"):
         s.submit(reqs[0][3], reqs[0][0], reqs[0][4], reqs[0][5])
     s.close()
+
+
+@pytest.mark.parametrize("tb", [12, 14])
+def test_server_uses_the_tuned_tile_shape(q, tb, monkeypatch):
+    """A server copies its context's tile shapes when made: requests of a
+    tuned size run with that shape, and each result equals the single path
+    on a context with the same shape (half and full states)."""
+    for half in ("1", "0"):
+        monkeypatch.setenv("QNAE_SERVER_HALF", half)
+        ctx = q.Context()
+        reqs = requests(24, 40 + tb, n_lo=15, n_hi=20)
+        for n in range(15, 21):
+            for dt in ("u8", "u16"):
+                ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": 5, "page_bit": 18}, cost_dtype=dt)
+        with q.Server(pool_bytes=1 << 28, max_slots=8, ctx=ctx) as s:
+            tickets = [s.submit(r[3], r[0], r[4], r[5]) for r in reqs]
+            got = [s.wait(t, timeout_ms=60000)[0] for t in tickets]
+        for r, res in zip(reqs, got):
+            n, k, m, cl, g, b = r
+            if half == "1":
+                ref = q.qaoa_run_z2(q.build_cost_diagonal_z2(cl, n, ctx=ctx), n, m, g, b, ctx=ctx)
+            else:
+                ref = q.qaoa_run(q.build_cost_diagonal(cl, n, ctx=ctx), n, m, g, b, ctx=ctx)
+            assert close(res, ref), (tb, half, n, m)
+        ctx.close()
