@@ -138,6 +138,29 @@ int qnae_qaoa_run(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype,
                   const double *betas, int32_t p, void *state_dev,
                   qnae_result *out, void *stream);
 
+/* qnae_qaoa_run for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, kernels, sweep plan and results as qnae_qaoa_run (bit for bit,
+ * under the same context's tile settings), but the call allocates nothing,
+ * on the device or on the host: its device scratch (phase tables, mixer
+ * forms, per-tile readout sums, the three result sums) is one static array
+ * of 8.03 MiB that the library holds on each device it runs on until the
+ * process ends, and its host staging is a fixed pinned buffer that
+ * qnae_create reserved. Every call on a device shares that device's array
+ * and keeps the last call's contents (nothing in it needs to start at zero),
+ * so calls that overlap on one device race, also from different contexts.
+ *
+ *   state_dev    required for n > 14 (the sweeps update the state in place);
+ *                optional, as in qnae_qaoa_run, for n <= 14
+ *   limits       p <= 4096; p * (m + 1) <= 2^18 phase table entries;
+ *                n - tile_bits <= 18 (n <= 31 with the default 13-bit tiles)
+ *
+ * Synchronous. Errors: QNAE_EINVAL (as qnae_qaoa_run, a size beyond the
+ * limits, or a missing state_dev), QNAE_EHIP. */
+int qnae_qaoa_run_noalloc(qnae_ctx *ctx, const void *cost_dev, int32_t cost_dtype, int32_t n, int32_t m,
+                          const double *gammas, const double *betas, int32_t p, void *state_dev, qnae_result *out,
+                          void *stream);
+
 /* Gradient of F = w_psucc * p_succ + w_energy * E[C] with respect to every
  * gamma_l and beta_l, by the adjoint (reverse-mode) method written out by
  * hand: dF/dbeta_l = 2 Im <lam_l|sum_j X_j|psi_l> and

@@ -23,6 +23,7 @@ from ._binding import (  # noqa: F401
     qaoa_grad_batched,
     qaoa_run,
     qaoa_run_batched,
+    qaoa_run_noalloc,
     qaoa_run_z2,
     sample,
 )

@@ -144,6 +144,8 @@ def load_library():
                                                ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_CResult), vp]
         lib.qnae_build_cost_diagonal_z2.argtypes = [vp, _I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                                     ctypes.c_int32, u64p, vp]
+        lib.qnae_qaoa_run_noalloc.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
+                                              ctypes.c_int32, vp, ctypes.POINTER(_CResult), vp]
         lib.qnae_qaoa_run_z2.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _F64P, _F64P,
                                          ctypes.c_int32, vp, ctypes.POINTER(_CResult), vp]
         lib.qnae_sample.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, _F64P, ctypes.c_int32, u64p, _I32P,
@@ -168,7 +170,7 @@ def load_library():
                    lib.qnae_qaoa_run_batched, lib.qnae_qaoa_grad, lib.qnae_server_create, lib.qnae_server_submit,
                    lib.qnae_server_wait, lib.qnae_server_stats, lib.qnae_server_destroy, lib.qnae_autotune,
                    lib.qnae_set_tune, lib.qnae_get_tune, lib.qnae_sample, lib.qnae_build_cost_diagonal_z2,
-                   lib.qnae_qaoa_run_z2, lib.qnae_qaoa_grad_batched, lib.qnae_server_cancel,
+                   lib.qnae_qaoa_run_z2, lib.qnae_qaoa_grad_batched, lib.qnae_server_cancel, lib.qnae_qaoa_run_noalloc,
                    lib.qnae_autotune_batched,
                    lib.qnae_server_pool_in_use):
             fn.restype = ctypes.c_int
@@ -413,6 +415,28 @@ def qaoa_run(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[C
         g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
         ctypes.c_void_p(sptr) if sptr is not None else None,
         ctypes.byref(res), _stream(stream)))
+    return Result(res.p_success, res.expected_cost, res.norm)
+
+
+def qaoa_run_noalloc(cost, n: int, m: int, gammas, betas, *, state=None, ctx: Optional[Context] = None,
+                     stream=None) -> Result:
+    """qaoa_run through the entry point that allocates nothing (device
+    scratch in the library's static array; for callers that cannot allocate).
+    ``state`` (complex64, 2^n on the device) is required for n > 14."""
+    g = np.ascontiguousarray(np.atleast_1d(np.asarray(gammas, dtype=np.float64)))
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(betas, dtype=np.float64)))
+    if g.shape != b.shape or g.ndim != 1:
+        raise ValueError("gammas and betas must be 1-D of equal length")
+    _check_n(n)
+    ctx = ctx or default_context()
+    cptr = _device_buffer(cost, "cost", ctx, _cost_types(), 1 << n)
+    sptr = _device_buffer(state, "state", ctx, _state_types(), 1 << n) if state is not None else None
+    res = _CResult()
+    p = g.shape[0]
+    _check(load_library().qnae_qaoa_run_noalloc(
+        ctx.handle, ctypes.c_void_p(cptr), _cost_code(cost), n, m,
+        g.ctypes.data_as(_F64P) if p else None, b.ctypes.data_as(_F64P) if p else None, p,
+        ctypes.c_void_p(sptr) if sptr is not None else None, ctypes.byref(res), _stream(stream)))
     return Result(res.p_success, res.expected_cost, res.norm)
 
 

@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqnae.so")
-SOURCES = ["runtime.cpp", "qnae.cpp", "batch.cpp", "grad.cpp", "server.cpp", "tune.cpp", "sample.cpp",
+SOURCES = ["runtime.cpp", "qnae.cpp", "batch.cpp", "grad.cpp", "server.cpp", "tune.cpp", "sample.cpp", "noalloc.hip",
            "cost.hip", "sweep.hip", "adjoint.hip", "sample.hip"]
 ARCH = os.environ.get("QNAE_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-fPIC", "-O3", "-std=c++17", "-Wall", "-Wno-unused-result"]

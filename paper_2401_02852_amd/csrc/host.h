@@ -163,12 +163,21 @@ struct qnae_ctx {
     int page_bit = 18;                  // first index bit above a 2 MiB page of amplitudes
     // host threads for per-instance planning of large batches (made on first use)
     std::unique_ptr<qnae_host::WorkerPool> pool;
+    // qnae_qaoa_run_noalloc: the device's static scratch array (its address
+    // from hipGetSymbolAddress) and fixed pinned staging, both set up by
+    // qnae_create
+    void* na_dev = nullptr;
+    qnae_host::HostBuf na_host;
 };
 
 namespace qnae_host {
 
 // Makes the context's device current and waits until pinned staging is free.
 int enter(qnae_ctx* ctx);
+// With the context's device current: looks up that device's static scratch
+// array of qnae_qaoa_run_noalloc (once per device) and reserves the
+// context's fixed pinned staging for it.
+int noalloc_setup(qnae_ctx* ctx);
 // fn(i) for i in [0, count), spread over the context's host threads when the
 // work is large enough to pay for the hand-off (`items` units of it).
 void parallel_for(qnae_ctx* ctx, int count, size_t items, const std::function<void(int)>& fn);

@@ -33,6 +33,11 @@ int qnae_create(qnae_ctx** out, int device) try {
         qnae_destroy(ctx);
         return fail(QNAE_EHIP, "qnae_create: %s", hipGetErrorString(e));
     }
+    if (int rc = noalloc_setup(ctx)) {
+        const std::string msg = last_error();
+        qnae_destroy(ctx);
+        return fail(rc, "qnae_create: %s", msg.c_str());
+    }
     if (const char* tb = std::getenv("QNAE_TILE_BITS")) {
         const int v = std::atoi(tb);
         if (v >= 12 && v <= 14) ctx->tile_bits = v;
@@ -58,7 +63,7 @@ int qnae_destroy(qnae_ctx* ctx) try {
                       &ctx->g_partials, &ctx->tune_cost, &ctx->s_dev})
         b->release();
     for (HostBuf* b : {&ctx->h_luts, &ctx->h_clauses, &ctx->h_forms, &ctx->h_small, &ctx->h_blob, &ctx->h_results,
-                       &ctx->h_sample, &ctx->h_cblob})
+                       &ctx->h_sample, &ctx->na_host, &ctx->h_cblob})
         b->release();
     if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
     ctx->batch_plans.clear();  // destroys their captured launch sequences

@@ -307,3 +307,25 @@ def test_misaligned_device_buffers_rejected_without_gpu():
     inst_ = b._CInstance(0x1000, 1, 20, 5, 1, g, g, 0x3008, 0)
     assert lib.qnae_qaoa_run_batched(None, ctypes.byref(inst_), 1, ctypes.byref(res), None) == -1
     assert b"instance 0: state_dev is not 16-byte aligned" in lib.qnae_last_error(None)
+
+
+def test_noalloc_limits_without_gpu():
+    """The entry point that allocates nothing refuses, before it touches the
+    device, inputs beyond its static scratch: more than 4096 layers, phase
+    tables above 2^18 entries, or no state buffer above n = 14."""
+    b = _lib_or_skip()
+    lib = b.load_library()
+    res = b._CResult()
+    g = (ctypes.c_double * 5000)()
+    vp = ctypes.c_void_p
+    assert lib.qnae_qaoa_run_noalloc(None, vp(0x1000), 1, 20, 5, g, g, 4097, vp(0x2000), ctypes.byref(res), None) == -1
+    assert b"layers" in lib.qnae_last_error(None)
+    assert lib.qnae_qaoa_run_noalloc(None, vp(0x1000), 1, 20, 255, g, g, 1100, vp(0x2000), ctypes.byref(res),
+                                     None) == -1
+    assert b"phase tables" in lib.qnae_last_error(None)
+    assert lib.qnae_qaoa_run_noalloc(None, vp(0x1000), 1, 20, 5, g, g, 3, None, ctypes.byref(res), None) == -1
+    assert b"state_dev is required" in lib.qnae_last_error(None)
+    assert lib.qnae_qaoa_run_noalloc(None, vp(0x1000), 1, 20, 5, g, g, 3, vp(0x2008), ctypes.byref(res), None) == -1
+    assert b"aligned" in lib.qnae_last_error(None)
+    assert lib.qnae_qaoa_run_noalloc(None, vp(0x1000), 1, 20, 5, g, g, 3, vp(0x2000), ctypes.byref(res), None) == -1
+    assert b"null context" in lib.qnae_last_error(None)
