@@ -316,19 +316,20 @@ def _device_buffers(ts, name: str, ctx: "Context", dtypes, numels):
     count = len(ts)
     if count == 0:
         return np.zeros(0, dtype=np.uint64), np.zeros(0, dtype=np.int32)
-    try:
-        dev = np.fromiter((t.get_device() for t in ts), dtype=np.int64, count=count)
-        typ = np.fromiter((_DTYPE_CODES.get(t.dtype, 0) for t in ts), dtype=np.int32, count=count)
-        num = np.fromiter((t.numel() for t in ts), dtype=np.int64, count=count)
-        con = np.fromiter((t.is_contiguous() for t in ts), dtype=bool, count=count)
+    codes = _DTYPE_CODES
+    try:  # three passes: (device, contiguous), (entries, dtype), address
+        dc = np.fromiter((2 * t.get_device() + t.is_contiguous() for t in ts), dtype=np.int64, count=count)
+        nt = np.fromiter((4 * t.numel() + codes.get(t.dtype, 0) for t in ts), dtype=np.int64, count=count)
         ptr = np.fromiter((t.data_ptr() for t in ts), dtype=np.uint64, count=count)
     except AttributeError:
-        dev = None
-    allowed = np.array([_DTYPE_CODES[d] for d in dtypes], dtype=np.int32)
-    if dev is None or not isinstance(ts[0], torch.Tensor):
+        dc = None
+    if dc is None or not isinstance(ts[0], torch.Tensor):
+        ptr, typ = None, None
         bad = range(count)
     else:
-        bad = np.nonzero((dev != ctx.device) | ~np.isin(typ, allowed) | (num != np.asarray(numels)) | ~con)[0]
+        typ = (nt & 3).astype(np.int32)
+        allowed = np.array([codes[d] for d in dtypes], dtype=np.int32)
+        bad = np.nonzero((dc != 2 * ctx.device + 1) | ~np.isin(typ, allowed) | ((nt >> 2) != np.asarray(numels)))[0]
     for i in bad:
         _device_buffer(ts[i], f"{name}[{i}]", ctx, dtypes, int(np.broadcast_to(numels, (count,))[i]))
     return ptr, typ
@@ -455,7 +456,7 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     build_cost_diagonal_z2. Returns the list of tensors, or (tensors, solution
     counts) with count_solutions."""
     import torch
-    arrs = [np.ascontiguousarray(np.asarray(c, dtype=np.int32)) for c in clause_sets]
+    arrs = [np.asarray(c, dtype=np.int32) for c in clause_sets]
     if len(arrs) != len(ns):
         raise ValueError("clause_sets and ns differ in length")
     halves = _per_item(half, len(arrs), "half")
@@ -471,7 +472,12 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
         raise ValueError("predicate list and clause_sets differ in length")
     if any(a.ndim != 2 for a in arrs):
         raise ValueError("clauses must be [m, k] literal arrays")
-    mk = np.array([a.shape for a in arrs], dtype=np.int64).reshape(count, 2)
+    mk = np.empty((count, 2), dtype=np.int64)
+    mk[:, 0] = np.fromiter((a.shape[0] for a in arrs), dtype=np.int64, count=count)
+    mk[:, 1] = np.fromiter((a.shape[1] for a in arrs), dtype=np.int64, count=count)
+    # every job's literals in one buffer (one address, offsets by arithmetic)
+    flat = np.concatenate([a.reshape(-1) for a in arrs]) if count and mk.prod(axis=1).sum() else np.zeros(1, np.int32)
+    lit_at = np.concatenate(([0], np.cumsum(mk.prod(axis=1))[:-1])).astype(np.uint64) if count else np.zeros(0, np.uint64)
     hv = np.asarray(halves, dtype=bool)
     nv = np.asarray(ns, dtype=np.int64).reshape(count)
     if np.any(nv < 1) or np.any(nv > 34):
@@ -481,7 +487,7 @@ def build_cost_diagonals(clause_sets, ns, *, outs=None, count_solutions: bool = 
     sols = np.zeros(max(count, 1), dtype=np.uint64)
     jobs = (_CCostJob * count)()
     v = _np_view(jobs, _CCostJob)
-    v["clauses"] = np.fromiter((a.ctypes.data if a.shape[0] else 0 for a in arrs), dtype=np.uint64, count=count)
+    v["clauses"] = np.where(mk[:, 0] > 0, np.uint64(flat.ctypes.data) + np.uint64(4) * lit_at, np.uint64(0))
     v["m"] = mk[:, 0]
     v["n"] = nv
     v["k"] = np.maximum(mk[:, 1], 1)

@@ -20,7 +20,6 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
-from workloads import instances as inst
 from ._binding import Context, build_cost_diagonals, default_context, qaoa_grad_batched, qaoa_run_batched, sample
 
 
@@ -44,12 +43,14 @@ def random_set(k: int, n: int, count: int, seed: int, satisfiable: bool = False,
     instance j from PCG64(seed * 1_000_003 + j) for j = 0, 1, ...; with
     `satisfiable`, the ones without an NAE solution (counted on the GPU) are
     skipped."""
+    from workloads.instances import cnf_instance  # the seeded generator (repository root)
+
     out: List[np.ndarray] = []
     j = 0
     r = r_hat(k)
     while len(out) < count:
         want = count - len(out)
-        batch = [inst.cnf_instance(n, k, r, seed * 1_000_003 + j + i) for i in range(want)]
+        batch = [cnf_instance(n, k, r, seed * 1_000_003 + j + i) for i in range(want)]
         j += want
         if not satisfiable:
             out += batch
