@@ -8,6 +8,8 @@ is no fallback: without the built library every call raises.
 from __future__ import annotations
 
 from ._binding import (  # noqa: F401
+    PreparedBatch,
+    PreparedCostBuild,
     QNAEError,
     Context,
     Result,

@@ -567,6 +567,111 @@ def autotune_batched(costs, ns, ms, gammas, betas, *, states=None, half=False, r
     return _tune_dict(t) if t.tile_bits else {}
 
 
+class PreparedCostBuild:
+    """build_cost_diagonals with the arguments marshalled once: the device
+    buffers are checked and the literals copied into one buffer when it is
+    made, so build() is one library call (the library rebuilds the clause
+    records and the diagonals every time). Later changes to the clause arrays
+    are not seen."""
+
+    def __init__(self, clause_sets, ns, *, outs=None, predicate="nae", half=False, ctx: Optional[Context] = None):
+        import torch
+        arrs = [np.asarray(c, dtype=np.int32) for c in clause_sets]
+        count = len(arrs)
+        if len(ns) != count:
+            raise ValueError("clause_sets and ns differ in length")
+        if any(a.ndim != 2 for a in arrs):
+            raise ValueError("clauses must be [m, k] literal arrays")
+        halves = np.asarray(_per_item(half, count, "half"), dtype=bool)
+        ctx = ctx or default_context()
+        nv = np.asarray(ns, dtype=np.int64).reshape(count)
+        if np.any(nv < 1) or np.any(nv > 34):
+            i = int(np.nonzero((nv < 1) | (nv > 34))[0][0])
+            raise ValueError(f"job {i}: n={int(nv[i])} outside [1, 34]")
+        if outs is None:
+            outs = [torch.empty(1 << int(n - hf), dtype=cost_dtype_for(a.shape[0]), device=f"cuda:{ctx.device}")
+                    for a, n, hf in zip(arrs, nv, halves)]
+        if len(outs) != count:
+            raise ValueError("outs and clause_sets differ in length")
+        preds = [predicate] * count if isinstance(predicate, str) else list(predicate)
+        if len(preds) != count:
+            raise ValueError("predicate list and clause_sets differ in length")
+        ptrs, codes = _device_buffers(outs, "outs", ctx, _cost_types(), np.left_shift(np.int64(1), nv - halves))
+        mk = np.array([a.shape for a in arrs], dtype=np.int64).reshape(count, 2)
+        size = mk.prod(axis=1)
+        self._lits = np.concatenate([a.reshape(-1) for a in arrs]) if size.sum() else np.zeros(1, np.int32)
+        lit_at = np.concatenate(([0], np.cumsum(size)[:-1])).astype(np.uint64) if count else np.zeros(0, np.uint64)
+        self._sols = np.zeros(max(count, 1), dtype=np.uint64)
+        self._jobs = (_CCostJob * count)()
+        v = _np_view(self._jobs, _CCostJob)
+        v["clauses"] = np.where(mk[:, 0] > 0, np.uint64(self._lits.ctypes.data) + np.uint64(4) * lit_at, np.uint64(0))
+        v["m"] = mk[:, 0]
+        v["n"] = nv
+        v["k"] = np.maximum(mk[:, 1], 1)
+        v["cost_dev"] = ptrs
+        v["cost_dtype"] = codes
+        v["predicate"] = np.fromiter((_pred_code(x) for x in preds), dtype=np.int32, count=count)
+        v["half"] = halves
+        self._view, self._count, self._ctx, self.outs = v, count, ctx, outs
+
+    def build(self, *, count_solutions: bool = False, stream=None):
+        """The diagonals into ``outs``; with count_solutions also the
+        solution counts."""
+        self._view["num_solutions"] = (np.uint64(self._sols.ctypes.data) + np.uint64(8) *
+                                       np.arange(self._count, dtype=np.uint64) if count_solutions else np.uint64(0))
+        _check(load_library().qnae_build_cost_diagonal_batched(self._ctx.handle, self._jobs, self._count,
+                                                               _stream(stream)))
+        return (self.outs, [int(x) for x in self._sols[:self._count]]) if count_solutions else self.outs
+
+
+class PreparedBatch:
+    """qaoa_run_batched with the instances marshalled once (device buffers
+    checked, instance records built); run() takes the angles and makes one
+    library call. Angles may be a [count, p] float64 array when every
+    instance has the same p (no per-instance work at all), or per-instance
+    1-D arrays as for qaoa_run_batched; each instance's p is fixed here."""
+
+    def __init__(self, costs, ns, ms, ps, *, states=None, half=False, ctx: Optional[Context] = None):
+        count = len(costs)
+        ctx = ctx or default_context()
+        pv = np.asarray(ps, dtype=np.int64).reshape(count)
+        if np.any(pv < 0):
+            raise ValueError("p must be >= 0")
+        zero = [np.zeros(int(p)) for p in pv]
+        self._inst, _ = _instances(costs, ns, ms, zero, zero, states, half, ctx)
+        self._view = _np_view(self._inst, _CInstance)
+        self._p = pv
+        self._at = np.concatenate(([0], np.cumsum(pv)[:-1])).astype(np.uint64) if count else np.zeros(0, np.uint64)
+        self._count, self._ctx = count, ctx
+        self._keep = (costs, states)
+        self._res = (_CResult * max(count, 1))()
+
+    def _angles(self, values, name):
+        if isinstance(values, np.ndarray) and values.ndim == 2:
+            a = np.ascontiguousarray(values, dtype=np.float64)
+            if a.shape[0] != self._count or np.any(self._p != a.shape[1]):
+                raise ValueError(f"{name}: shape {a.shape} does not match the prepared p of every instance")
+            return a, np.uint64(a.shape[1]) * np.arange(self._count, dtype=np.uint64)
+        if len(values) != self._count:
+            raise ValueError(f"{name}: {len(values)} entries, expected {self._count}")
+        flat, off, cnt = _packed_angles(values, name)
+        if np.any(cnt != self._p):
+            i = int(np.nonzero(cnt != self._p)[0][0])
+            raise ValueError(f"instance {i}: {name} has {int(cnt[i])} entries, prepared p={int(self._p[i])}")
+        return flat, off
+
+    def run(self, gammas, betas, *, stream=None) -> np.ndarray:
+        """Results as a [count, 3] array: p_success, expected_cost, norm."""
+        G, goff = self._angles(gammas, "gammas")
+        B, boff = self._angles(betas, "betas")
+        has = self._p > 0
+        self._view["gammas"] = np.where(has, np.uint64(G.ctypes.data) + np.uint64(8) * goff, np.uint64(0))
+        self._view["betas"] = np.where(has, np.uint64(B.ctypes.data) + np.uint64(8) * boff, np.uint64(0))
+        _check(load_library().qnae_qaoa_run_batched(self._ctx.handle, self._inst, self._count, self._res,
+                                                    _stream(stream)))
+        return np.frombuffer(self._res, dtype=np.float64)[:3 * self._count].reshape(self._count, 3).copy()
+
+
 def qaoa_grad(cost, n: int, m: int, gammas, betas, *, w_psucc: float = 1.0, w_energy: float = 0.0,
               checkpoint_every: int = 4, ctx: Optional[Context] = None, stream=None):
     """Adjoint gradient of w_psucc * p_succ + w_energy * E[C].

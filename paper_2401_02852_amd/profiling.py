@@ -4,13 +4,16 @@
     python -m paper_2401_02852_amd.profiling pmc FETCH_CSV WRITE_CSV \
         COPY_FETCH_CSV COPY_WRITE_CSV COPY_BYTES N OUT.txt -- CMD...
 
+    python -m paper_2401_02852_amd.profiling counters OUT.txt CSV... -- CMD...
+
 `trace` condenses a `--kernel-trace --stats --output-format csv` run into
 per-kernel call counts and average durations. `pmc` turns two counter runs
 (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) into HBM bytes per launch of
 each sweep kind. Each counter is scaled by what it reads for a plain device
 copy of COPY_BYTES (the copy reads and writes COPY_BYTES), so the figures are
 bytes, whatever the counter's own unit convention. The text after `--` is the
-command that produced the input and is written into the summary.
+command that produced the input and is written into the summary. `counters`
+averages any set of counters per launch of each kernel kind.
 
 The summary records a hash of the kernel sources, so a reader (bench.py) can
 tell whether the counters still describe the current kernels.
@@ -44,6 +47,10 @@ def short_name(name: str) -> str:
     if m:
         half = ",half" if m.group(4) == "true" else ""
         return f"sweep_kernel<TB={m.group(1)},{m.group(2).replace('unsigned ', 'u')}{half}> {KIND_NAMES[m.group(3)]}"
+    m = re.match(r"void adjoint_kernel<([a-z ]+), (\d)>", name)
+    if m:
+        kind = {"0": "middle", "1": "boundary", "2": "end"}[m.group(2)]
+        return f"adjoint_kernel<{m.group(1).replace('unsigned ', 'u')}> adjoint_{kind}"
     return name.split("(")[0].replace("void ", "")
 
 
@@ -96,6 +103,29 @@ def pmc(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, n, out, cmd):
         f.write("\n".join(lines) + "\n")
 
 
+def counters(out, cmd, csvs):
+    """Per kernel kind, the average per launch of every counter in the given
+    `--pmc ... --output-format csv` counter_collection files."""
+    agg = OrderedDict()
+    names = []
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            k, c = short_name(r["Kernel_Name"]), r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            a = agg.setdefault(k, {}).setdefault(c, [0, 0.0])
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+    lines = ["# rocprofv3 counters per launch (average over launches of each kernel kind)", f"command: {cmd}",
+             f"kernel_sources_sha256_16: {kernel_source_hash()}", "",
+             f"{'kernel':62s} " + " ".join(f"{c:>34s}" for c in names)]
+    for k, per in agg.items():
+        lines.append(f"{k:62s} " + " ".join(f"{per[c][1] / per[c][0]:34.1f}" if c in per else f"{'-':>34s}"
+                                            for c in names))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def read_traffic(path):
     """{kernel short name: (fetch bytes, write bytes) per launch} and the
     source hash recorded in a pmc summary."""
@@ -121,5 +151,7 @@ if __name__ == "__main__":
         trace(*argv[1:4], cmd)
     elif argv[0] == "pmc":
         pmc(*argv[1:8], cmd)
+    elif argv[0] == "counters":
+        counters(argv[1], cmd, argv[2:])
     else:
         sys.exit(__doc__)

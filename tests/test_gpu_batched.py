@@ -269,3 +269,29 @@ def test_cached_plan_with_kept_states_and_changing_flips(q, monkeypatch):
             assert torch.equal(a, c), rep
     eager.close()
     graph.close()
+
+
+def test_prepared_batch_and_cost_build_match(q):
+    """Prepared cost builds and batches (arguments marshalled once) give the
+    same diagonals, solution counts and results as the per-call functions,
+    with angles as per-instance lists or as one [count, p] array, run after
+    run with new angles."""
+    import torch
+    batch = inst.batched_workload(count=80, seed=11)
+    ns = [x["n"] for x in batch]
+    ms = [x["m"] for x in batch]
+    cls = [x["clauses"] for x in batch]
+    ref_costs, ref_sols = q.build_cost_diagonals(cls, ns, count_solutions=True)
+    cb = q.PreparedCostBuild(cls, ns)
+    for _ in range(2):
+        costs, sols = cb.build(count_solutions=True)
+        assert sols == ref_sols
+        assert all(torch.equal(a, b) for a, b in zip(costs, ref_costs))
+    pb = q.PreparedBatch(costs, ns, ms, [5] * len(batch))
+    rng = np.random.default_rng(2)
+    for rep in range(3):
+        g = rng.uniform(0, np.pi, (len(batch), 5))
+        b = rng.uniform(0, np.pi, (len(batch), 5))
+        ref = np.array(q.qaoa_run_batched(costs, ns, ms, list(g), list(b)))
+        assert np.array_equal(pb.run(g, b), ref), rep
+        assert np.array_equal(pb.run(list(g), list(b)), ref), rep

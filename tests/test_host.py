@@ -329,3 +329,31 @@ def test_noalloc_limits_without_gpu():
     assert b"aligned" in lib.qnae_last_error(None)
     assert lib.qnae_qaoa_run_noalloc(None, vp(0x1000), 1, 20, 5, g, g, 3, vp(0x2000), ctypes.byref(res), None) == -1
     assert b"null context" in lib.qnae_last_error(None)
+
+
+def test_prepared_batch_marshalling_without_gpu():
+    """Prepared batches check their buffers once and marshal angles per run:
+    a 2-D angle array must match every instance's p, lists are checked per
+    instance; the call then reaches the library (which rejects the null
+    context)."""
+    import torch
+    b = _lib_or_skip()
+    ctx = _NullCtx()
+    costs = [_fake_cuda(torch.zeros(1 << 10, dtype=torch.uint8)), _fake_cuda(torch.zeros(1 << 11, dtype=torch.uint8))]
+    with pytest.raises(ValueError, match="entries"):
+        b.PreparedBatch(costs, [10, 12], [5, 5], [2, 2], ctx=ctx)
+    pb = b.PreparedBatch(costs, [10, 11], [5, 5], [2, 2], ctx=ctx)
+    with pytest.raises(ValueError, match="shape"):
+        pb.run(np.zeros((2, 3)), np.zeros((2, 3)))
+    with pytest.raises(ValueError, match="prepared p"):
+        pb.run([np.zeros(2), np.zeros(1)], [np.zeros(2), np.zeros(2)])
+    with pytest.raises(b.QNAEError, match="null context"):
+        pb.run(np.zeros((2, 2)), np.zeros((2, 2)), stream=0)
+    with pytest.raises(b.QNAEError, match="null context"):
+        pb.run([np.zeros(2), np.zeros(2)], [np.zeros(2), np.zeros(2)], stream=0)
+    cl = inst.instance(10, 3, 5, 0)
+    with pytest.raises(ValueError, match="entries"):
+        b.PreparedCostBuild([cl, cl], [10, 12], outs=costs, ctx=ctx)
+    cb = b.PreparedCostBuild([cl, inst.instance(11, 3, 5, 1)], [10, 11], outs=costs, ctx=ctx)
+    with pytest.raises(b.QNAEError, match="null context"):
+        cb.build(count_solutions=True, stream=0)
