@@ -3,8 +3,15 @@
 Section 3.3 selects fixed angles per (k, p) by maximising the mean success
 probability (1/t) sum_i p_succ(sigma_i) over t = 100 random instances
 CNF(n = 12, k, r_hat_k) with Adam for 100 epochs from beta = 0.01,
-gamma = -0.01 (the paper's sign convention; here (gamma, beta) =
-(0.01, 0.01), the same circuit up to the global sign symmetry). Section 4.1
+gamma = -0.01 in the paper's convention. The paper writes the mixer two ways:
+exp(-i beta H_B) in Section 2.1 and exp(+i beta H_B) in Section 3.4 and
+Appendix A.3/A.4. The start is read in the latter convention, because those
+are the sections that describe the simulator the paper ran; this library
+applies exp(-i beta H_B), so the paper's (gamma, beta) is this library's
+(gamma, -beta), i.e. (-0.01, -0.01), which the global sign symmetry
+(gamma, beta) -> (-gamma, -beta) maps to the default start (0.01, 0.01).
+Under Section 2.1's convention the same start would be (0.01, -0.01) here;
+`init` accepts either. Section 4.1
 and 4.2 evaluate the angles on ensembles of satisfiable instances for a range
 of n: the mean success probability and the median running time, and
 Section 4.4 fits both to 2^(c n + d).

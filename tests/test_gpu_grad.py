@@ -23,10 +23,20 @@ def q():
 
 
 def check(dg, db, rg, rb, w):
+    """The p_succ part within 1e-5 absolute and within 1e-3 of the largest
+    reference component (whichever is tighter: small gradients are held to
+    the relative bound), the E[C] part within 1e-4 of the largest."""
     scale = max(np.max(np.abs(rg)), np.max(np.abs(rb)), 1e-12)
-    tol = 1e-5 * abs(w[0]) + 1e-4 * scale * (abs(w[1]) > 0)
+    tol = abs(w[0]) * min(1e-5, 1e-3 * scale + 1e-10) + 1e-4 * scale * (abs(w[1]) > 0)
     assert np.max(np.abs(dg - rg)) <= tol, (dg, rg)
     assert np.max(np.abs(db - rb)) <= tol, (db, rb)
+
+
+def check_readout(r, ro):
+    """p_succ within 1e-5 absolute and 1e-4 relative (whichever is tighter),
+    E[C] within 1e-5 relative."""
+    assert abs(r.p_success - ro[0]) <= min(1e-5, 1e-4 * ro[0] + 1e-12), (r, ro)
+    assert abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1], (r, ro)
 
 
 @pytest.mark.parametrize("n", [4, 9, 13, 14, 16, 19])
@@ -41,7 +51,7 @@ def test_grad_vs_oracle_adjoint(q, n, w):
     dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=2)
     rg, rb, ro = oracle.qaoa_grad(oracle.cost(cl, n), n, g, b, *w)
     check(dg, db, rg, rb, w)
-    assert abs(r.p_success - ro[0]) <= 1e-5 and abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1]
+    check_readout(r, ro)
 
 
 @pytest.mark.parametrize("n", [7, 15])
@@ -106,7 +116,7 @@ def test_grad_three_groups_n23(q):
         dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=2)
         rg, rb, ro = oracle.qaoa_grad(cost, n, g, b, *w)
         check(dg, db, rg, rb, w)
-        assert abs(r.p_success - ro[0]) <= 1e-5 and abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1]
+        check_readout(r, ro)
     del c
     torch.cuda.empty_cache()
 
