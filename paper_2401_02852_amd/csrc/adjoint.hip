@@ -9,7 +9,9 @@
 //   dF/dgamma_l = 2 Im <mu_l | C | phi_l>,
 //   lam_{l-1}   = U_C(gamma_l)^dagger mu_l,   psi_{l-1} = U_C(gamma_l)^dagger phi_l
 // (U_B and U_C as in Section 2.1 / Section 3.2). A reverse sweep applies the
-// inverse one-qubit factors to lam and psi alike. Because X_j commutes with
+// inverse one-qubit factors to lam and psi alike, as the forward sweeps'
+// butterflies (I - i t X), |t| <= 1 (two multiply-adds per amplitude and
+// qubit instead of four for the exact cos/sin form). Because X_j commutes with
 // every one-qubit factor, <lam|X_j|psi> is the same before and after any of
 // them is applied to both states, so the X_j terms of a qubit group are summed
 // inside the sweep that inverts that group. The inverse phase of the layer is
@@ -20,18 +22,6 @@ namespace qnae {
 namespace {
 
 using namespace tile;
-
-// a' = c a - i s b for both members of the pairs on register bit S.
-template <int S>
-__device__ __forceinline__ void ebfly(float2 (&v)[32], float c, float s) {
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-        if (j & (1 << S)) continue;
-        const float2 a = v[j], b = v[j | (1 << S)];
-        v[j] = make_float2(fmaf(c, a.x, s * b.y), fmaf(c, a.y, -s * b.x));
-        v[j | (1 << S)] = make_float2(fmaf(c, b.x, s * a.y), fmaf(c, b.y, -s * a.x));
-    }
-}
 
 // Im of sum over pairs on register bit S of conj(l_a) p_b + conj(l_b) p_a,
 // i.e. the pairs' share of Im <l|X|p> for that bit.
@@ -50,19 +40,24 @@ __device__ __forceinline__ float ipair(const float2 (&l)[32], const float2 (&p)[
     return acc;
 }
 
+// One qubit of an inverse mixer on both states. The butterflies leave out a
+// factor f per qubit, so after k of them both states are 1/f^k of the exact
+// ones and the pair term is |f|^-2k of the exact term: w = |f|^2k restores it.
 template <int S>
-__device__ __forceinline__ void adj_bit(float2 (&l)[32], float2 (&p)[32], float c, float s, float& acc) {
-    acc += ipair<S>(l, p);
-    ebfly<S>(l, c, s);
-    ebfly<S>(p, c, s);
+__device__ __forceinline__ void adj_bit(float2 (&l)[32], float2 (&p)[32], float t, float r, float& w, float& acc) {
+    acc = fmaf(w, ipair<S>(l, p), acc);
+    w *= r;
+    bfly<32, S>(l, t);
+    bfly<32, S>(p, t);
 }
 
-__device__ __forceinline__ void adj_mix(float2 (&l)[32], float2 (&p)[32], uint32_t sm, float c, float s, float& acc) {
-    if (sm & 1u) adj_bit<0>(l, p, c, s, acc);
-    if (sm & 2u) adj_bit<1>(l, p, c, s, acc);
-    if (sm & 4u) adj_bit<2>(l, p, c, s, acc);
-    if (sm & 8u) adj_bit<3>(l, p, c, s, acc);
-    if (sm & 16u) adj_bit<4>(l, p, c, s, acc);
+__device__ __forceinline__ void adj_mix(float2 (&l)[32], float2 (&p)[32], uint32_t sm, float t, float r, float& w,
+                                        float& acc) {
+    if (sm & 1u) adj_bit<0>(l, p, t, r, w, acc);
+    if (sm & 2u) adj_bit<1>(l, p, t, r, w, acc);
+    if (sm & 4u) adj_bit<2>(l, p, t, r, w, acc);
+    if (sm & 8u) adj_bit<3>(l, p, t, r, w, acc);
+    if (sm & 16u) adj_bit<4>(l, p, t, r, w, acc);
 }
 
 // Both register arrays from layout FROM to layout TO through one LDS buffer.
@@ -127,14 +122,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         w >>= 1;
     }
 
+    // Element x of lam sits at x ^ flip in psi (relabelled by an odd number
+    // of cotangent forms since psi was restored), and the phase reads
+    // cost[x ^ a.cost_flip]. The tile's thread part t and slot part s of an
+    // element have disjoint bits, so (t | s) ^ (2^n - 1) = (t ^ (2^n - 1)) - s.
+    const uint64_t all = (1ull << a.n) - 1ull;
     uint32_t cvp[NC];
     if (PHASE) {
-        const CT* const c2 = (const CT*)a.cost + base + scat(L::t2(lane, wave));
+        const uint64_t ct = base + scat(L::t2(lane, wave));
+        const bool cf = a.cost_flip != 0ull;
+        const CT* const c2 = (const CT*)a.cost + (cf ? ct ^ all : ct);
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             uint32_t wv = 0u;
 #pragma unroll
-            for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2(PK * i + q))] << (8 * sizeof(CT) * q);
+            for (int q = 0; q < PK; ++q) {
+                const uint64_t d = scat(L::s2(PK * i + q));
+                wv |= (uint32_t)(cf ? c2[-(int64_t)d] : c2[d]) << (8 * sizeof(CT) * q);
+            }
             cvp[i] = wv;
         }
         // Pack the cost bytes as soon as they arrive (the state loads issued
@@ -152,32 +157,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
     };
 
+    // Layout L0 pairs tile bits 0 (global bit 0) in one float4: flipped, the
+    // pair (x, x + 1) sits at (x ^ (2^n - 1) ^ 1, its successor) in reverse
+    // order.
+    const bool pf = a.psi_flip != 0;
     float2 l[32], p[32];
     {
         const uint64_t o0 = base + scat(L::t0(lane, wave));
+        const float2* const pb = a.psi + (pf ? o0 ^ all ^ 1ull : o0);
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
-            const uint64_t off = o0 + scat(L::s0(2 * jj));
-            const float4 ql = *(const float4*)(a.lam + off);
-            const float4 qp = *(const float4*)(a.psi + off);
+            const uint64_t d = scat(L::s0(2 * jj));
+            const float4 ql = *(const float4*)(a.lam + o0 + d);
+            const float4 qp = *(const float4*)(pf ? pb - d : pb + d);
             l[2 * jj] = make_float2(ql.x, ql.y);
             l[2 * jj + 1] = make_float2(ql.z, ql.w);
-            p[2 * jj] = make_float2(qp.x, qp.y);
-            p[2 * jj + 1] = make_float2(qp.z, qp.w);
+            p[2 * jj] = pf ? make_float2(qp.z, qp.w) : make_float2(qp.x, qp.y);
+            p[2 * jj + 1] = pf ? make_float2(qp.x, qp.y) : make_float2(qp.z, qp.w);
         }
     }
     float acc_pre = 0.f, acc_g = 0.f, acc_post = 0.f;
     {
         const uint32_t m = a.pre_mask;
-        adj_mix(l, p, L::sm0(m), a.pre_c, a.pre_s, acc_pre);
+        float w = a.pre_w;
+        adj_mix(l, p, L::sm0(m), a.pre_t, a.pre_r, w, acc_pre);
         if (L::sm1(m)) {
             xpose2<TB, 0, 1>(lds, l, p, lane, wave);
-            adj_mix(l, p, L::sm1(m), a.pre_c, a.pre_s, acc_pre);
+            adj_mix(l, p, L::sm1(m), a.pre_t, a.pre_r, w, acc_pre);
             xpose2<TB, 1, 2>(lds, l, p, lane, wave);
         } else {
             xpose2<TB, 0, 2>(lds, l, p, lane, wave);
         }
-        adj_mix(l, p, L::sm2(m), a.pre_c, a.pre_s, acc_pre);
+        adj_mix(l, p, L::sm2(m), a.pre_t, a.pre_r, w, acc_pre);
     }
     if (PHASE) {
 #pragma unroll
@@ -198,30 +209,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (POST) {
         const uint32_t m = a.post_mask;
-        adj_mix(l, p, L::sm2(m), a.post_c, a.post_s, acc_post);
+        float w = a.post_w;
+        adj_mix(l, p, L::sm2(m), a.post_t, a.post_r, w, acc_post);
         if (L::sm1(m)) {
             xpose2<TB, 2, 1>(lds, l, p, lane, wave);
-            adj_mix(l, p, L::sm1(m), a.post_c, a.post_s, acc_post);
+            adj_mix(l, p, L::sm1(m), a.post_t, a.post_r, w, acc_post);
             xpose2<TB, 1, 0>(lds, l, p, lane, wave);
         } else {
             xpose2<TB, 2, 0>(lds, l, p, lane, wave);
         }
-        adj_mix(l, p, L::sm0(m), a.post_c, a.post_s, acc_post);
+        adj_mix(l, p, L::sm0(m), a.post_t, a.post_r, w, acc_post);
         const uint64_t o0 = base + scat(L::t0(lane, wave));
+        float2* const pb = a.psi + (pf ? o0 ^ all ^ 1ull : o0);
+        // lam's stores, then psi's under a branch on the (uniform) relabelling:
+        // one loop selecting order and address per element spills 161 instead
+        // of 64 dwords per lane in this kind.
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
-            const uint64_t off = o0 + scat(L::s0(2 * jj));
-            *(float4*)(a.lam + off) = make_float4(l[2 * jj].x, l[2 * jj].y, l[2 * jj + 1].x, l[2 * jj + 1].y);
-            if (a.store_psi)
-                *(float4*)(a.psi + off) = make_float4(p[2 * jj].x, p[2 * jj].y, p[2 * jj + 1].x, p[2 * jj + 1].y);
+            const uint64_t d = scat(L::s0(2 * jj));
+            *(float4*)(a.lam + o0 + d) = make_float4(l[2 * jj].x, l[2 * jj].y, l[2 * jj + 1].x, l[2 * jj + 1].y);
+        }
+        if (a.store_psi) {
+            if (pf) {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj)
+                    *(float4*)(pb - scat(L::s0(2 * jj))) =
+                        make_float4(p[2 * jj + 1].x, p[2 * jj + 1].y, p[2 * jj].x, p[2 * jj].y);
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj)
+                    *(float4*)(pb + scat(L::s0(2 * jj))) =
+                        make_float4(p[2 * jj].x, p[2 * jj].y, p[2 * jj + 1].x, p[2 * jj + 1].y);
+            }
         }
     } else {
         const uint64_t o2 = base + scat(L::t2(lane, wave));
+        float2* const pb = a.psi + (pf ? o2 ^ all : o2);
 #pragma unroll
         for (int j = 0; j < 32; ++j) {
-            const uint64_t off = o2 + scat(L::s2(j));
-            a.lam[off] = l[j];
-            if (a.store_psi) a.psi[off] = p[j];
+            const uint64_t d = scat(L::s2(j));
+            a.lam[o2 + d] = l[j];
+            if (a.store_psi) *(pf ? pb - d : pb + d) = p[j];
         }
     }
     double d0 = acc_pre, d1 = acc_g, d2 = acc_post;

@@ -98,6 +98,7 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
         SweepPlan plan;
         std::vector<AdjOp> aops;
         std::complex<double> final_scale;
+        std::vector<Layer> inv;  // inverse mixer of b-layer i: exp(+i beta X) per qubit
     };
     std::vector<Seg> segs(nseg);
     const int T = p > 0 ? p : 1;
@@ -116,10 +117,15 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
                                           forms.data() + S.a, first);
         plan_sweeps(S.plan, n, m, L, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, true, forms.data() + S.a,
                     S.final_scale, j > 0);
-        // reverse tables: b-layer i is forward layer b - 1 - i, exp(+i gamma c)
+        // reverse tables: b-layer i is forward layer b - 1 - i; its inverse
+        // phase exp(+i gamma c) times the scalar factor its inverse mixer's
+        // butterflies left out
         S.blut_at = (size_t)S.a * lut_len;
-        for (int i = 0; i < L; ++i)
-            phase_row(gammas[S.b - 1 - i], m, 1.0, +1, btab.data() + S.blut_at + (size_t)i * lut_len);
+        S.inv.resize(L);
+        for (int i = 0; i < L; ++i) {
+            S.inv[i] = mixer_form(-betas[S.b - 1 - i], n);
+            phase_row(gammas[S.b - 1 - i], m, S.inv[i].scale, +1, btab.data() + S.blut_at + (size_t)i * lut_len);
+        }
         if (L > 0) S.aops = make_adjoint_plan((int)groups.size(), L);
         total_aops += (int)S.aops.size();
     }
@@ -171,12 +177,20 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     // lam = W psi_p
     float2* psi_p = ck + N * (size_t)(nseg - 1);
     HIP_TRY(qnae::launch_weight(cost_dtype, cost_dev, psi_p, lam, n, w_psucc, w_energy, s));
-    // reverse segments, last first
+    // reverse segments, last first. `relabel`: lam's index x holds element
+    // x ^ (2^n - 1) (an odd number of cotangent forms so far); psi restarts
+    // from a checkpoint in natural order at each segment, so within a segment
+    // it is relabelled against lam by the value `relabel` had at the start.
+    // done[i]: qubits of b-layer i mixed by earlier sweeps.
     int q = 0;
     std::vector<std::pair<int, const AdjOp*>> order;  // (segment, op) in launch order
+    std::vector<double> gamma_weight;                 // per op: |F|^2 of its phase layer
+    int relabel = 0;
     for (int j = nseg - 1; j >= 0; --j) {
         const Seg& S = segs[j];
         float2* psi = ck + N * (size_t)j;
+        const int psi_flip = relabel;
+        std::vector<int> done(S.inv.size(), 0);
         for (const AdjOp& op : S.aops) {
             const Group& g = groups[op.group];
             qnae::AdjointArgs a;
@@ -196,20 +210,40 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
             a.wmask = ((1ull << n) - 1ull) & ~a.tile_bits;
             a.pre_mask = op.pre_layer >= 0 ? g.mask : 0u;
             a.post_mask = op.post_layer >= 0 ? g.mask : 0u;
+            const int qubits = __builtin_popcount(g.mask);
+            // one qubit's |factor|^2: cos^2 (tangent form) or sin^2, 1 / (1 + t^2) either way
+            auto factor2 = [&](int i) {
+                const double b = betas[S.b - 1 - i];
+                const double c = std::cos(b), sn = std::sin(b);
+                return S.inv[i].form.flip ? sn * sn : c * c;
+            };
             if (op.pre_layer >= 0) {
-                const double b = betas[S.b - 1 - op.pre_layer];
-                a.pre_c = (float)std::cos(b);
-                a.pre_s = (float)-std::sin(b);
+                const int i = op.pre_layer;
+                a.pre_t = S.inv[i].form.t;
+                a.pre_r = (float)factor2(i);
+                a.pre_w = (float)std::pow(factor2(i), done[i]);
+                done[i] += qubits;
+            }
+            double gw = 0.0;
+            if (op.phase_layer >= 0) {
+                const int i = op.phase_layer;
+                relabel ^= S.inv[i].form.flip;
+                a.cost_flip = relabel ? (uint64_t)N - 1ull : 0ull;
+                gw = std::pow(factor2(i), n);
             }
             if (op.post_layer >= 0) {
-                const double b = betas[S.b - 1 - op.post_layer];
-                a.post_c = (float)std::cos(b);
-                a.post_s = (float)-std::sin(b);
+                const int i = op.post_layer;
+                a.post_t = S.inv[i].form.t;
+                a.post_r = (float)factor2(i);
+                a.post_w = (float)std::pow(factor2(i), done[i]);
+                done[i] += qubits;
             }
+            a.psi_flip = psi_flip;
             a.store_psi = op.kind == qnae::AK_END ? 0 : 1;
             const double bytes = std::ldexp(32.0 - (a.store_psi ? 0.0 : 8.0) + (op.phase_layer >= 0 ? (cost_dtype == QNAE_U8 ? 1.0 : 2.0) : 0.0), n);
             HIP_TRY(timed(ctx, K_ADJOINT, bytes, s, [&] { return qnae::launch_adjoint(cost_dtype, op.kind, a, s); }));
             order.emplace_back(j, &op);
+            gamma_weight.push_back(gw);
             ++q;
         }
     }
@@ -224,7 +258,7 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
         const Seg& S = segs[order[k].first];
         const AdjOp& op = *order[k].second;
         if (op.pre_layer >= 0) dbetas[S.b - 1 - op.pre_layer] += 2.0 * r[3 * k];
-        if (op.phase_layer >= 0) dgammas[S.b - 1 - op.phase_layer] += 2.0 * r[3 * k + 1];
+        if (op.phase_layer >= 0) dgammas[S.b - 1 - op.phase_layer] += 2.0 * gamma_weight[k] * r[3 * k + 1];
         if (op.post_layer >= 0) dbetas[S.b - 1 - op.post_layer] += 2.0 * r[3 * k + 2];
     }
     const double sc = std::norm(segs[nseg - 1].final_scale);

@@ -210,6 +210,16 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
 // QNAE_EINVAL if some literal is 0 or outside +-[1, n].
 int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k);
 
+// One layer's mixer exp(-i beta X) on each of n qubits as device butterflies
+// (I - i t X) per qubit, |t| <= 1, followed by X on every qubit when
+// form.flip, times the scalar `scale` (cos(beta)^n, or (-i sin(beta))^n with
+// the flip).
+struct Layer {
+    qnae::MixForm form;
+    std::complex<double> scale;
+};
+Layer mixer_form(double beta, int n);
+
 // scale * exp(sign i g c) for c = 0..m (sign -1 or +1) as m + 1 FP32 pairs.
 void phase_row(double g, int m, std::complex<double> scale, int sign, float2* out);
 // Phase tables (p tables of m + 1 entries, or one when p = 0) and per-layer

@@ -126,8 +126,12 @@ hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s);
 // ---------------------------------------------------------------------------
 // Adjoint (gradient) sweeps: the reverse pass carries the adjoint state lam
 // and the forward state psi together and applies the inverse of each layer to
-// both (psi is uncomputed), with exact butterflies (cos, -sin) so no scalar
-// factor or relabelling is involved. Tiles as in the forward sweeps, TB = 13.
+// both (psi is uncomputed). The inverse mixers use the forward sweeps'
+// butterflies (I - i t X) with |t| <= 1: the layer's scalar factor is folded
+// into its inverse phase table, the X on every qubit of the cotangent form is
+// a relabelling (index x holds element x ^ (2^n - 1)), and the inner products
+// taken between butterflies carry the factor the butterflies left out.
+// Tiles as in the forward sweeps, TB = 13.
 // ---------------------------------------------------------------------------
 
 enum AdjointKind {
@@ -140,13 +144,18 @@ struct AdjointArgs {
     float2* lam;
     float2* psi;
     const void* cost;
-    const float2* lut;     // exp(+i gamma c), c = 0 .. lut_len - 1
+    const float2* lut;     // F exp(+i gamma c), c = 0 .. lut_len - 1, F the layer's mixer factor
     double* partials;      // 3 per tile: Im<lam|X|psi> (pre group), Im<lam|C|psi>, Im<lam|X|psi> (post group)
     int32_t n, nw, lut_len;
     uint64_t tile_bits, wmask;
     uint8_t pos[16];
     uint32_t pre_mask, post_mask;
-    float pre_c, pre_s, post_c, post_s;  // butterfly a' = c a - i s b
+    // Butterfly own' = own - i t partner. Before each butterfly the pair term
+    // is added with weight w, then w *= r (r = |one qubit's factor|^2): w
+    // starts at r^k for k qubits of the layer mixed by earlier sweeps.
+    float pre_t, pre_r, pre_w, post_t, post_r, post_w;
+    uint64_t cost_flip;  // 0 or 2^n - 1: the phase of element x reads cost[x ^ cost_flip]
+    int32_t psi_flip;    // psi of element x sits at x ^ (2^n - 1) (relabelled against lam)
     int32_t store_psi;
 };
 

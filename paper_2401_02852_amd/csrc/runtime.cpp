@@ -15,11 +15,7 @@ namespace qnae_host {
 
 namespace {
 thread_local std::string g_err;
-
-struct Layer {
-    MixForm form;
-    std::complex<double> scale;  // scalar factor of the whole layer's mixer
-};
+}  // namespace
 
 // R(beta) = cos(beta) I - i sin(beta) X for every qubit. Device butterflies
 // apply (I - i t X), optionally followed by X; the product of the n scalar
@@ -38,8 +34,6 @@ Layer mixer_form(double beta, int n) {
     }
     return L;
 }
-
-}  // namespace
 
 // Phase tables: table l holds prev_scale * exp(-i gamma_l c) for c = 0..m,
 // where prev_scale is the previous layer's mixer factor (2^{-n/2}, the

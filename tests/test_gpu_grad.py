@@ -121,6 +121,27 @@ def test_grad_three_groups_n23(q):
     torch.cuda.empty_cache()
 
 
+def test_grad_extreme_mixer_angles(q):
+    """Mixer angles at and near +-pi/2 (cotangent forms, t = 0 and small t),
+    next to pi/4 (|t| about 1) and past pi/2, checkpoints every 1, 2 and 4
+    layers, so reverse segments start with lam relabelled against the
+    restored psi; against the oracle's adjoint."""
+    n, p = 20, 6
+    m = inst.clause_count(n, 2.1)
+    cl = inst.instance(n, 3, m, 13)  # 6 solutions
+    g = np.array([0.4, 0.9, 0.2, 1.3, 0.6, 0.8])
+    b = np.array([np.pi / 2, -np.pi / 4, 1.5707, np.pi / 4 + 1e-3, -1.56, 2.9])
+    c = q.build_cost_diagonal(cl, n)
+    cost = oracle.cost(cl, n)
+    assert int((cost == 0).sum()) == 6
+    w = (0.6, 0.3)
+    rg, rb, ro = oracle.qaoa_grad(cost, n, g, b, *w)
+    for every in (1, 2, 4):
+        dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=every)
+        check(dg, db, rg, rb, w)
+        check_readout(r, ro)
+
+
 def test_grad_workload_n22_p12(q, golden):
     """The differentiation workload: n = 22, m = 46, p = 12 from the linear
     ramp (beta negated), checkpoints every 4 layers, against the oracle's
