@@ -16,6 +16,8 @@
 // them is applied to both states, so the X_j terms of a qubit group are summed
 // inside the sweep that inverts that group. The inverse phase of the layer is
 // fused in the same way as the forward phase.
+#include <type_traits>
+
 #include "tile.h"
 
 namespace qnae {
@@ -79,7 +81,10 @@ __device__ __forceinline__ void xpose2(float2* lds, float2 (&l)[32], float2 (&p)
 // unhidden at one (the inverse-mixer-only kinds 5% and the boundary kind,
 // after the fence before its inverse mixing, another 5% per gradient at
 // n = 22).
-template <typename CT, int KIND>
+// WEIGH (first sweep of the reverse pass, natural order): lam is not read but
+// formed as W psi from the loaded psi and cost, which saves a pass over both
+// states.
+template <typename CT, int KIND, bool WEIGH = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void adjoint_kernel(
     const AdjointArgs a) {
     constexpr int TB = kAdjointTileBits;
@@ -168,12 +173,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
             const uint64_t d = scat(L::s0(2 * jj));
-            const float4 ql = *(const float4*)(a.lam + o0 + d);
             const float4 qp = *(const float4*)(pf ? pb - d : pb + d);
-            l[2 * jj] = make_float2(ql.x, ql.y);
-            l[2 * jj + 1] = make_float2(ql.z, ql.w);
             p[2 * jj] = pf ? make_float2(qp.z, qp.w) : make_float2(qp.x, qp.y);
             p[2 * jj + 1] = pf ? make_float2(qp.x, qp.y) : make_float2(qp.z, qp.w);
+            if (WEIGH) {
+                // lam = W psi: the pair's two costs are adjacent (tile bit 0)
+                using PT = typename std::conditional<sizeof(CT) == 1, uint16_t, uint32_t>::type;
+                constexpr uint32_t CB = 8 * sizeof(CT);
+                const PT cc = *(const PT*)((const CT*)a.cost + o0 + d);
+                const uint32_t c0 = (uint32_t)cc & ((1u << CB) - 1u), c1 = (uint32_t)cc >> CB;
+                const float w0 = fmaf(a.w_energy, (float)c0, c0 == 0u ? a.w_psucc : 0.f);
+                const float w1 = fmaf(a.w_energy, (float)c1, c1 == 0u ? a.w_psucc : 0.f);
+                l[2 * jj] = make_float2(w0 * p[2 * jj].x, w0 * p[2 * jj].y);
+                l[2 * jj + 1] = make_float2(w1 * p[2 * jj + 1].x, w1 * p[2 * jj + 1].y);
+            } else {
+                const float4 ql = *(const float4*)(a.lam + o0 + d);
+                l[2 * jj] = make_float2(ql.x, ql.y);
+                l[2 * jj + 1] = make_float2(ql.z, ql.w);
+            }
         }
     }
     float acc_pre = 0.f, acc_g = 0.f, acc_post = 0.f;
@@ -269,17 +286,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         for (int q = 0; q < (1 << WB); ++q) sum += red[threadIdx.x][q];
         a.partials[3 * (size_t)t + threadIdx.x] = sum;
     }
-}
-
-template <typename CT>
-__global__ __launch_bounds__(256) void weight_kernel(const CT* cost, const float2* psi, float2* lam, uint64_t N,
-                                                     float w_psucc, float w_energy) {
-    const uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (x >= N) return;
-    const uint32_t c = cost[x];
-    const float w = w_energy * (float)c + (c == 0u ? w_psucc : 0.f);
-    const float2 v = psi[x];
-    lam[x] = make_float2(w * v.x, w * v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,8 +428,14 @@ __global__ __launch_bounds__(kResidentGradThreads) void resident_grad_batch_kern
 
 }  // namespace
 
-hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s) {
+hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s, bool weigh) {
     const dim3 grid(1u << a.nw), block(256);
+    if (weigh) {
+        if (kind != AK_MIDDLE || a.psi_flip || a.cost_flip) return hipErrorInvalidValue;
+        if (dtype == 1) hipLaunchKernelGGL((adjoint_kernel<uint8_t, AK_MIDDLE, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((adjoint_kernel<uint16_t, AK_MIDDLE, true>), grid, block, 0, s, a);
+        return hipGetLastError();
+    }
     if (dtype == 1) {
         switch (kind) {
             case AK_MIDDLE: hipLaunchKernelGGL((adjoint_kernel<uint8_t, AK_MIDDLE>), grid, block, 0, s, a); break;
@@ -439,19 +451,6 @@ hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t
             default: return hipErrorInvalidValue;
         }
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_weight(int dtype, const void* cost, const float2* psi, float2* lam, int n, double w_psucc,
-                         double w_energy, hipStream_t s) {
-    const uint64_t N = 1ull << n;
-    const dim3 grid((uint32_t)((N + 255) / 256)), block(256);
-    if (dtype == 1)
-        hipLaunchKernelGGL(weight_kernel<uint8_t>, grid, block, 0, s, (const uint8_t*)cost, psi, lam, N,
-                           (float)w_psucc, (float)w_energy);
-    else
-        hipLaunchKernelGGL(weight_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)cost, psi, lam, N,
-                           (float)w_psucc, (float)w_energy);
     return hipGetLastError();
 }
 

@@ -4,9 +4,9 @@
 // n <= 13: one workgroup does the forward pass, the readout and the reverse
 // pass with both states in LDS. Larger n: the forward pass runs as sweep
 // segments of `every` layers that each keep their final state (checkpoints);
-// lam = W psi_p; then for each segment from the last, reverse sweeps take lam
-// and that segment's checkpoint (psi, uncomputed in place) through the inverse
-// layers, summing the inner products per tile.
+// then for each segment from the last, reverse sweeps take lam (the first one
+// forms lam = W psi_p) and that segment's checkpoint (psi, uncomputed in
+// place) through the inverse layers, summing the inner products per tile.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -129,6 +129,9 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
         if (L > 0) S.aops = make_adjoint_plan((int)groups.size(), L);
         total_aops += (int)S.aops.size();
     }
+    // The reverse pass opens with a sweep that mixes one group and forms lam.
+    if (!segs[nseg - 1].aops.empty() && segs[nseg - 1].aops[0].kind != qnae::AK_MIDDLE)
+        return fail(QNAE_EINVAL, "n=%d: %zu qubit groups, the reverse pass needs at least two", n, groups.size());
     Blob B;
     const size_t flut_at = B.take(sizeof(float2) * ftab.size());
     const size_t blut_at = B.take(sizeof(float2) * btab.size());
@@ -174,9 +177,9 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
         }
         if (S.plan.p > 0 && S.plan.flips_before[S.plan.p]) HIP_TRY(qnae::launch_reverse(psi, N, s));
     }
-    // lam = W psi_p
-    float2* psi_p = ck + N * (size_t)(nseg - 1);
-    HIP_TRY(qnae::launch_weight(cost_dtype, cost_dev, psi_p, lam, n, w_psucc, w_energy, s));
+    // lam = W psi_p is formed by the first reverse sweep, which mixes one
+    // group only (a layer spans at least two groups here, n > TB), from the
+    // psi_p and cost it loads
     // reverse segments, last first. `relabel`: lam's index x holds element
     // x ^ (2^n - 1) (an odd number of cotangent forms so far); psi restarts
     // from a checkpoint in natural order at each segment, so within a segment
@@ -240,8 +243,15 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
             }
             a.psi_flip = psi_flip;
             a.store_psi = op.kind == qnae::AK_END ? 0 : 1;
-            const double bytes = std::ldexp(32.0 - (a.store_psi ? 0.0 : 8.0) + (op.phase_layer >= 0 ? (cost_dtype == QNAE_U8 ? 1.0 : 2.0) : 0.0), n);
-            HIP_TRY(timed(ctx, K_ADJOINT, bytes, s, [&] { return qnae::launch_adjoint(cost_dtype, op.kind, a, s); }));
+            const bool weigh = q == 0;
+            a.w_psucc = (float)w_psucc;
+            a.w_energy = (float)w_energy;
+            const double cost_bytes = cost_dtype == QNAE_U8 ? 1.0 : 2.0;
+            const double bytes = std::ldexp(32.0 - (a.store_psi ? 0.0 : 8.0) - (weigh ? 8.0 : 0.0) +
+                                                (op.phase_layer >= 0 || weigh ? cost_bytes : 0.0),
+                                            n);
+            HIP_TRY(timed(ctx, K_ADJOINT, bytes, s,
+                          [&] { return qnae::launch_adjoint(cost_dtype, op.kind, a, s, weigh); }));
             order.emplace_back(j, &op);
             gamma_weight.push_back(gw);
             ++q;

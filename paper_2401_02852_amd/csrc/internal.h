@@ -157,14 +157,14 @@ struct AdjointArgs {
     uint64_t cost_flip;  // 0 or 2^n - 1: the phase of element x reads cost[x ^ cost_flip]
     int32_t psi_flip;    // psi of element x sits at x ^ (2^n - 1) (relabelled against lam)
     int32_t store_psi;
+    float w_psucc, w_energy;  // weigh: lam = (w_psucc [C = 0] + w_energy C) psi instead of a load
 };
 
 constexpr int kAdjointTileBits = 13;
-hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s);
+// weigh: the middle kind forms lam from psi (first sweep of the reverse pass,
+// no relabelling) instead of loading it.
+hipError_t launch_adjoint(int dtype, int kind, const AdjointArgs& a, hipStream_t s, bool weigh = false);
 
-// lam(x) = (w_psucc [C(x) = 0] + w_energy C(x)) psi(x), x in [0, 2^n).
-hipError_t launch_weight(int dtype, const void* cost, const float2* psi, float2* lam, int n, double w_psucc,
-                         double w_energy, hipStream_t s);
 
 // Whole gradient for n <= 13 in one workgroup (lam and psi resident in LDS):
 // forward with exact butterflies (checkpoints of psi every `every` layers in
