@@ -2,11 +2,12 @@
 // adjoint pass (include/qnae.h). See adjoint.hip for the formulas.
 //
 // n <= 13: one workgroup does the forward pass, the readout and the reverse
-// pass with both states in LDS. Larger n: the forward pass runs as sweep
-// segments of `every` layers that each keep their final state (checkpoints);
-// then for each segment from the last, reverse sweeps take lam (the first one
-// forms lam = W psi_p) and that segment's checkpoint (psi, uncomputed in
-// place) through the inverse layers, summing the inner products per tile.
+// pass with both states in LDS. Larger n: the forward pass runs as one sweep
+// plan that also stores the state after every `every` layers (checkpoints:
+// the ends of segments); then for each segment from the last, reverse sweeps
+// take lam (the first one forms lam = W psi_p) and that segment's checkpoint
+// (psi, uncomputed in place) through the inverse layers, summing the inner
+// products per tile.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -91,35 +92,45 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     float2* ck = (float2*)ctx->g_states.ptr;
     float2* lam = ck + N * (size_t)nseg;
 
-    // Host tables for every forward segment and every reverse segment.
-    struct Seg {
-        int a, b;
-        size_t flut_at, blut_at;
-        SweepPlan plan;
-        std::vector<AdjOp> aops;
-        std::complex<double> final_scale;
-        std::vector<Layer> inv;  // inverse mixer of b-layer i: exp(+i beta X) per qubit
-    };
-    std::vector<Seg> segs(nseg);
+    // The forward pass is one plan over all p layers, in place in the last
+    // checkpoint's buffer; the boundary sweep that completes the last layer
+    // of segment j < nseg - 1 also stores checkpoint j.
     const int T = p > 0 ? p : 1;
     std::vector<float2> ftab((size_t)T * lut_len), btab((size_t)T * lut_len);
     std::vector<MixForm> forms(T);
+    const std::complex<double> final_scale = build_tables(n, m, gammas, betas, p, ftab.data(), forms.data());
+    SweepPlan F;
+    plan_sweeps(F, n, m, p, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, true, forms.data(), final_scale);
+    std::vector<int> ckpt_of(F.ops.size(), -1);  // checkpoint stored by each forward sweep
+    int stored = 0;
+    for (size_t q = 0; q < F.ops.size(); ++q) {
+        const Op& op = F.ops[q];
+        if (op.kind != qnae::SK_BOUNDARY || op.pre_layer < 0) continue;
+        const int done_layers = op.lut_layer;  // its pre mixing completes layer lut_layer - 1
+        if (done_layers % every == 0 && done_layers < p) {
+            ckpt_of[q] = done_layers / every - 1;
+            ++stored;
+        }
+    }
+    if (stored != nseg - 1)
+        return fail(QNAE_EINVAL, "n=%d: %zu qubit groups, the forward pass needs at least two", n, groups.size());
+
+    // Reverse segments: b-layer i of segment j is forward layer b - 1 - i.
+    struct Seg {
+        int a, b;
+        size_t blut_at;
+        std::vector<AdjOp> aops;
+        std::vector<Layer> inv;  // inverse mixer of b-layer i: exp(+i beta X) per qubit
+    };
+    std::vector<Seg> segs(nseg);
     int total_aops = 0;
     for (int j = 0; j < nseg; ++j) {
         Seg& S = segs[j];
         S.a = j * every;
         S.b = p > 0 ? std::min(p, S.a + every) : 0;
         const int L = S.b - S.a;
-        S.flut_at = (size_t)S.a * lut_len;
-        const std::complex<double> first = j == 0 ? std::complex<double>(std::pow(2.0, -0.5 * n), 0.0)
-                                                  : std::complex<double>(1.0, 0.0);
-        S.final_scale = build_tables_from(n, m, gammas + S.a, betas + S.a, L, ftab.data() + S.flut_at,
-                                          forms.data() + S.a, first);
-        plan_sweeps(S.plan, n, m, L, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, true, forms.data() + S.a,
-                    S.final_scale, j > 0);
-        // reverse tables: b-layer i is forward layer b - 1 - i; its inverse
-        // phase exp(+i gamma c) times the scalar factor its inverse mixer's
-        // butterflies left out
+        // the inverse phase exp(+i gamma c) times the scalar factor the
+        // inverse mixer's butterflies left out
         S.blut_at = (size_t)S.a * lut_len;
         S.inv.resize(L);
         for (int i = 0; i < L; ++i) {
@@ -162,21 +173,25 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     const float2* d_flut = (const float2*)(d + flut_at);
     const float2* d_blut = (const float2*)(d + blut_at);
 
-    // forward segments
+    // forward pass
     double* fwd_parts = parts + 3 * (size_t)tiles * total_aops;
-    for (int j = 0; j < nseg; ++j) {
-        const Seg& S = segs[j];
-        float2* psi = ck + N * (size_t)j;
-        for (size_t q = 0; q < S.plan.ops.size(); ++q) {
-            const Op& op = S.plan.ops[q];
-            SweepArgs a;
-            sweep_args(S.plan, op, psi, cost_dev, d_flut + S.flut_at, fwd_parts, &a);
-            if (q == 0 && j > 0) a.psi_in = ck + N * (size_t)(j - 1);
-            HIP_TRY(timed(ctx, op_profile_kind(op), op_bytes(S.plan, op), s,
+    float2* const run = ck + N * (size_t)(nseg - 1);
+    for (size_t q = 0; q < F.ops.size(); ++q) {
+        const Op& op = F.ops[q];
+        SweepArgs a;
+        sweep_args(F, op, run, cost_dev, d_flut, fwd_parts, &a);
+        if (ckpt_of[q] < 0) {
+            HIP_TRY(timed(ctx, op_profile_kind(op), op_bytes(F, op), s,
                           [&] { return qnae::launch_sweep(TB, cost_dtype, op.kind, a, s); }));
+            continue;
         }
-        if (S.plan.p > 0 && S.plan.flips_before[S.plan.p]) HIP_TRY(qnae::launch_reverse(psi, N, s));
+        const std::complex<double> f = mixer_form(betas[op.lut_layer - 1], n).scale;
+        a.ckpt = ck + N * (size_t)ckpt_of[q];
+        a.ckpt_scale = make_float2((float)f.real(), (float)f.imag());
+        HIP_TRY(timed(ctx, op_profile_kind(op), op_bytes(F, op) + std::ldexp(8.0, n), s,
+                      [&] { return qnae::launch_sweep_ckpt(cost_dtype, a, s); }));
     }
+    if (p > 0 && F.flips_before[p]) HIP_TRY(qnae::launch_reverse(run, N, s));
     // lam = W psi_p is formed by the first reverse sweep, which mixes one
     // group only (a layer spans at least two groups here, n > TB), from the
     // psi_p and cost it loads
@@ -271,7 +286,7 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
         if (op.phase_layer >= 0) dgammas[S.b - 1 - op.phase_layer] += 2.0 * gamma_weight[k] * r[3 * k + 1];
         if (op.post_layer >= 0) dbetas[S.b - 1 - op.post_layer] += 2.0 * r[3 * k + 2];
     }
-    const double sc = std::norm(segs[nseg - 1].final_scale);
+    const double sc = std::norm(final_scale);
     out->p_success = r[3 * total_aops] * sc;
     out->expected_cost = r[3 * total_aops + 1] * sc;
     out->norm = r[3 * total_aops + 2] * sc;

@@ -96,9 +96,18 @@ struct SweepArgs {
     int32_t half;
     int32_t vbit;
     uint64_t mir;
+    // Checkpointing boundary sweep (gradient forward pass): the state right
+    // after the pre mixing, which completes a layer, times ckpt_scale (that
+    // layer's mixer factor), in natural order (element x at x ^ (2^n - 1)
+    // when cflip) to ckpt.
+    float2* ckpt;
+    float2 ckpt_scale;
 };
 
 hipError_t launch_sweep(int tb, int dtype, int kind, const SweepArgs& a, hipStream_t s);
+// A boundary sweep that also stores a checkpoint (a.ckpt), 13-bit tiles,
+// full state.
+hipError_t launch_sweep_ckpt(int dtype, const SweepArgs& a, hipStream_t s);
 
 // One sweep step over `count` states at once. Instance i owns blocks
 // first[i] .. first[i+1]-1 (first has count+1 entries, first[count] =

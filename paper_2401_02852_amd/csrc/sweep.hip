@@ -84,7 +84,7 @@ __device__ __forceinline__ void move(float* lds, float2 (&v)[32], uint32_t lane,
 
 // One workgroup's work on tile t of one sweep. Readout kinds write the three
 // block sums to partial[0..2].
-template <int TB, typename CT, int KIND, bool HALF>
+template <int TB, typename CT, int KIND, bool HALF, bool CKPT = false>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, double* partial) {
     constexpr int WB = TB - 11;
     constexpr int NT = 64 << WB;
@@ -292,6 +292,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         }
         mix32<UNCOND>(v, L::sm2(m), tt);
     }
+    if (CKPT) {
+        // The tile's thread part t and slot part s have disjoint bits, so
+        // (t | s) ^ (2^n - 1) = (t ^ (2^n - 1)) - s.
+        const uint64_t all = (1ull << a.n) - 1ull;
+        const uint64_t o2 = base + scat(L::t2(lane, wave));
+        const float2 f = a.ckpt_scale;
+        if (a.cflip) {
+            float2* const c2 = a.ckpt + (o2 ^ all);
+#pragma unroll
+            for (int j = 0; j < 32; ++j) st_state(c2 - scat(L::s2(j)), cmul(v[j], f));
+        } else {
+            float2* const c2 = a.ckpt + o2;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) st_state(c2 + scat(L::s2(j)), cmul(v[j], f));
+        }
+    }
     if (PHASE) {
 #pragma unroll
         for (int j = 0; j < 32; ++j) v[j] = cmul(v[j], lut(cval(j)));
@@ -374,10 +390,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
 }
 
 // One sweep over one state: block b handles tile b.
-template <int TB, typename CT, int KIND, bool HALF = false>
+template <int TB, typename CT, int KIND, bool HALF = false, bool CKPT = false>
 __global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(KIND, HALF)))) void sweep_kernel(
     const SweepArgs a) {
-    sweep_tile<TB, CT, KIND, HALF>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
+    sweep_tile<TB, CT, KIND, HALF, CKPT>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
 }
 
 // Instance of work item b in a ragged batch: the largest i with first[i] <= b.
@@ -628,6 +644,17 @@ hipError_t launch_sweep_batch(int tb, int dtype, int kind, const SweepArgs* args
         case 14: return launch_batch_tb<14>(dtype, kind, args, first, count, blocks, s, half);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_sweep_ckpt(int dtype, const SweepArgs& a, hipStream_t s) {
+    constexpr int TB = kAdjointTileBits;
+    if (a.half || !a.ckpt || a.nw < 0) return hipErrorInvalidValue;
+    const dim3 grid(1u << a.nw), block(64 << (TB - 11));
+    if (dtype == 1)
+        hipLaunchKernelGGL((sweep_kernel<TB, uint8_t, SK_BOUNDARY, false, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<TB, uint16_t, SK_BOUNDARY, false, true>), grid, block, 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_reverse(float2* psi, uint64_t N, hipStream_t s) {
