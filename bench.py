@@ -136,6 +136,36 @@ def measured_traffic(stats):
     return tot / launches if launches else None
 
 
+def stream_ceilings(torch, gib=4, reps=5):
+    """What the runtime's and torch's own streaming kernels reach on this
+    device, as context for the roofline fraction (not an upper bound): a
+    device-to-device copy (read + write, the sweeps' pattern), a fill (write
+    only) and a sum (read only), over `gib` GiB, best of `reps`."""
+    count = gib << 28  # float32 elements
+    src = torch.ones(count, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+
+    def best(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return nbytes / (min(ms) * 1e-3) / 1e9
+
+    size = count * 4
+    out = {"bytes": size, "copy_GBps": best(lambda: dst.copy_(src), 2 * size),
+           "fill_GBps": best(lambda: dst.fill_(1.0), size), "read_GBps": best(lambda: src.sum(), size)}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def scale_bench(q, ctx, names=("nae3_n24_p10", "nae3_n28_p10"), steps=5):
     """The headline step (cost build + p = 10 ramp layers + readout) at the
     smaller sizes of the same family: amp-layer updates/s and the sweeps'
@@ -402,11 +432,12 @@ def latency_bench(q, ctx, reps=200):
             "run_p50_us": run50, "run_p99_us": run99, "build_and_run_p50_us": both50, "build_and_run_p99_us": both99}
 
 
-def grad_bench(q, ctx, reps=10, adam_steps=200):
+def grad_bench(q, ctx, reps=20, adam_steps=200):
     """Differentiation workload: n = 22, m = 46, p = 12 from the linear ramp
     (beta negated), checkpoints every 4 layers. Time of one adjoint gradient
     against one forward run, then Adam (lr 0.01) maximising p_succ through
     QAOAFunction; parity of the gradient is the test suite's job."""
+    import numpy as np
     import torch
     rec, cl, g0, b0 = load_workload("nae3_n22_p12")
     n, m, p = rec["n"], rec["m"], rec["p"]
@@ -414,14 +445,16 @@ def grad_bench(q, ctx, reps=10, adam_steps=200):
     cost = q.build_cost_diagonal(cl, n, ctx=ctx)
     torch.cuda.synchronize()
 
-    def timed(fn):
+    def timed(fn):  # median of single synchronous calls
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ts = []
         for _ in range(reps):
+            t0 = time.perf_counter()
             fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
 
     t_fwd = timed(lambda: q.qaoa_run(cost, n, m, g0, b0, ctx=ctx))
     t_grad = timed(lambda: q.qaoa_grad(cost, n, m, g0, b0, w_psucc=1.0, w_energy=0.0, checkpoint_every=4, ctx=ctx))
@@ -543,13 +576,14 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the n=30 step (no other legs, no CPU baseline, no autotuning): for profiling")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.headline_only:
         for leg in ("cpu_baseline", "scale", "latency", "batched", "serving", "grad", "sampling", "z2", "pretrain",
-                    "autotune"):
+                    "autotune", "ceilings"):
             setattr(args, "no_" + leg, True)
     if args.calibrate_copy:
         import torch
@@ -651,6 +685,10 @@ def main():
         out["sampling"] = sampling_bench(q, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(q, ctx, count=args.serving_requests)
+    if not args.no_ceilings:  # last: its 8 GiB of torch buffers are freed again
+        ceil = stream_ceilings(torch)
+        ceil["sweeps_over_copy"] = achieved / ceil["copy_GBps"] if ceil["copy_GBps"] > 0 else None
+        out["roofline"]["stream_ceilings"] = ceil
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)

@@ -43,14 +43,17 @@ def kernel_source_hash() -> str:
 
 def short_name(name: str) -> str:
     name = re.sub(r"qnae::\(anonymous namespace\)::", "", name)
-    m = re.match(r"void sweep_kernel<(\d+), ([a-z ]+), (\d)(?:, (true|false))?>", name)
+    m = re.match(r"void sweep_kernel<(\d+), ([a-z ]+), (\d)(?:, (true|false))?(?:, (true|false))?>", name)
     if m:
         half = ",half" if m.group(4) == "true" else ""
-        return f"sweep_kernel<TB={m.group(1)},{m.group(2).replace('unsigned ', 'u')}{half}> {KIND_NAMES[m.group(3)]}"
-    m = re.match(r"void adjoint_kernel<([a-z ]+), (\d)>", name)
+        ckpt = "_ckpt" if m.group(5) == "true" else ""
+        return (f"sweep_kernel<TB={m.group(1)},{m.group(2).replace('unsigned ', 'u')}{half}> "
+                f"{KIND_NAMES[m.group(3)]}{ckpt}")
+    m = re.match(r"void adjoint_kernel<([a-z ]+), (\d)(?:, (true|false))?>", name)
     if m:
         kind = {"0": "middle", "1": "boundary", "2": "end"}[m.group(2)]
-        return f"adjoint_kernel<{m.group(1).replace('unsigned ', 'u')}> adjoint_{kind}"
+        weigh = "_weigh" if m.group(3) == "true" else ""
+        return f"adjoint_kernel<{m.group(1).replace('unsigned ', 'u')}> adjoint_{kind}{weigh}"
     return name.split("(")[0].replace("void ", "")
 
 
