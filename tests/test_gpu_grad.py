@@ -142,6 +142,25 @@ def test_grad_extreme_mixer_angles(q):
         check_readout(r, ro)
 
 
+@pytest.mark.parametrize("n", [12, 17])
+def test_grad_u16_costs(q, n):
+    """m = 300 clauses: 16-bit cost values through the weighing, checkpointing,
+    phase-carrying and resident kinds; mixer angles on both butterfly forms;
+    against the oracle's adjoint."""
+    rng = np.random.default_rng(100 + n)
+    m, p = 300, 5
+    cl = inst.instance(n, 3, m, 3)
+    c = q.build_cost_diagonal(cl, n)
+    assert str(c.dtype) == "torch.uint16"
+    g, b = rng.uniform(0, 0.2, p), rng.uniform(0, np.pi, p)
+    cost = oracle.cost(cl, n)
+    for w in [(1.0, 0.0), (0.0, 1.0)]:
+        dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=2)
+        rg, rb, ro = oracle.qaoa_grad(cost, n, g, b, *w)
+        check(dg, db, rg, rb, w)
+        assert abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1], (r, ro)
+
+
 def test_grad_workload_n22_p12(q, golden):
     """The differentiation workload: n = 22, m = 46, p = 12 from the linear
     ramp (beta negated), checkpoints every 4 layers, against the oracle's
