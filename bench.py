@@ -28,10 +28,21 @@ HBM_PEAK_GBS = 8000.0
 
 
 def load_workload(name):
+    """Instance and ramp angles of a named workload: m and seed from the
+    stored oracle runs, or, for sizes beyond those, from the stored
+    whole-diagonal digests."""
     from workloads import instances as inst
     with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
-        rec = json.load(f)[name]
-    n, k, r, p, _ = inst.SINGLE_WORKLOADS[name]
+        golden = json.load(f)
+    if name in golden:
+        rec = golden[name]
+        n, k, r, p, _ = inst.SINGLE_WORKLOADS[name]
+    else:  # "<digest workload>_p<layers>"
+        base, layers = name.rsplit("_p", 1)
+        with open(os.path.join(ROOT, "tests", "golden", "cost_digests.json")) as f:
+            d = json.load(f)[base]
+        n, k, p = d["n"], d["k"], int(layers)
+        rec = {"n": n, "k": k, "m": d["m"], "seed": d["seed"], "p": p}
     cl = inst.instance(n, k, rec["m"], rec["seed"])
     g, b = inst.ramp_angles(p)
     return rec, cl, g, b
@@ -166,16 +177,23 @@ def stream_ceilings(torch, gib=4, reps=5):
     return out
 
 
-def scale_bench(q, ctx, names=("nae3_n24_p10", "nae3_n28_p10"), steps=5):
-    """The headline step (cost build + p = 10 ramp layers + readout) at the
-    smaller sizes of the same family: amp-layer updates/s and the sweeps'
-    share of HBM peak. At n = 24 the 128 MiB state and 16 MiB cost fit the
-    256 MiB last-level cache, so its share of HBM peak is cache-inflated."""
+def scale_bench(q, ctx, names=("nae3_n24_p10", "nae3_n28_p10", "nae3_n33_p10"), steps=5, autotune=True):
+    """The headline step (cost build + p = 10 ramp layers + readout) at other
+    sizes of the same family: amp-layer updates/s and the sweeps' share of HBM
+    peak. At n = 24 the 128 MiB state and 16 MiB cost fit the 256 MiB
+    last-level cache, so its share of HBM peak is cache-inflated. n = 33
+    holds a 64 GiB state and an 8 GiB cost (the instance whose whole cost
+    diagonal the tests compare by digest; unsatisfiable, so p_succ is 0) on a
+    context of its own, closed afterwards."""
     import torch
     out = {}
+    main_ctx = ctx
     for name in names:
         rec, cl, g, b = load_workload(name)
         n, m, p = rec["n"], rec["m"], rec["p"]
+        ctx = q.Context(0) if n > 32 else main_ctx
+        shape = ctx.autotune(n, "u8", reps=2) if autotune else {}
+        shape = shape or ctx.get_tune(n, "u8")
         cost = torch.empty(1 << n, dtype=torch.uint8, device="cuda")
         q.build_cost_diagonal(cl, n, out=cost, ctx=ctx)
         q.qaoa_run(cost, n, m, g, b, ctx=ctx)
@@ -193,8 +211,13 @@ def scale_bench(q, ctx, names=("nae3_n24_p10", "nae3_n28_p10"), steps=5):
         gbs = sum(v[2] for v in sw) / (sum(v[1] for v in sw) * 1e-3) / 1e9
         out[name] = {"n": n, "m": m, "p": p, "amp_layer_updates_per_s": (2 ** n) * p / dt,
                      "ms_per_step": dt * 1e3, "sweep_GBps": gbs, "sweep_frac_of_peak": gbs / HBM_PEAK_GBS,
-                     "cache_resident": n <= 24, "p_success": res.p_success, "expected_cost": res.expected_cost}
+                     "cache_resident": n <= 24, "p_success": res.p_success, "expected_cost": res.expected_cost,
+                     "state_GiB": (8 << n) / 2 ** 30,
+                     "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit")}}
         del cost
+        if ctx is not main_ctx:
+            ctx.close()
+            torch.cuda.empty_cache()
     return out
 
 
@@ -670,7 +693,7 @@ def main():
         "parity": parity_vs_oracle(q, ctx, rec, cost, n, m, p, g, b, res),
     }
     if not args.no_scale:
-        out["scale"] = scale_bench(q, ctx)
+        out["scale"] = scale_bench(q, ctx, autotune=not args.no_autotune)
     if not args.no_latency:
         out["latency"] = latency_bench(q, ctx)
     if not args.no_batched:

@@ -64,7 +64,11 @@ struct HalfAddr {
 // plane transposes leave LDS room for 4 workgroups per CU; capping its
 // registers at 3 waves per SIMD keeps most of that (the other kinds fit
 // their LDS-bound occupancy without a cap).
-constexpr int sweep_waves(int kind, bool half) { return kind == SK_FINAL && !half ? 3 : 1; }
+constexpr int sweep_waves(int tb, int kind, bool half) {
+    if (half) return 1;
+    if (tb == 14) return kind == SK_BOUNDARY || kind == SK_FINAL ? 4 : 1;
+    return kind == SK_FINAL ? 3 : 1;
+}
 
 // The tile from layout A to layout B through LDS: whole float2 elements, or
 // (PLANES) one component plane after the other in half the LDS. CROSS: the
@@ -97,7 +101,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
     // readout) gain from more resident workgroups: their transposes go
     // through LDS one component plane at a time.
     // (Half-state final sweeps need too many registers for that to pay.)
-    constexpr bool PLANES = KIND == SK_FIRST || (KIND == SK_FINAL && !HALF);
+    constexpr bool PLANES = KIND == SK_FIRST || (KIND == SK_FINAL && !HALF) ||
+                            (TB == 14 && !HALF && (KIND == SK_MIDDLE || KIND == SK_BOUNDARY));
     // Straight-line butterflies in the kinds that mix the tile once and hold
     // no readout state: measured faster there (the boundary kind measured
     // slower, and the final kind needs the registers).
@@ -391,7 +396,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
 
 // One sweep over one state: block b handles tile b.
 template <int TB, typename CT, int KIND, bool HALF = false, bool CKPT = false>
-__global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(KIND, HALF)))) void sweep_kernel(
+__global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(TB, KIND, HALF)))) void sweep_kernel(
     const SweepArgs a) {
     sweep_tile<TB, CT, KIND, HALF, CKPT>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
 }
@@ -410,7 +415,7 @@ __device__ __forceinline__ int batch_item(const uint32_t* first, int count, uint
 // One sweep step over many states at once (ragged): instance i owns blocks
 // first[i] .. first[i+1]-1, one per tile, with its own arguments.
 template <int TB, typename CT, int KIND, bool HALF>
-__global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(KIND, HALF)))) void sweep_batch_kernel(const SweepArgs* args, const uint32_t* first,
+__global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(TB, KIND, HALF)))) void sweep_batch_kernel(const SweepArgs* args, const uint32_t* first,
                                                                       int count) {
     const int i = batch_item(first, count, blockIdx.x);
     const SweepArgs a = args[i];

@@ -285,20 +285,30 @@ def test_n30_workload_every_tile_shape(q, golden):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n", [24, 30])
+@pytest.mark.parametrize("n", [24, 30, 33])
 def test_ring_closed_form_at_scale(q, n):
     """k = 2 ring of all-positive clauses at p = 1:
-    E[C] = n/2 (1 + sin(4 beta) sin(2 gamma) / 2) (graph closed form)."""
+    E[C] = n/2 (1 + sin(4 beta) sin(2 gamma) / 2) (graph closed form).
+    n = 33: 2^33 amplitudes (64 GiB state, 8 GiB cost) through 64-bit
+    indices in every sweep kind, on a context of its own that is closed
+    afterwards."""
     import torch
-    cl = np.array([[i + 1, (i + 1) % n + 1] for i in range(n)], dtype=np.int32)
-    c = gpu_cost(q, cl, n)
-    for g, b in [(0.37, 0.21), (-1.1, 0.6), (2.0, 1.2)]:
-        r = q.qaoa_run(c, n, n, [g], [b])
-        ref = n / 2 * (1 + 0.5 * math.sin(4 * b) * math.sin(2 * g))
-        assert abs(r.expected_cost - ref) <= E_REL * ref
-        assert abs(r.norm - 1) < 1e-5
-    del c
-    torch.cuda.empty_cache()
+    ctx = q.Context(0) if n > 32 else None
+    try:
+        cl = np.array([[i + 1, (i + 1) % n + 1] for i in range(n)], dtype=np.int32)
+        c = q.build_cost_diagonal(cl, n, ctx=ctx)
+        for g, b in [(0.37, 0.21), (-1.1, 0.6), (2.0, 1.2)]:
+            r = q.qaoa_run(c, n, n, [g], [b], ctx=ctx)
+            ref = n / 2 * (1 + 0.5 * math.sin(4 * b) * math.sin(2 * g))
+            assert abs(r.expected_cost - ref) <= E_REL * ref
+            assert abs(r.norm - 1) < 1e-5
+            if n % 2:  # odd ring: no 2-colouring, no state satisfies every clause
+                assert r.p_success == 0.0
+        del c
+    finally:
+        if ctx is not None:
+            ctx.close()
+        torch.cuda.empty_cache()
 
 
 def test_default_context_per_thread(q):
