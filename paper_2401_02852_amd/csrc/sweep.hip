@@ -105,8 +105,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
                             (TB == 14 && !HALF && (KIND == SK_MIDDLE || KIND == SK_BOUNDARY));
     // Straight-line butterflies in the kinds that mix the tile once and hold
     // no readout state: measured faster there (the boundary kind measured
-    // slower, and the final kind needs the registers).
-    constexpr bool UNCOND = KIND == SK_FIRST || KIND == SK_MIDDLE;
+    // slower, and the final kind needs the registers). With 14-bit tiles the
+    // boundary and final kinds, capped at 128 registers, spill less with them
+    // (21 and 15 dwords instead of 38 and 36): n = 33 590 -> 561 ms, n = 24
+    // 0.96 -> 0.85 ms per 10-layer run.
+    constexpr bool UNCOND = KIND == SK_FIRST || KIND == SK_MIDDLE ||
+                            (TB == 14 && !HALF && (KIND == SK_BOUNDARY || KIND == SK_FINAL));
     // The first sweep (no cost flip) of a group without the virtual bit reads
     // its costs in layout L0 and mixes L0, L1, L2 in that order (see below).
     // Decided the same way in half and full kernels, whose addressing agrees
