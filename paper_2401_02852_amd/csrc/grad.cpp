@@ -30,7 +30,8 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     if (p > 0 && (!dgammas || !dbetas)) return fail(QNAE_EINVAL, "null gradient arrays with p=%d", p);
     if (checkpoint_every < 0) return fail(QNAE_EINVAL, "checkpoint_every=%d < 0", checkpoint_every);
     if (!std::isfinite(w_psucc) || !std::isfinite(w_energy)) return fail(QNAE_EINVAL, "non-finite weights");
-    const int every = checkpoint_every > 0 ? checkpoint_every : 4;
+    // a segment longer than p layers is one segment (and p + every stays in range)
+    const int every = checkpoint_every > 0 ? std::min(checkpoint_every, std::max(p, 1)) : 4;
     if (int rc = enter(ctx)) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int lut_len = m + 1;

@@ -68,7 +68,7 @@ def test_grad_vs_finite_differences(q, n):
         check(dg, db, fg, fb, w)
 
 
-@pytest.mark.parametrize("every", [1, 3, 4, 0])
+@pytest.mark.parametrize("every", [1, 3, 4, 0, 2**31 - 1])
 @pytest.mark.parametrize("p", [1, 4, 7])
 def test_checkpoint_intervals(q, every, p):
     n = 17
