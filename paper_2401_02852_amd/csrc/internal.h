@@ -132,6 +132,16 @@ struct ResidentArgs {
 
 hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s);
 
+// The same with the tables in the kernel arguments (no copy ahead of the
+// launch): p phase tables of lut_len entries (one when p = 0), then the p
+// mixer forms, each stored in one float2 slot; a.luts and a.forms unused.
+constexpr int kResidentInline = 448;
+struct ResidentInlineArgs {
+    ResidentArgs a;
+    float2 tab[kResidentInline];
+};
+hipError_t launch_resident_inline(int dtype, const ResidentInlineArgs& a, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Adjoint (gradient) sweeps: the reverse pass carries the adjoint state lam
 // and the forward state psi together and applies the inverse of each layer to

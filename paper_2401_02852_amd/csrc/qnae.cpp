@@ -179,11 +179,30 @@ int run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int3
     const double readout_scale = std::norm(final_scale) * (half ? 2.0 : 1.0);
     const float2 store_scale = make_float2((float)final_scale.real(), (float)final_scale.imag());
 
-    HIP_TRY(ctx->luts.reserve(sizeof(float2) * (size_t)T * lut_len));
-    HIP_TRY(hipMemcpyAsync(ctx->luts.ptr, tables, sizeof(float2) * (size_t)T * lut_len, hipMemcpyHostToDevice, s));
     double* out_dev = (double*)((char*)ctx->small.ptr + 16);
+    const double rb = std::ldexp((double)(cost_dtype == QNAE_U8 ? 1 : 2) * T + (keep ? 8.0 : 0.0), n);
+    static_assert(sizeof(MixForm) == sizeof(float2), "a mixer form fills one table slot");
 
-    if (n <= kResidentMaxN) {
+    if (n <= kResidentMaxN && (int64_t)T * lut_len + p <= qnae::kResidentInline) {
+        // small tables travel in the kernel arguments: one launch, no copies ahead of it
+        qnae::ResidentInlineArgs ia;
+        qnae::ResidentArgs& a = ia.a;
+        a.state_in = nullptr;
+        a.cost = cost_dev;
+        a.luts = nullptr;
+        a.forms = nullptr;
+        a.state_out = (float2*)state_dev;
+        a.out = out_dev;
+        a.store_scale = store_scale;
+        a.n = n;
+        a.p = p;
+        a.lut_len = lut_len;
+        std::memcpy(ia.tab, tables, sizeof(float2) * (size_t)T * lut_len);
+        if (p > 0) std::memcpy(ia.tab + (size_t)T * lut_len, forms, sizeof(MixForm) * p);
+        HIP_TRY(timed(ctx, K_RESIDENT, rb, s, [&] { return qnae::launch_resident_inline(cost_dtype, ia, s); }));
+    } else if (n <= kResidentMaxN) {
+        HIP_TRY(ctx->luts.reserve(sizeof(float2) * (size_t)T * lut_len));
+        HIP_TRY(hipMemcpyAsync(ctx->luts.ptr, tables, sizeof(float2) * (size_t)T * lut_len, hipMemcpyHostToDevice, s));
         HIP_TRY(ctx->forms.reserve(sizeof(MixForm) * (size_t)T));
         if (p > 0) HIP_TRY(hipMemcpyAsync(ctx->forms.ptr, forms, sizeof(MixForm) * p, hipMemcpyHostToDevice, s));
         qnae::ResidentArgs a;
@@ -197,9 +216,10 @@ int run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int3
         a.n = n;
         a.p = p;
         a.lut_len = lut_len;
-        const double rb = std::ldexp((double)(cost_dtype == QNAE_U8 ? 1 : 2) * T + (keep ? 8.0 : 0.0), n);
         HIP_TRY(timed(ctx, K_RESIDENT, rb, s, [&] { return qnae::launch_resident(cost_dtype, a, s); }));
     } else {
+        HIP_TRY(ctx->luts.reserve(sizeof(float2) * (size_t)T * lut_len));
+        HIP_TRY(hipMemcpyAsync(ctx->luts.ptr, tables, sizeof(float2) * (size_t)T * lut_len, hipMemcpyHostToDevice, s));
         const qnae_tune tune = tune_for(ctx, n, cost_dtype);
         const int TB = tune.tile_bits;
         const int stored = half ? n - 1 : n;

@@ -533,6 +533,21 @@ __global__ __launch_bounds__(kResidentThreads) void resident_kernel(const Reside
     resident_body<CT>(a);
 }
 
+// Tables from the kernel arguments, staged in LDS (3.5 KiB beside the
+// state's 136 KiB) and read through generic pointers.
+template <typename CT>
+__global__ __launch_bounds__(kResidentThreads) void resident_inline_kernel(const ResidentInlineArgs ia) {
+    __shared__ float2 tab[kResidentInline];
+    const int layers = ia.a.p > 0 ? ia.a.p : 1;
+    const int count = layers * ia.a.lut_len + ia.a.p;
+    for (int i = threadIdx.x; i < count; i += kResidentThreads) tab[i] = ia.tab[i];
+    __syncthreads();
+    ResidentArgs a = ia.a;
+    a.luts = tab;
+    a.forms = (const MixForm*)(tab + layers * ia.a.lut_len);
+    resident_body<CT>(a);
+}
+
 // Many small instances, one workgroup each.
 template <typename CT>
 __global__ __launch_bounds__(kResidentThreads) void resident_batch_kernel(const ResidentArgs* args) {
@@ -677,6 +692,16 @@ hipError_t launch_resident(int dtype, const ResidentArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((resident_kernel<uint8_t>), dim3(1), dim3(kResidentThreads), 0, s, a);
     else
         hipLaunchKernelGGL((resident_kernel<uint16_t>), dim3(1), dim3(kResidentThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resident_inline(int dtype, const ResidentInlineArgs& a, hipStream_t s) {
+    const int layers = a.a.p > 0 ? a.a.p : 1;
+    if ((int64_t)layers * a.a.lut_len + a.a.p > kResidentInline) return hipErrorInvalidValue;
+    if (dtype == 1)
+        hipLaunchKernelGGL((resident_inline_kernel<uint8_t>), dim3(1), dim3(kResidentThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((resident_inline_kernel<uint16_t>), dim3(1), dim3(kResidentThreads), 0, s, a);
     return hipGetLastError();
 }
 

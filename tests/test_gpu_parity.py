@@ -148,6 +148,20 @@ def test_qaoa_resident(q, n, kind):
     check_result(got, ref, f"n={n} {kind}")
 
 
+@pytest.mark.parametrize("p", [17, 18])
+def test_qaoa_resident_table_paths(q, p):
+    """n = 11, m = 23: 17 layers of 24-entry tables plus their mixer forms
+    (425 slots) travel in the kernel arguments, 18 layers (450) are copied
+    to the device first; both against the oracle."""
+    n = 11
+    m = inst.clause_count(n, 2.1)
+    assert p * (m + 1) + p == (425 if p == 17 else 450)
+    cl = inst.instance(n, 3, m, 300)
+    g, b = angles("random", p, 7 + p)
+    got, ref = run_pair(q, cl, n, m, g, b)
+    check_result(got, ref, f"n={n} p={p}")
+
+
 @pytest.mark.parametrize("n", [15, 17, 20, 22])
 @pytest.mark.parametrize("kind", ANGLE_SETS)
 @pytest.mark.parametrize("p", [1, 2, 5])
