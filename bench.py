@@ -213,7 +213,7 @@ def scale_bench(q, ctx, names=("nae3_n24_p10", "nae3_n28_p10", "nae3_n33_p10"), 
                      "ms_per_step": dt * 1e3, "sweep_GBps": gbs, "sweep_frac_of_peak": gbs / HBM_PEAK_GBS,
                      "cache_resident": n <= 24, "p_success": res.p_success, "expected_cost": res.expected_cost,
                      "state_GiB": (8 << n) / 2 ** 30,
-                     "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit")}}
+                     "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit", "split")}}
         del cost
         if ctx is not main_ctx:
             ctx.close()
@@ -308,7 +308,7 @@ def batched_bench(q, ctx, reps=5, count=512):
             "plain_instance_layers_per_s": layers / t_plain,
             "plain_instance_layers_per_s_cost_resident": layers / t_plain_nc,
             "speedup_vs_plain": t_plain / t_with,
-            "tile_shape": {k: shape.get(k) for k in ("tile_bits", "low_run_bits", "page_bit")},
+            "tile_shape": {k: shape.get(k) for k in ("tile_bits", "low_run_bits", "page_bit", "split")},
             "autotune_s": t_tune,
             "instance_layers_per_s_half_state": layers / t_half,
             "ms_per_batch": t_with * 1e3, "plain_ms": t_plain * 1e3}
@@ -673,7 +673,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "k": rec["k"], "m": m, "p": p,
                    "angles": "linear ramp", "seed": rec["seed"], "state": "complex64",
                    "cost": "uint8" if m <= 255 else "uint16",
-                   "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit")},
+                   "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit", "split")},
                    "autotuned": not args.no_autotune},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(stats),

@@ -360,17 +360,24 @@ int qnae_sample(qnae_ctx *ctx, const void *state_dev, int32_t n, const void *cos
  * to tiles of 2^tile_bits amplitudes held on chip. Every tile starts with a
  * contiguous run of 2^low_run_bits amplitudes; index bits from page_bit up
  * are spread over the groups so that a tile touches few memory pages
- * (page_bit 64: no spreading). The fastest shape depends on n and is found by
- * timing, not by formula. */
+ * (page_bit 64: no spreading). With two groups besides the first, `split`
+ * chooses which of the index bits below page_bit the third group mixes:
+ * 0 the top run of them (the second group the run below), 1 the top run
+ * less one and the second-lowest, 2 the top run less one and the lowest,
+ * 3 the top three and every other one from the lowest up; other group counts
+ * ignore it. The fastest shape depends on n and is found by timing, not by
+ * formula. */
 typedef struct {
     int32_t tile_bits;    /* 12, 13 or 14 */
     int32_t low_run_bits; /* 4 .. 6 */
     int32_t page_bit;     /* 4 .. 64 */
+    int32_t split;        /* 0 .. 3 */
     double ms_per_layer;  /* measured by qnae_autotune; ignored by qnae_set_tune */
 } qnae_tune;
 
 /* Times every candidate shape (tile_bits 12..14 x low_run_bits 4..5 x
- * page_bit 18 or 64) on `reps` two-layer runs of an n-qubit state in the
+ * page_bit 18 or 64, split 0; then splits 1..3 of the fastest of those, when
+ * its groups have a third) on `reps` two-layer runs of an n-qubit state in the
  * context's scratch memory, on `stream`, keeps the fastest for later
  * qnae_qaoa_run calls at this n and cost type on this context, and writes it
  * to *out. Needs 2^n * (8 + cost bytes) of device memory. For n <= 14 the

@@ -92,7 +92,7 @@ class _CGradJob(ctypes.Structure):
 
 class _CTune(ctypes.Structure):
     _fields_ = [("tile_bits", ctypes.c_int32), ("low_run_bits", ctypes.c_int32), ("page_bit", ctypes.c_int32),
-                ("ms_per_layer", ctypes.c_double)]
+                ("split", ctypes.c_int32), ("ms_per_layer", ctypes.c_double)]
 
 
 class _CKernelStat(ctypes.Structure):
@@ -231,11 +231,12 @@ class Context:
         return _tune_dict(t) if t.tile_bits else {}
 
     def set_tune(self, n: int, tune: Optional[dict], cost_dtype: str = "u8"):
-        """Use `tune` ({tile_bits, low_run_bits, page_bit}) at n; None restores the default."""
+        """Use `tune` ({tile_bits, low_run_bits, page_bit[, split]}) at n; None
+        restores the default."""
         t = None
         if tune is not None:
             t = _CTune(int(tune["tile_bits"]), int(tune["low_run_bits"]), int(tune["page_bit"]),
-                       float(tune.get("ms_per_layer", 0.0)))
+                       int(tune.get("split", 0)), float(tune.get("ms_per_layer", 0.0)))
         _check(load_library().qnae_set_tune(self.handle, int(n), _dtype_code(cost_dtype),
                                             ctypes.byref(t) if t is not None else None))
 
@@ -265,7 +266,7 @@ def _dtype_code(name) -> int:
 
 def _tune_dict(t) -> dict:
     return {"tile_bits": int(t.tile_bits), "low_run_bits": int(t.low_run_bits), "page_bit": int(t.page_bit),
-            "ms_per_layer": float(t.ms_per_layer)}
+            "split": int(t.split), "ms_per_layer": float(t.ms_per_layer)}
 
 
 _default = threading.local()

@@ -139,12 +139,12 @@ namespace qnae_host {
 // phase tables and the angle fields of the kernel arguments.
 struct BatchPlan {
     struct Ident {
-        int32_t n, m, p, dtype, half, tb, low, page;
+        int32_t n, m, p, dtype, half, tb, low, page, split;
         const void* cost;
         void* state;
         bool operator==(const Ident& o) const {
             return n == o.n && m == o.m && p == o.p && dtype == o.dtype && half == o.half && tb == o.tb &&
-                   low == o.low && page == o.page && cost == o.cost && state == o.state;
+                   low == o.low && page == o.page && split == o.split && cost == o.cost && state == o.state;
         }
     };
     struct Job {
@@ -214,7 +214,7 @@ int make_batch_plan(qnae_ctx* ctx, const qnae_instance* inst, int count, BatchPl
         J.state_at = P.state_elems;
         if (!J.resident && !q.state_dev) P.state_elems += (size_t)1 << stored;
         if (!J.resident) {
-            plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, id.tb, id.low, id.page, q.state_dev != nullptr,
+            plan_sweeps(J.plan, q.n, q.m, q.p, q.cost_dtype, id.tb, id.low, id.page, id.split, q.state_dev != nullptr,
                         no_forms.data(), std::complex<double>(1.0, 0.0));
             J.plan.half = q.half != 0;
             steps = std::max(steps, (int)J.plan.ops.size());
@@ -341,13 +341,13 @@ int qnae_qaoa_run_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     uint64_t key = 1469598103934665603ull;
     for (int i = 0; i < count; ++i) {
         const qnae_instance& q = inst[i];
-        const qnae_tune t = q.n <= kResidentMaxN ? qnae_tune{0, 0, 0, 0.0} : tune_for(ctx, q.n, q.cost_dtype);
-        ident[i] = {q.n, q.m, q.p, q.cost_dtype, q.half, t.tile_bits, t.low_run_bits, t.page_bit, q.cost_dev,
+        const qnae_tune t = q.n <= kResidentMaxN ? qnae_tune{0, 0, 0, 0, 0.0} : tune_for(ctx, q.n, q.cost_dtype);
+        ident[i] = {q.n, q.m, q.p, q.cost_dtype, q.half, t.tile_bits, t.low_run_bits, t.page_bit, t.split, q.cost_dev,
                     q.state_dev};
         key = fnv(key, (uint64_t)q.n | (uint64_t)q.m << 8 | (uint64_t)q.p << 24 | (uint64_t)t.tile_bits << 56);
         key = fnv(key, (uint64_t)(uintptr_t)q.cost_dev ^ ((uint64_t)(uintptr_t)q.state_dev << 1) ^
                            ((uint64_t)q.half << 63) ^ ((uint64_t)q.cost_dtype << 62) ^
-                           ((uint64_t)t.low_run_bits << 48) ^ ((uint64_t)t.page_bit << 40));
+                           ((uint64_t)t.low_run_bits << 48) ^ ((uint64_t)t.page_bit << 40) ^ ((uint64_t)t.split << 36));
     }
     BatchPlan* P = nullptr;
     auto& cache = ctx->batch_plans;

@@ -86,7 +86,7 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     // ---- tiled path ----------------------------------------------------------
     const int TB = qnae::kAdjointTileBits;
     const int nseg = p > 0 ? (p + every - 1) / every : 1;
-    const std::vector<Group> groups = make_groups(n, TB, ctx->min_low_run, ctx->page_bit);
+    const std::vector<Group> groups = make_groups(n, TB, ctx->min_low_run, ctx->page_bit, 0);
     const uint32_t tiles = 1u << (n - TB);
     // checkpoints 0 .. nseg-1 (state after each segment), then lam
     HIP_TRY(ctx->g_states.reserve(sizeof(float2) * N * (size_t)(nseg + 1)));
@@ -101,7 +101,7 @@ int qnae_qaoa_grad(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int3
     std::vector<MixForm> forms(T);
     const std::complex<double> final_scale = build_tables(n, m, gammas, betas, p, ftab.data(), forms.data());
     SweepPlan F;
-    plan_sweeps(F, n, m, p, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, true, forms.data(), final_scale);
+    plan_sweeps(F, n, m, p, cost_dtype, TB, ctx->min_low_run, ctx->page_bit, 0, true, forms.data(), final_scale);
     std::vector<int> ckpt_of(F.ops.size(), -1);  // checkpoint stored by each forward sweep
     int stored = 0;
     for (size_t q = 0; q < F.ops.size(); ++q) {

@@ -250,8 +250,8 @@ struct GroupSpec {
     uint8_t pos[16];  // global bit of each tile bit (TB entries)
     uint32_t mask;    // tile bits this group mixes
 };
-int make_group_specs(int n, int TB, int cmin, int page, GroupSpec* out);
-std::vector<Group> make_groups(int n, int TB, int cmin, int page);
+int make_group_specs(int n, int TB, int cmin, int page, int split, GroupSpec* out);
+std::vector<Group> make_groups(int n, int TB, int cmin, int page, int split = 0);
 
 // The sweeps of a depth-p solve over `ngroups` qubit groups, in order, handed
 // to fn(const Op&) one at a time (allocates nothing). Each layer mixes every
@@ -307,7 +307,7 @@ struct SweepPlan {
 };
 
 // Plans a tiled solve; `forms` are the per-layer mixer forms from build_tables.
-void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, bool keep,
+void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, int split, bool keep,
                  const qnae::MixForm* forms, std::complex<double> final_scale, bool from_state = false);
 
 // Reverse pass of a gradient over L layers ("b-layers", the last forward

@@ -132,7 +132,7 @@ extern "C" int qnae_qaoa_run_noalloc(qnae_ctx* ctx, const void* cost_dev, int32_
         HIP_TRY(qnae::launch_resident(cost_dtype, a, s));
     } else {
         GroupSpec spec[kMaxGroups];
-        const int ngroups = make_group_specs(n, TB, tune.low_run_bits, tune.page_bit, spec);
+        const int ngroups = make_group_specs(n, TB, tune.low_run_bits, tune.page_bit, tune.split, spec);
         const PlanRef plan{n, p, TB, lut_len, keep, false, h_forms, h_flips, final_scale};
         float2* const psi = (float2*)state_dev;
         hipError_t e = hipSuccess;

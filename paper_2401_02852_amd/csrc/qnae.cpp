@@ -231,7 +231,8 @@ int run(qnae_ctx* ctx, const void* cost_dev, int32_t cost_dtype, int32_t n, int3
         const int64_t blocks = 1ll << (stored - TB);
         HIP_TRY(ctx->partials.reserve(sizeof(double) * 3 * (size_t)blocks));
         SweepPlan P;
-        plan_sweeps(P, n, m, p, cost_dtype, TB, tune.low_run_bits, tune.page_bit, keep, forms, final_scale);
+        plan_sweeps(P, n, m, p, cost_dtype, TB, tune.low_run_bits, tune.page_bit, tune.split, keep, forms,
+                    final_scale);
         P.half = half;
         for (const Op& op : P.ops) {
             SweepArgs a;

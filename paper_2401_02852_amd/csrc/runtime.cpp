@@ -365,7 +365,37 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
 // n = 30 (13-bit tiles): a tile that mixes index bits 14..17 together with
 // page bits streams slowest, least so beside bits 18..21; this arrangement
 // ran 3% faster than dealing the page bits out round-robin.
-int make_group_specs(int n, int TB, int cmin, int page, GroupSpec* out) {
+//
+// With two groups besides A, `split` 1..3 changes which of the bits below
+// `page` the second of them mixes (see qnae_tune); which split streams
+// fastest depends on n (measured: 1 at n = 30, 3 at n = 31), so the tuner
+// times them.
+namespace {
+// second[k] != 0: the second group takes bit k of the nrn bits below page
+// (it takes k1 of them); false when the split does not fit, and then the
+// consecutive runs stay.
+bool split_second(int split, int nrn, int k1, bool* second) {
+    int pick[64], np = 0;
+    auto take = [&](int k) {
+        for (int j = 0; j < np; ++j)
+            if (pick[j] == k) return;
+        if (k >= 0 && k < nrn && np < k1) pick[np++] = k;
+    };
+    if (split == 1 || split == 2) {
+        take(split == 1 ? 1 : 0);
+        for (int j = 1; j < k1; ++j) take(nrn - j);
+    } else if (split == 3) {
+        for (int j = 1; j <= 3 && j <= k1; ++j) take(nrn - j);
+        for (int k = 0; np < k1 && k < nrn; k += 2) take(k);
+    }
+    if (np != k1) return false;
+    for (int k = 0; k < nrn; ++k) second[k] = false;
+    for (int j = 0; j < np; ++j) second[pick[j]] = true;
+    return true;
+}
+}  // namespace
+
+int make_group_specs(int n, int TB, int cmin, int page, int split, GroupSpec* out) {
     GroupSpec& A = out[0];
     A.mask = (1u << TB) - 1u;
     if (n <= TB) {
@@ -386,15 +416,28 @@ int make_group_specs(int n, int TB, int cmin, int page, GroupSpec* out) {
     int RP[64], RN[64], nrp = 0, nrn = 0;
     for (int b = cA; b < n - a; ++b) (b >= page ? RP[nrp++] : RN[nrn++]) = b;
     const int R = nrp + nrn;
-    int nx = 0;
-    for (int i = 0, q = nrp; i < h; ++i) {
-        // consecutive page runs, evenly, top run first; then the other bits in order
+    // the group of each bit below page: consecutive runs in ascending order
+    int rn_group[64];
+    for (int i = 0, k = 0; i < h; ++i) {
         const int c = nrp / h + (i < nrp % h ? 1 : 0);
         const int size = R / h + (i < R % h ? 1 : 0);
+        for (int j = c; j < size; ++j) rn_group[k++] = i;
+    }
+    if (h == 2 && split != 0) {
+        int k1 = 0;
+        for (int k = 0; k < nrn; ++k) k1 += rn_group[k] == 1;
+        bool second[64];
+        if (split_second(split, nrn, k1, second))
+            for (int k = 0; k < nrn; ++k) rn_group[k] = second[k] ? 1 : 0;
+    }
+    for (int i = 0, q = nrp; i < h; ++i) {
+        // consecutive page runs, evenly, top run first; then the other bits
+        const int c = nrp / h + (i < nrp % h ? 1 : 0);
         q -= c;
         uint64_t bits = 0;
         for (int k = 0; k < c; ++k) bits |= 1ull << RP[q + k];
-        for (int k = c; k < size; ++k) bits |= 1ull << RN[nx++];
+        for (int k = 0; k < nrn; ++k)
+            if (rn_group[k] == i) bits |= 1ull << RN[k];
         // fill up to TB - cmin bits with unmixed bits just above the low run
         uint64_t all = bits;
         for (int b = cmin; __builtin_popcountll(all) < TB - cmin; ++b) all |= 1ull << b;
@@ -411,9 +454,9 @@ int make_group_specs(int n, int TB, int cmin, int page, GroupSpec* out) {
     return 1 + h;
 }
 
-std::vector<Group> make_groups(int n, int TB, int cmin, int page) {
+std::vector<Group> make_groups(int n, int TB, int cmin, int page, int split) {
     GroupSpec spec[kMaxGroups];
-    const int count = make_group_specs(n, TB, cmin, page, spec);
+    const int count = make_group_specs(n, TB, cmin, page, split, spec);
     std::vector<Group> g(count);
     for (int i = 0; i < count; ++i) {
         g[i].pos.assign(spec[i].pos, spec[i].pos + TB);
@@ -451,7 +494,7 @@ std::vector<AdjOp> make_adjoint_plan(int ngroups, int L) {
     return ops;
 }
 
-void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, bool keep,
+void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin, int page, int split, bool keep,
                  const qnae::MixForm* forms, std::complex<double> final_scale, bool from_state) {
     P.n = n;
     P.m = m;
@@ -460,7 +503,7 @@ void plan_sweeps(SweepPlan& P, int n, int m, int p, int dtype, int TB, int cmin,
     P.dtype = dtype;
     P.lut_len = m + 1;
     P.keep = keep;
-    P.groups = make_groups(n, TB, cmin, page);
+    P.groups = make_groups(n, TB, cmin, page, split);
     P.ops = make_plan((int)P.groups.size(), p, from_state);
     P.forms.assign(forms, forms + p);
     P.flips_before.assign(p + 1, 0);

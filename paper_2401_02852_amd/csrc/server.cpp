@@ -218,7 +218,8 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
         r.final_scale = build_tables(r.n, r.m, r.gammas.data(), r.betas.data(), r.p, w.tabs.data(), w.forms.data());
         w.tab_at = B.take(r.part_off);  // same layout as the aux block: tables, then forms
         if (!r.resident) {
-            plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, r.shape.tile_bits, r.shape.low_run_bits, r.shape.page_bit, false,
+            plan_sweeps(r.plan, r.n, r.m, r.p, r.dtype, r.shape.tile_bits, r.shape.low_run_bits, r.shape.page_bit,
+                        r.shape.split, false,
                         w.forms.data(), r.final_scale);
             r.plan.half = r.half;
         }
@@ -512,7 +513,7 @@ int qnae_server_create(qnae_ctx* ctx, uint64_t pool_bytes, int32_t max_slots, qn
     S->ctx = ctx;
     S->device = ctx->device;
     S->tunes = ctx->tunes;
-    S->default_shape = qnae_tune{ctx->tile_bits, ctx->min_low_run, ctx->page_bit, 0.0};
+    S->default_shape = qnae_tune{ctx->tile_bits, ctx->min_low_run, ctx->page_bit, 0, 0.0};
     S->max_slots = max_slots;
     S->pool_bytes = 1ull << order;
     if (const char* e = std::getenv("QNAE_SERVER_HALF")) S->use_half = std::atoi(e) != 0;

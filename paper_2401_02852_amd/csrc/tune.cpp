@@ -20,7 +20,7 @@ namespace qnae_host {
 qnae_tune tune_for(const qnae_ctx* ctx, int n, int dtype) {
     auto it = ctx->tunes.find({n, dtype});
     if (it != ctx->tunes.end()) return it->second;
-    return qnae_tune{ctx->tile_bits, ctx->min_low_run, ctx->page_bit, 0.0};
+    return qnae_tune{ctx->tile_bits, ctx->min_low_run, ctx->page_bit, 0, 0.0};
 }
 
 }  // namespace qnae_host
@@ -32,7 +32,14 @@ int check_shape(const qnae_tune& t) {
     if (t.low_run_bits < 4 || t.low_run_bits > 6)
         return fail(QNAE_EINVAL, "low_run_bits=%d outside [4, 6]", t.low_run_bits);
     if (t.page_bit < 4 || t.page_bit > 64) return fail(QNAE_EINVAL, "page_bit=%d outside [4, 64]", t.page_bit);
+    if (t.split < 0 || t.split > 3) return fail(QNAE_EINVAL, "split=%d outside [0, 3]", t.split);
     return QNAE_OK;
+}
+
+// Do the groups of this shape at n have a third one (where split applies)?
+bool has_split(int n, const qnae_tune& t) {
+    GroupSpec spec[kMaxGroups];
+    return make_group_specs(n, t.tile_bits, t.low_run_bits, t.page_bit, 0, spec) == 3;
 }
 
 int check_tune_target(int32_t n, int32_t dtype, int32_t lo) {
@@ -50,7 +57,7 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     if (reps < 1 || reps > 1000) return fail(QNAE_EINVAL, "reps=%d outside [1, 1000]", reps);
     if (!out) return fail(QNAE_EINVAL, "null output pointer");
     if (int rc = enter(ctx)) return rc;
-    *out = qnae_tune{0, 0, 0, 0.0};
+    *out = qnae_tune{0, 0, 0, 0, 0.0};
     if (n <= kResidentMaxN) return QNAE_OK;
     hipStream_t s = (hipStream_t)stream;
     const int p = 2, m = 63, lut_len = m + 1;
@@ -83,22 +90,30 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
         }
         return hipSuccess;
     };
-    qnae_tune best{0, 0, 0, 1e300};
+    qnae_tune best{0, 0, 0, 0, 1e300};
     hipError_t err = hipSuccess;
+    auto time_shape = [&](const qnae_tune& t) {
+        SweepPlan P;
+        plan_sweeps(P, n, m, p, cost_dtype, t.tile_bits, t.low_run_bits, t.page_bit, t.split, false, forms,
+                    final_scale);
+        if ((err = run(P, t.tile_bits))) return;  // warm-up
+        if ((err = hipEventRecord(ev[0], s))) return;
+        for (int r = 0; r < reps && !err; ++r) err = run(P, t.tile_bits);
+        if (err || (err = hipEventRecord(ev[1], s)) || (err = hipEventSynchronize(ev[1]))) return;
+        float ms = 0.f;
+        if ((err = hipEventElapsedTime(&ms, ev[0], ev[1]))) return;
+        const double per_layer = ms / (double)(reps * p);
+        if (per_layer < best.ms_per_layer) best = qnae_tune{t.tile_bits, t.low_run_bits, t.page_bit, t.split, per_layer};
+    };
     for (int TB = 12; TB <= 14 && !err; ++TB)
         for (int low = 4; low <= 5 && !err; ++low)
-            for (int page : {18, 64}) {
-                SweepPlan P;
-                plan_sweeps(P, n, m, p, cost_dtype, TB, low, page, false, forms, final_scale);
-                if ((err = run(P, TB))) break;  // warm-up
-                if ((err = hipEventRecord(ev[0], s))) break;
-                for (int r = 0; r < reps && !err; ++r) err = run(P, TB);
-                if (err || (err = hipEventRecord(ev[1], s)) || (err = hipEventSynchronize(ev[1]))) break;
-                float ms = 0.f;
-                if ((err = hipEventElapsedTime(&ms, ev[0], ev[1]))) break;
-                const double per_layer = ms / (double)(reps * p);
-                if (per_layer < best.ms_per_layer) best = qnae_tune{TB, low, page, per_layer};
-            }
+            for (int page : {18, 64})
+                if (!err) time_shape(qnae_tune{TB, low, page, 0, 0.0});
+    if (!err && has_split(n, best)) {
+        const qnae_tune base = best;
+        for (int split = 1; split <= 3 && !err; ++split)
+            time_shape(qnae_tune{base.tile_bits, base.low_run_bits, base.page_bit, split, 0.0});
+    }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (err) return fail(QNAE_EHIP, "autotune: %s", hipGetErrorString(err));
@@ -117,7 +132,8 @@ int qnae_set_tune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, const qnae_tune*
         return QNAE_OK;
     }
     if (int rc = check_shape(*tune)) return rc;
-    ctx->tunes[{n, cost_dtype}] = qnae_tune{tune->tile_bits, tune->low_run_bits, tune->page_bit, tune->ms_per_layer};
+    ctx->tunes[{n, cost_dtype}] =
+        qnae_tune{tune->tile_bits, tune->low_run_bits, tune->page_bit, tune->split, tune->ms_per_layer};
     return QNAE_OK;
 } catch (...) {
     return host_exception();
@@ -129,7 +145,7 @@ int qnae_autotune_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     if (!out) return fail(QNAE_EINVAL, "null output pointer");
     if (count < 0 || (count > 0 && !inst)) return fail(QNAE_EINVAL, "bad instance array (count=%d)", count);
     if (!ctx) return fail(QNAE_EINVAL, "null context");
-    *out = qnae_tune{0, 0, 0, 0.0};
+    *out = qnae_tune{0, 0, 0, 0, 0.0};
     // the (n, cost type) classes the shape applies to: instances on the sweep path
     std::vector<std::pair<int, int>> classes;
     int layers = 0;
@@ -142,26 +158,36 @@ int qnae_autotune_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     if (classes.empty()) return QNAE_OK;
     std::vector<qnae_result> res((size_t)count);
     const auto saved = ctx->tunes;
-    qnae_tune best{0, 0, 0, 1e300};
+    qnae_tune best{0, 0, 0, 0, 1e300};
+    auto time_shape = [&](const qnae_tune& shape) -> int {
+        for (const auto& c : classes) ctx->tunes[c] = shape;
+        // one warm-up run plans the shape and captures its launches
+        int rc = qnae_qaoa_run_batched(ctx, inst, count, res.data(), stream);
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; r < reps && !rc; ++r) rc = qnae_qaoa_run_batched(ctx, inst, count, res.data(), stream);
+        if (rc) {
+            const std::string msg = last_error();
+            ctx->tunes = saved;
+            return fail(rc, "autotune_batched: %s", msg.c_str());
+        }
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+        const double per_layer = ms / std::max(layers, 1);
+        if (per_layer < best.ms_per_layer)
+            best = qnae_tune{shape.tile_bits, shape.low_run_bits, shape.page_bit, shape.split, per_layer};
+        return QNAE_OK;
+    };
     for (int TB = 12; TB <= 14; ++TB)
         for (int low = 4; low <= 5; ++low)
-            for (int page : {18, 64}) {
-                const qnae_tune shape{TB, low, page, 0.0};
-                for (const auto& c : classes) ctx->tunes[c] = shape;
-                // one warm-up run plans the shape and captures its launches
-                int rc = qnae_qaoa_run_batched(ctx, inst, count, res.data(), stream);
-                const auto t0 = std::chrono::steady_clock::now();
-                for (int r = 0; r < reps && !rc; ++r) rc = qnae_qaoa_run_batched(ctx, inst, count, res.data(), stream);
-                if (rc) {
-                    const std::string msg = last_error();
-                    ctx->tunes = saved;
-                    return fail(rc, "autotune_batched: %s", msg.c_str());
-                }
-                const double ms =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
-                const double per_layer = ms / std::max(layers, 1);
-                if (per_layer < best.ms_per_layer) best = qnae_tune{TB, low, page, per_layer};
-            }
+            for (int page : {18, 64})
+                if (int rc = time_shape(qnae_tune{TB, low, page, 0, 0.0})) return rc;
+    bool splits = false;
+    for (const auto& c : classes) splits |= has_split(c.first, best);
+    if (splits) {
+        const qnae_tune base = best;
+        for (int split = 1; split <= 3; ++split)
+            if (int rc = time_shape(qnae_tune{base.tile_bits, base.low_run_bits, base.page_bit, split, 0.0})) return rc;
+    }
     for (const auto& c : classes) ctx->tunes[c] = best;
     *out = best;
     return QNAE_OK;

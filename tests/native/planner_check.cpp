@@ -36,8 +36,9 @@ static void check_groups_and_plans() {
     for (int TB = 12; TB <= 14; ++TB)
         for (int cmin = 4; cmin <= 6; ++cmin)
             for (int page : {18, 64})
+                for (int split = 0; split <= 3; ++split)
                 for (int n = TB + 1; n <= 34; ++n) {
-                    const std::vector<Group> g = make_groups(n, TB, cmin, page);
+                    const std::vector<Group> g = make_groups(n, TB, cmin, page, split);
                     uint64_t mixed = 0;
                     for (const Group& gr : g) {
                         CHECK((int)gr.pos.size() == TB);
@@ -70,7 +71,7 @@ static void check_groups_and_plans() {
                         // half-state sweeps: the tile index fills n-1-TB stored bits
                         if (n - 1 > TB && n >= 15) {
                             SweepPlan P;
-                            plan_sweeps(P, n, 10, p, QNAE_U8, TB, cmin, page, false, forms.data(),
+                            plan_sweeps(P, n, 10, p, QNAE_U8, TB, cmin, page, split, false, forms.data(),
                                         std::complex<double>(1.0, 0.0));
                             P.half = true;
                             for (const Op& op : P.ops) {
@@ -328,7 +329,7 @@ static void check_half_addressing() {
             for (int page : {13, 64})
                 for (int n = std::max(15, TB + 1); n <= 17; ++n) {
                     SweepPlan P;
-                    plan_sweeps(P, n, 10, 2, QNAE_U8, TB, cmin, page, false, forms.data(),
+                    plan_sweeps(P, n, 10, 2, QNAE_U8, TB, cmin, page, 0, false, forms.data(),
                                 std::complex<double>(1.0, 0.0));
                     P.half = true;
                     const uint64_t N = 1ull << (n - 1);
@@ -370,7 +371,7 @@ static void check_fixed_planner_matches_vectors() {
                 for (int n = TB + 1; n <= 34; ++n) {
                     const std::vector<Group> want = vector_make_groups(n, TB, cmin, page);
                     GroupSpec spec[kMaxGroups];
-                    const int count = make_group_specs(n, TB, cmin, page, spec);
+                    const int count = make_group_specs(n, TB, cmin, page, 0, spec);
                     CHECK(count == (int)want.size() && count <= kMaxGroups);
                     for (int i = 0; i < count; ++i) {
                         CHECK(spec[i].mask == want[i].mask);
@@ -389,10 +390,46 @@ static void check_fixed_planner_matches_vectors() {
                 }
 }
 
+// The split variants at the sizes where they were measured fastest: the
+// index bits below the page bits that the third group mixes.
+static uint64_t third_group_low_bits(int n, int split) {
+    GroupSpec spec[kMaxGroups];
+    CHECK(make_group_specs(n, 13, 4, 18, split, spec) == 3);
+    uint64_t bits = 0;
+    for (int i = 0; i < 13; ++i)
+        if (((spec[2].mask >> i) & 1u) && spec[2].pos[i] < 18) bits |= 1ull << spec[2].pos[i];
+    return bits;
+}
+
+static void check_split_layouts() {
+    auto set = [](std::initializer_list<int> b) {
+        uint64_t v = 0;
+        for (int x : b) v |= 1ull << x;
+        return v;
+    };
+    CHECK(third_group_low_bits(30, 0) == set({14, 15, 16, 17}));
+    CHECK(third_group_low_bits(30, 1) == set({10, 15, 16, 17}));
+    CHECK(third_group_low_bits(29, 2) == set({9, 14, 15, 16, 17}));
+    CHECK(third_group_low_bits(31, 3) == set({8, 10, 15, 16, 17}));
+    // a split changes nothing where there is no third group
+    for (int n : {15, 20, 32, 33})
+        for (int split = 1; split <= 3; ++split) {
+            GroupSpec a[kMaxGroups], b[kMaxGroups];
+            const int ca = make_group_specs(n, 13, 4, 18, 0, a), cb = make_group_specs(n, 13, 4, 18, split, b);
+            CHECK(ca == cb);
+            if (ca == 3) continue;
+            for (int i = 0; i < ca; ++i) {
+                CHECK(a[i].mask == b[i].mask);
+                for (int j = 0; j < 13; ++j) CHECK(a[i].pos[j] == b[i].pos[j]);
+            }
+        }
+}
+
 int main() {
     check_fixed_planner_matches_vectors();
     check_half_addressing();
     check_groups_and_plans();
+    check_split_layouts();
     check_clause_records();
     check_phase_rows();
     check_host_exception();

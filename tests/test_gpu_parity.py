@@ -275,8 +275,9 @@ def test_workloads_vs_stored_oracle(q, golden, name):
 
 def test_n30_workload_every_tile_shape(q, golden):
     """The n = 30 workload (the benchmark's step) under every tile shape the
-    autotuner may choose, against the stored oracle values: the timed launch
-    configuration is covered whichever shape it keeps."""
+    autotuner may choose (and every group split), against the stored oracle
+    values: the timed launch configuration is covered whichever shape it
+    keeps."""
     import torch
     rec = golden["nae3_n30_p10"]
     n, k, m, p = rec["n"], rec["k"], rec["m"], rec["p"]
@@ -288,12 +289,12 @@ def test_n30_workload_every_tile_shape(q, golden):
     c = q.build_cost_diagonal(cl, n, ctx=ctx)
     ref = rec["results"]["ramp_min"]
     g, b = inst.ramp_angles(p)
-    for tb in (12, 13, 14):
-        for low in (4, 5, 6):
-            for page in (18, 64):
-                ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": low, "page_bit": page})
-                r = q.qaoa_run(c, n, m, g, -b, ctx=ctx)
-                check_result(r, (ref["p_success"], ref["expected_cost"], ref["norm"]), f"shape {tb}/{low}/{page}")
+    shapes = [(tb, low, page, 0) for tb in (12, 13, 14) for low in (4, 5, 6) for page in (18, 64)]
+    shapes += [(tb, 4, 18, split) for tb in (12, 13, 14) for split in (1, 2, 3)]
+    for tb, low, page, split in shapes:
+        ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": low, "page_bit": page, "split": split})
+        r = q.qaoa_run(c, n, m, g, -b, ctx=ctx)
+        check_result(r, (ref["p_success"], ref["expected_cost"], ref["norm"]), f"shape {tb}/{low}/{page}/{split}")
     ctx.close()
     del c
     torch.cuda.empty_cache()

@@ -49,6 +49,7 @@ def test_autotune_keeps_a_candidate(q, tmp_path):
     shapes = tuning.autotune(ctx, [18, 20], ("u8", "u16"), reps=2)
     for (n, dt), t in shapes.items():
         assert t["tile_bits"] in (12, 13, 14) and t["low_run_bits"] in (4, 5) and t["page_bit"] in (18, 64)
+        assert t["split"] in (0, 1, 2, 3)
         assert t["ms_per_layer"] > 0
         assert ctx.get_tune(n, dt)["tile_bits"] == t["tile_bits"]
     path = str(tmp_path / "tune.json")
@@ -67,5 +68,7 @@ def test_autotune_keeps_a_candidate(q, tmp_path):
         ctx.set_tune(n, {"tile_bits": 15, "low_run_bits": 4, "page_bit": 18})
     with pytest.raises(q.QNAEError, match="n=14"):
         ctx.set_tune(14, {"tile_bits": 13, "low_run_bits": 4, "page_bit": 18})
+    with pytest.raises(q.QNAEError, match="split=4"):
+        ctx.set_tune(n, {"tile_bits": 13, "low_run_bits": 4, "page_bit": 18, "split": 4})
     ctx.close()
     fresh.close()

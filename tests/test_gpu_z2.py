@@ -87,6 +87,23 @@ def test_half_run_tile_shapes(q, tb, n):
     ctx.close()
 
 
+@pytest.mark.parametrize("tb", [12, 13])
+@pytest.mark.parametrize("split", [1, 2, 3])
+def test_half_run_group_splits(q, tb, split):
+    """n = 25 (three qubit groups): every split of the low index bits between
+    the second and third group, on the half state, against the oracle."""
+    n = 25
+    ctx = q.Context()
+    ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": 4, "page_bit": 18, "split": split})
+    m = inst.clause_count(n, 2.1)
+    cl = inst.instance(n, 3, m, 650)
+    rng = np.random.default_rng(split + 10 * tb)
+    g, b = rng.uniform(0, np.pi, 3), rng.uniform(0, np.pi, 3)
+    c = q.build_cost_diagonal_z2(cl, n, ctx=ctx)
+    check(q.qaoa_run_z2(c, n, m, g, b, ctx=ctx), oracle.qaoa(oracle.cost(cl, n), n, g, b), f"tb={tb} split={split}")
+    ctx.close()
+
+
 def test_half_uint16_and_k5(q):
     n, m = 17, 300
     cl = inst.instance(n, 5, m, 2)

@@ -143,7 +143,7 @@ def test_server_binding_without_gpu():
 def test_tune_binding_without_gpu():
     b = _lib_or_skip()
     lib = b.load_library()
-    t = b._CTune(13, 4, 18, 0.0)
+    t = b._CTune(13, 4, 18, 0, 0.0)
     assert lib.qnae_set_tune(None, 20, 1, ctypes.byref(t)) == -1
     assert b"null context" in lib.qnae_last_error(None)
     assert lib.qnae_autotune(None, 20, 1, 0, ctypes.byref(t), None) == -1
