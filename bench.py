@@ -599,6 +599,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the n=30 step (no other legs, no CPU baseline, no autotuning): for profiling")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile-shape", default="", metavar="TB,LOW,PAGE,SPLIT",
+                    help="use this tile shape for the headline step instead of autotuning (e.g. the shape a "
+                         "default run picked, for profiling runs that must time the same launches)")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -630,8 +633,14 @@ def main():
     n, m, p = rec["n"], rec["m"], rec["p"]
     ctx = q.Context(0)
     cost = torch.empty(1 << n, dtype=torch.uint8 if m <= 255 else torch.uint16, device="cuda")
-    shape = {} if args.no_autotune else ctx.autotune(n, "u8" if m <= 255 else "u16", reps=3)
-    shape = shape or ctx.get_tune(n, "u8" if m <= 255 else "u16")
+    cdt = "u8" if m <= 255 else "u16"
+    if args.tile_shape:
+        tb, low, page, split = (int(x) for x in args.tile_shape.split(","))
+        ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": low, "page_bit": page, "split": split}, cdt)
+        shape = ctx.get_tune(n, cdt)
+    else:
+        shape = {} if args.no_autotune else ctx.autotune(n, cdt, reps=3)
+        shape = shape or ctx.get_tune(n, cdt)
 
     def step():
         q.build_cost_diagonal(cl, n, out=cost, ctx=ctx)
@@ -674,7 +683,7 @@ def main():
                    "angles": "linear ramp", "seed": rec["seed"], "state": "complex64",
                    "cost": "uint8" if m <= 255 else "uint16",
                    "tile_shape": {k: shape[k] for k in ("tile_bits", "low_run_bits", "page_bit", "split")},
-                   "autotuned": not args.no_autotune},
+                   "autotuned": not args.no_autotune and not args.tile_shape},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(stats),
                      "traffic_source": "profiles/sweep_n30_p10_hbm_traffic.txt: rocprofv3 FETCH_SIZE and WRITE_SIZE "
