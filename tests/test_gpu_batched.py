@@ -210,6 +210,32 @@ def test_batched_under_every_tile_shape(q):
         ctx.close()
 
 
+@pytest.mark.parametrize("split", [1, 2, 3])
+def test_batched_group_splits(q, split):
+    """Instances at n = 23..25 (three qubit groups at 13-bit tiles) with a
+    group split set: the batched results equal the single-instance path under
+    the same shape, which the oracle checks on one instance."""
+    jobs = []
+    for i, n in enumerate((23, 24, 25, 24)):
+        m = inst.clause_count(n, 2.1)
+        cl = inst.instance(n, 3, m, 700 + i)
+        rng = np.random.default_rng(split * 10 + i)
+        jobs.append((n, m, cl, rng.uniform(0, np.pi, 2), rng.uniform(0, np.pi, 2)))
+    ns = [j[0] for j in jobs]
+    ctx = q.Context()
+    for n in set(ns):
+        ctx.set_tune(n, {"tile_bits": 13, "low_run_bits": 4, "page_bit": 18, "split": split})
+    costs = q.build_cost_diagonals([j[2] for j in jobs], ns, ctx=ctx)
+    res = q.qaoa_run_batched(costs, ns, [j[1] for j in jobs], [j[3] for j in jobs], [j[4] for j in jobs], ctx=ctx)
+    for (n, m, cl, g, b), c, r in zip(jobs, costs, res):
+        assert np.allclose(r, q.qaoa_run(c, n, m, g, b, ctx=ctx), rtol=1e-12, atol=1e-15), (split, n)
+    n, m, cl, g, b = jobs[0]
+    ref = oracle.qaoa(oracle.cost(cl, n), n, g, b)
+    assert abs(res[0].p_success - ref[0]) <= 1e-5 and abs(res[0].expected_cost - ref[1]) <= 1e-5 * ref[1]
+    del costs
+    ctx.close()
+
+
 def test_autotune_batched_keeps_a_candidate(q):
     """The batch-level tuner keeps one of the candidate shapes for every
     (n, cost type) of the batch's tiled instances; afterwards batched and
@@ -223,6 +249,7 @@ def test_autotune_batched_keeps_a_candidate(q):
     ctx = q.Context()
     best = q.autotune_batched(costs, ns, ms, gs, bs, reps=1, ctx=ctx)
     assert {k: best[k] for k in ("tile_bits", "low_run_bits", "page_bit")} in SHAPES
+    assert best["split"] in (0, 1, 2, 3)
     assert best["ms_per_layer"] > 0
     for n in sorted({n for n in ns if n > 14}):
         got = ctx.get_tune(n)
