@@ -300,14 +300,19 @@ def test_n30_workload_every_tile_shape(q, golden):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n", [24, 30, 33])
+@pytest.mark.parametrize("n", [24, 30, 33, 34])
 def test_ring_closed_form_at_scale(q, n):
     """k = 2 ring of all-positive clauses at p = 1:
     E[C] = n/2 (1 + sin(4 beta) sin(2 gamma) / 2) (graph closed form).
-    n = 33: 2^33 amplitudes (64 GiB state, 8 GiB cost) through 64-bit
-    indices in every sweep kind, on a context of its own that is closed
+    n = 33 and 34 (the largest n the library takes): 2^33 and 2^34
+    amplitudes (64 and 128 GiB of state, 8 and 16 GiB of cost) through 64-bit
+    indices in every sweep kind, on a context of their own that is closed
     afterwards."""
     import torch
+    if n > 33:
+        free, _ = torch.cuda.mem_get_info()
+        if free < (150 << 30):
+            pytest.skip("not enough device memory for a 2^34-amplitude state")
     ctx = q.Context(0) if n > 32 else None
     try:
         cl = np.array([[i + 1, (i + 1) % n + 1] for i in range(n)], dtype=np.int32)
