@@ -499,7 +499,7 @@ def grad_bench(q, ctx, reps=20, adam_steps=200):
             "p_success_start": start, "p_success_end": ps.item(), "expected_cost_end": e.item()}
 
 
-def serving_bench(q, ctx, count=2000, warm=100, rate=200.0):
+def serving_bench(q, ctx, count=2000, warm=100, rate=200.0, autotune=True):
     """Poisson request trace (n 14..26, p 2..20, k in {3, 5}) through the
     continuous-batching server and through the plain path one request at a
     time in arrival order (FIFO), at the trace's rate and at saturation (every
@@ -511,6 +511,12 @@ def serving_bench(q, ctx, count=2000, warm=100, rate=200.0):
     from workloads import instances as inst
     trace = inst.serving_workload(count=count, rate=rate)
     layers = sum(r["p"] for r in trace[warm:])
+    # the tile shape of every request size on the sweep path, for both paths
+    tuned = {}
+    if autotune:
+        for n in sorted({r["n"] for r in trace if r["n"] > 14}):
+            for dt in sorted({"u16" if r["m"] > 255 else "u8" for r in trace if r["n"] == n}):
+                tuned[f"{n}/{dt}"] = ctx.autotune(n, dt, reps=2)
     pct = lambda a, x: float(np.percentile(np.asarray(a), x)) * 1e3
 
     def served(saturate):
@@ -567,7 +573,9 @@ def serving_bench(q, ctx, count=2000, warm=100, rate=200.0):
 
     out = {"workload": f"{count} Poisson requests at {rate:g}/s (first {warm} warm-up), k in {{3,5}}, "
                        "n in 14..26, p in 2..20, angles U(0,pi)",
-           "instance_layers": layers}
+           "instance_layers": layers,
+           "tile_shapes": {k: {f: v[f] for f in ("tile_bits", "low_run_bits", "page_bit", "split")}
+                           for k, v in tuned.items() if v}}
     for mode, sat in (("rate", False), ("saturation", True)):
         lat, wall, st = served(sat)
         torch.cuda.synchronize()
@@ -716,7 +724,7 @@ def main():
     if not args.no_sampling:
         out["sampling"] = sampling_bench(q, ctx)
     if not args.no_serving:
-        out["serving"] = serving_bench(q, ctx, count=args.serving_requests)
+        out["serving"] = serving_bench(q, ctx, count=args.serving_requests, autotune=not args.no_autotune)
     if not args.no_ceilings:  # last: its 8 GiB of torch buffers are freed again
         ceil = stream_ceilings(torch)
         ceil["sweeps_over_copy"] = achieved / ceil["copy_GBps"] if ceil["copy_GBps"] > 0 else None
