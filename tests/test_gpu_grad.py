@@ -161,6 +161,28 @@ def test_grad_u16_costs(q, n):
         assert abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1], (r, ro)
 
 
+def test_grad_n24_streaming(q):
+    """n = 24: the reverse sweeps stream their states with nontemporal accesses
+    (the two states exceed the last-level cache); both butterfly forms,
+    checkpoints every 2 of 3 layers, satisfiable instance (seed 4, 96
+    solutions), against the oracle's adjoint."""
+    import torch
+    n, p = 24, 3
+    m = inst.clause_count(n, 2.1)
+    cl = inst.instance(n, 3, m, 4)
+    rng = np.random.default_rng(24)
+    g, b = rng.uniform(0, 1.5, p), rng.uniform(0, np.pi, p)
+    c = q.build_cost_diagonal(cl, n)
+    cost = oracle.cost(cl, n)
+    w = (0.5, 0.2)
+    dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=2)
+    rg, rb, ro = oracle.qaoa_grad(cost, n, g, b, *w)
+    check(dg, db, rg, rb, w)
+    check_readout(r, ro)
+    del c
+    torch.cuda.empty_cache()
+
+
 def test_grad_workload_n22_p12(q, golden):
     """The differentiation workload: n = 22, m = 46, p = 12 from the linear
     ramp (beta negated), checkpoints every 4 layers, against the oracle's
