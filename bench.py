@@ -459,9 +459,11 @@ def grad_bench(q, ctx, reps=20, adam_steps=200):
     """Differentiation workload: n = 22, m = 46, p = 12 from the linear ramp
     (beta negated), checkpoints every 4 layers. Time of one adjoint gradient
     against one forward run, then Adam (lr 0.01) maximising p_succ through
-    QAOAFunction; parity of the gradient is the test suite's job."""
+    QAOAFunction; the gradient/forward ratio also at n = 26 (same recipe).
+    Parity of the gradient is the test suite's job."""
     import numpy as np
     import torch
+    from workloads import instances as inst
     rec, cl, g0, b0 = load_workload("nae3_n22_p12")
     n, m, p = rec["n"], rec["m"], rec["p"]
     b0 = -b0
@@ -493,10 +495,20 @@ def grad_bench(q, ctx, reps=20, adam_steps=200):
         opt.step()
         start = ps.item() if start is None else start
     dt = time.perf_counter() - t0
+    # the same recipe at a size where a reverse sweep has many rounds of tiles
+    n2 = 26
+    m2 = inst.clause_count(n2, 2.1)
+    cl2 = inst.instance(n2, 3, m2, 0)
+    c2 = q.build_cost_diagonal(cl2, n2, ctx=ctx)
+    t_fwd2 = timed(lambda: q.qaoa_run(c2, n2, m2, g0, b0, ctx=ctx))
+    t_grad2 = timed(lambda: q.qaoa_grad(c2, n2, m2, g0, b0, w_psucc=1.0, w_energy=0.0, checkpoint_every=4, ctx=ctx))
+    del c2
     return {"workload": f"n={n} m={m} p={p} 3-NAE-SAT (seed {rec['seed']}), linear ramp start, checkpoint every 4",
             "forward_ms": t_fwd * 1e3, "grad_ms": t_grad * 1e3, "grad_over_forward": t_grad / t_fwd,
             "adam_steps": adam_steps, "adam_steps_per_s": adam_steps / dt,
-            "p_success_start": start, "p_success_end": ps.item(), "expected_cost_end": e.item()}
+            "p_success_start": start, "p_success_end": ps.item(), "expected_cost_end": e.item(),
+            f"n{n2}": {"workload": f"n={n2} m={m2} p={p} 3-NAE-SAT (seed 0), linear ramp start, checkpoint every 4",
+                       "forward_ms": t_fwd2 * 1e3, "grad_ms": t_grad2 * 1e3, "grad_over_forward": t_grad2 / t_fwd2}}
 
 
 def serving_bench(q, ctx, count=2000, warm=100, rate=200.0, autotune=True):
