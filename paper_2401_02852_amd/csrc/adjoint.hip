@@ -59,13 +59,160 @@ __device__ __forceinline__ void st2(float2* p, float2 q) {
     }
 }
 
+// A reverse tile is 2^13 elements of both states over 512 threads: each
+// thread holds the same 16 elements of lam and of psi (the pair terms below
+// need both at one place), 64 registers of state, so two workgroups (four
+// waves per SIMD) share a CU without scratch. (Holding 32 elements of each
+// state at two waves per SIMD spilled 17 to 64 dwords per lane, and the
+// spill traffic reached HBM: 10-25% more bytes written per reverse sweep at
+// n = 26.) Element e of the tile splits into a thread part (6 lane bits,
+// 3 wave bits) and a slot part (4 bits) in four layouts:
+//   Q0  slots e{0, 7, 8, 9},   lanes e{1..6},             waves e{10, 11, 12}
+//   Q1  slots e{1, 2, 3, 4},   lanes e{0, 6, 7, 8, 5, 9}, waves e{10, 11, 12}
+//   Q2  slots e{4, 5, 6, 10},  lanes e{0, 1, 2, 3, 11, 12}, waves e{7, 8, 9}
+//   Q3  slots e{4, 5, 12, 11}, lanes e{0, 1, 2, 3, 10, 6},  waves e{7, 8, 9}
+// Q0 is the global layout (tile bit 0 pairs in one 16-byte access); Q0 <-> Q1
+// stays inside each wave's eighth of the LDS tile, Q1 / Q0 <-> Q2 go through
+// the whole tile; Q2 <-> Q3 exchanges two slot bits with lane bits 4 and 5
+// in registers (lane-permute swaps, no LDS). Q0 mixes e{0, 7, 8, 9}, Q1 e{1, 2,
+// 3, 4} when it is used, Q2 e{5, 6, 10} (and e4 otherwise), Q3 e{11, 12};
+// groups whose low run e{0..3} is not mixed skip Q1.
+struct QLay {
+    static constexpr int slot[4][4] = {{0, 7, 8, 9}, {1, 2, 3, 4}, {4, 5, 6, 10}, {4, 5, 12, 11}};
+    static constexpr int lane[4][6] = {{1, 2, 3, 4, 5, 6}, {0, 6, 7, 8, 5, 9}, {0, 1, 2, 3, 11, 12}, {0, 1, 2, 3, 10, 6}};
+    static constexpr int wave[4][3] = {{10, 11, 12}, {10, 11, 12}, {7, 8, 9}, {7, 8, 9}};
+};
+constexpr int kQThreads = 512;
+
+template <int LY>
+__device__ __forceinline__ uint32_t qt(uint32_t lane, uint32_t wave) {
+    uint32_t e = 0u;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e |= ((lane >> i) & 1u) << QLay::lane[LY][i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) e |= ((wave >> i) & 1u) << QLay::wave[LY][i];
+    return e;
+}
+template <int LY>
+__device__ __forceinline__ constexpr uint32_t qs(int j) {
+    uint32_t e = 0u;
+    for (int i = 0; i < 4; ++i) e |= (uint32_t)((j >> i) & 1) << QLay::slot[LY][i];
+    return e;
+}
+
+// Slot masks of the tile bits each layout mixes, for tile mask m. USE1: the
+// tile passes through Q1, which mixes e{1..4}; otherwise the masks of the
+// launch hold no bit of e{0..3} (a group whose low run is not mixed) and Q2
+// mixes e4.
+template <bool USE1>
+__device__ __forceinline__ uint32_t qsm0(uint32_t m) {
+    return (USE1 ? m & 1u : 0u) | ((m >> 6) & 0xeu);
+}
+__device__ __forceinline__ uint32_t qsm1(uint32_t m) { return (m >> 1) & 0xfu; }
+template <bool USE1>
+__device__ __forceinline__ uint32_t qsm2(uint32_t m) {
+    return (USE1 ? 0u : (m >> 4) & 1u) | ((m >> 4) & 6u) | ((m >> 7) & 8u);
+}
+__device__ __forceinline__ uint32_t qsm3(uint32_t m) { return ((m >> 10) & 4u) | ((m >> 8) & 8u); }
+// Slot bits each layout can mix at all (compile time): the other slot bits
+// get no butterfly and no pair term.
+template <bool USE1>
+constexpr uint32_t kQPoss0 = USE1 ? 0xfu : 0xeu;
+constexpr uint32_t kQPoss1 = 0xfu;
+template <bool USE1>
+constexpr uint32_t kQPoss2 = USE1 ? 0xeu : 0xfu;
+constexpr uint32_t kQPoss3 = 0xcu;
+
+// LDS positions (two padding slots per 64 elements, as for the forward
+// tiles): 16 consecutive lanes of Q1 and Q2 hit 16 distinct 8-byte bank
+// pairs, 8 consecutive lanes of Q0's 16-byte accesses 8 distinct 16-byte
+// groups.
+template <int LY>
+__device__ __forceinline__ void to_q(float2* lds, const float2 (&v)[16], uint32_t lane, uint32_t wave) {
+    float2* const b = lds + phys(qt<LY>(lane, wave));
+    if (LY == 0) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+            *(float4*)(b + phys(qs<0>(2 * jj))) = make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) b[phys(qs<LY>(j))] = v[j];
+    }
+}
+template <int LY>
+__device__ __forceinline__ void from_q(const float2* lds, float2 (&v)[16], uint32_t lane, uint32_t wave) {
+    const float2* const b = lds + phys(qt<LY>(lane, wave));
+    if (LY == 0) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const float4 q = *(const float4*)(b + phys(qs<0>(2 * jj)));
+            v[2 * jj] = make_float2(q.x, q.y);
+            v[2 * jj + 1] = make_float2(q.z, q.w);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = b[phys(qs<LY>(j))];
+    }
+}
+
+// Both states from layout FROM to layout TO through one LDS buffer. Q0 and
+// Q1 keep a wave's elements in the wave's own eighth of the buffer, so a
+// transpose between them needs no workgroup barrier; one from or to Q2 does,
+// and one whose writes from Q2 reach every eighth first waits for the reads
+// of the previous transpose into Q2.
+template <int FROM, int TO>
+__device__ __forceinline__ void q_xpose(float2* lds, float2 (&l)[16], float2 (&p)[16], uint32_t lane, uint32_t wave) {
+    constexpr bool CROSS = FROM == 2 || TO == 2;
+    auto sync = [] {
+        if (CROSS) __syncthreads();
+        else wave_lds_sync();
+    };
+    if (FROM == 2) __syncthreads();
+    to_q<FROM>(lds, l, lane, wave);
+    sync();
+    from_q<TO>(lds, l, lane, wave);
+    sync();
+    to_q<FROM>(lds, p, lane, wave);
+    sync();
+    from_q<TO>(lds, p, lane, wave);
+}
+
+// Q2 <-> Q3: slot bit 3 (e10) trades places with lane bit 4 (e11) and slot
+// bit 2 (e6) with lane bit 5 (e12). A 16-lane permute swap of registers
+// (A, B) leaves rows (A0, B0, A2, B2) in A and (A1, B1, A3, B3) in B, which
+// exchanges "which register" with lane bit 4; the 32-lane swap does the same
+// with lane bit 5. Each is its own inverse.
+__device__ __forceinline__ void swap_rows16(float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap_rows32(float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void q_swap23(float2 (&v)[16]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        swap_rows16(v[j].x, v[j | 8].x);
+        swap_rows16(v[j].y, v[j | 8].y);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & 4) continue;
+        swap_rows32(v[j].x, v[j | 4].x);
+        swap_rows32(v[j].y, v[j | 4].y);
+    }
+}
+
 // Im of sum over pairs on register bit S of conj(l_a) p_b + conj(l_b) p_a,
 // i.e. the pairs' share of Im <l|X|p> for that bit.
 template <int S>
-__device__ __forceinline__ float ipair(const float2 (&l)[32], const float2 (&p)[32]) {
+__device__ __forceinline__ float ipair(const float2 (&l)[16], const float2 (&p)[16]) {
     float acc = 0.f;
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
+    for (int j = 0; j < 16; ++j) {
         if (j & (1 << S)) continue;
         const float2 la = l[j], lb = l[j | (1 << S)], pa = p[j], pb = p[j | (1 << S)];
         acc = fmaf(la.x, pb.y, acc);
@@ -80,59 +227,89 @@ __device__ __forceinline__ float ipair(const float2 (&l)[32], const float2 (&p)[
 // factor f per qubit, so after k of them both states are 1/f^k of the exact
 // ones and the pair term is |f|^-2k of the exact term: w = |f|^2k restores it.
 template <int S>
-__device__ __forceinline__ void adj_bit(float2 (&l)[32], float2 (&p)[32], float t, float r, float& w, float& acc) {
-    acc = fmaf(w, ipair<S>(l, p), acc);
+__device__ __forceinline__ void adj_bit(float2 (&l)[16], float2 (&p)[16], float t, float r, float& w, float& acc,
+                                        bool on) {
+    acc = fmaf(on ? w : 0.f, ipair<S>(l, p), acc);
     w *= r;
-    bfly<32, S>(l, t);
-    bfly<32, S>(p, t);
+    bfly<16, S>(l, t);
+    bfly<16, S>(p, t);
 }
 
-__device__ __forceinline__ void adj_mix(float2 (&l)[32], float2 (&p)[32], uint32_t sm, float t, float r, float& w,
+// The slot bits in POSS as straight-line code: a bit the group does not mix
+// takes t = 0 (an exact identity), weight 0 and r = 1, so no branch splits
+// the register arrays.
+template <int S>
+__device__ __forceinline__ void adj_bit_sel(float2 (&l)[16], float2 (&p)[16], uint32_t sm, float t, float r, float& w,
+                                            float& acc) {
+    const bool on = (sm >> S) & 1u;
+    adj_bit<S>(l, p, on ? t : 0.f, on ? r : 1.f, w, acc, on);
+}
+template <uint32_t POSS>
+__device__ __forceinline__ void adj_mix(float2 (&l)[16], float2 (&p)[16], uint32_t sm, float t, float r, float& w,
                                         float& acc) {
-    if (sm & 1u) adj_bit<0>(l, p, t, r, w, acc);
-    if (sm & 2u) adj_bit<1>(l, p, t, r, w, acc);
-    if (sm & 4u) adj_bit<2>(l, p, t, r, w, acc);
-    if (sm & 8u) adj_bit<3>(l, p, t, r, w, acc);
-    if (sm & 16u) adj_bit<4>(l, p, t, r, w, acc);
+    if constexpr ((POSS & 1u) != 0u) adj_bit_sel<0>(l, p, sm, t, r, w, acc);
+    if constexpr ((POSS & 2u) != 0u) adj_bit_sel<1>(l, p, sm, t, r, w, acc);
+    if constexpr ((POSS & 4u) != 0u) adj_bit_sel<2>(l, p, sm, t, r, w, acc);
+    if constexpr ((POSS & 8u) != 0u) adj_bit_sel<3>(l, p, sm, t, r, w, acc);
+    // The pair sums are complete here: sunk below the next transpose or the
+    // stores, they would hold the values from before the butterflies.
+    asm volatile("" : "+v"(acc));
 }
 
-// Both register arrays from layout FROM to layout TO through one LDS buffer.
-template <int TB, int FROM, int TO>
-__device__ __forceinline__ void xpose2(float2* lds, float2 (&l)[32], float2 (&p)[32], uint32_t lane, uint32_t wave) {
-    __syncthreads();
-    to_lds<TB, FROM>(lds, l, lane, wave);
-    __syncthreads();
-    from_lds<TB, TO>(lds, l, lane, wave);
-    __syncthreads();
-    to_lds<TB, FROM>(lds, p, lane, wave);
-    __syncthreads();
-    from_lds<TB, TO>(lds, p, lane, wave);
+// One group's inverse mixing from layout Q0 to Q3 (pre) or from Q3 to Q0
+// (post), with the group's pair terms. USE1 is chosen per launch: a branch
+// around the transposes here raises the register demand from about 120 to
+// 160.
+template <bool USE1>
+__device__ __forceinline__ void q_mix_down(float2* lds, float2 (&l)[16], float2 (&p)[16], uint32_t m, float t, float r,
+                                           float& w, float& acc, uint32_t lane, uint32_t wave) {
+    adj_mix<kQPoss0<USE1>>(l, p, qsm0<USE1>(m), t, r, w, acc);
+    if constexpr (USE1) {
+        q_xpose<0, 1>(lds, l, p, lane, wave);
+        adj_mix<kQPoss1>(l, p, qsm1(m), t, r, w, acc);
+        q_xpose<1, 2>(lds, l, p, lane, wave);
+    } else {
+        q_xpose<0, 2>(lds, l, p, lane, wave);
+    }
+    adj_mix<kQPoss2<USE1>>(l, p, qsm2<USE1>(m), t, r, w, acc);
+    q_swap23(l);
+    q_swap23(p);
+    adj_mix<kQPoss3>(l, p, qsm3(m), t, r, w, acc);
+}
+template <bool USE1>
+__device__ __forceinline__ void q_mix_up(float2* lds, float2 (&l)[16], float2 (&p)[16], uint32_t m, float t, float r,
+                                         float& w, float& acc, uint32_t lane, uint32_t wave) {
+    adj_mix<kQPoss3>(l, p, qsm3(m), t, r, w, acc);
+    q_swap23(l);
+    q_swap23(p);
+    adj_mix<kQPoss2<USE1>>(l, p, qsm2<USE1>(m), t, r, w, acc);
+    if constexpr (USE1) {
+        q_xpose<2, 1>(lds, l, p, lane, wave);
+        adj_mix<kQPoss1>(l, p, qsm1(m), t, r, w, acc);
+        q_xpose<1, 0>(lds, l, p, lane, wave);
+    } else {
+        q_xpose<2, 0>(lds, l, p, lane, wave);
+    }
+    adj_mix<kQPoss0<USE1>>(l, p, qsm0<USE1>(m), t, r, w, acc);
 }
 
-// Every kind is register-allocated for two waves per SIMD: two states of 32
-// amplitudes per thread do not fit in 128 registers with the mixing's
-// temporaries, and the spills at two waves cost less than the latency left
-// unhidden at one (the inverse-mixer-only kinds 5% and the boundary kind,
-// after the fence before its inverse mixing, another 5% per gradient at
-// n = 22).
 // WEIGH (first sweep of the reverse pass, natural order): lam is not read but
 // formed as W psi from the loaded psi and cost, which saves a pass over both
 // states.
-template <typename CT, int KIND, bool WEIGH, bool STREAM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void adjoint_kernel(
+template <typename CT, int KIND, bool WEIGH, bool STREAM, bool USE1>
+__global__ __launch_bounds__(kQThreads) __attribute__((amdgpu_waves_per_eu(4))) void adjoint_kernel(
     const AdjointArgs a) {
     constexpr int TB = kAdjointTileBits;
-    constexpr int WB = TB - 11;
-    constexpr int NT = 64 << WB;
+    static_assert(TB == 13, "the reverse tile layouts cover 13 tile bits");
+    constexpr int NWV = kQThreads / 64;
     constexpr bool PHASE = KIND == AK_BOUNDARY || KIND == AK_END;
     constexpr bool POST = KIND == AK_BOUNDARY;
     constexpr bool LUT_LDS = sizeof(CT) == 1;
     constexpr int PK = 4 / (int)sizeof(CT);
-    constexpr int NC = PHASE ? 32 / PK : 1;
-    using L = Lay<TB>;
-    __shared__ float2 lds[lds_elems<TB>()];
+    constexpr int NC = PHASE ? 16 / PK : 1;
+    __shared__ __align__(16) float2 lds[lds_elems<TB>()];
     __shared__ float2 lut_s[PHASE && LUT_LDS ? 256 : 1];
-    __shared__ double red[3][1 << WB];
+    __shared__ double red[3][NWV];
 
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t t = blockIdx.x;
@@ -149,8 +326,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     };
     // Tiles dealt to the 8 XCDs round-robin in chunks of 16 consecutive tiles
     // (a bijection: ntiles is a power of two), so the XCDs work on
-    // neighbouring chunks at once: 1.3% per gradient at n = 22 against one
-    // contiguous eighth of the tiles per XCD (chunks of 32: 0.9%).
+    // neighbouring chunks at once.
     constexpr uint32_t kChunk = 16;
     uint64_t w = ntiles >= 8 * kChunk
         ? (uint64_t)((t >> 3) / kChunk) * (8 * kChunk) + (uint64_t)(t & 7u) * kChunk + ((t >> 3) % kChunk)
@@ -168,27 +344,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     const uint64_t all = (1ull << a.n) - 1ull;
     uint32_t cvp[NC];
     if (PHASE) {
-        const uint64_t ct = base + scat(L::t2(lane, wave));
+        const uint64_t ct = base + scat(qt<3>(lane, wave));
         const bool cf = a.cost_flip != 0ull;
-        const CT* const c2 = (const CT*)a.cost + (cf ? ct ^ all : ct);
+        const CT* const c3 = (const CT*)a.cost + (cf ? ct ^ all : ct);
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             uint32_t wv = 0u;
 #pragma unroll
             for (int q = 0; q < PK; ++q) {
-                const uint64_t d = scat(L::s2(PK * i + q));
-                wv |= (uint32_t)(cf ? c2[-(int64_t)d] : c2[d]) << (8 * sizeof(CT) * q);
+                const uint64_t d = scat(qs<3>(PK * i + q));
+                wv |= (uint32_t)(cf ? c3[-(int64_t)d] : c3[d]) << (8 * sizeof(CT) * q);
             }
             cvp[i] = wv;
         }
         // Pack the cost bytes as soon as they arrive (the state loads issued
-        // after them stay in flight): left to itself the compiler keeps the 32
-        // loaded bytes in 32 registers until the phase step, and the boundary
-        // kind spills 116 instead of 90 dwords at two waves per SIMD.
+        // after them stay in flight) instead of holding one register per byte
+        // until the phase step.
 #pragma unroll
         for (int i = 0; i < NC; ++i) asm volatile("" : "+v"(cvp[i]));
         if (LUT_LDS)
-            for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
+            for (int i = threadIdx.x; i < a.lut_len; i += kQThreads) lut_s[i] = a.lut[i];
     }
     const uint32_t lut_last = (uint32_t)a.lut_len - 1u;
     auto lut = [&](uint32_t cidx) -> float2 { return LUT_LDS ? lut_s[cidx] : a.lut[min(cidx, lut_last)]; };
@@ -196,17 +371,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
         return (cvp[j / PK] >> (8 * sizeof(CT) * (j % PK))) & (sizeof(CT) == 1 ? 0xffu : 0xffffu);
     };
 
-    // Layout L0 pairs tile bits 0 (global bit 0) in one float4: flipped, the
+    // Layout Q0 pairs tile bit 0 (global bit 0) in one float4: flipped, the
     // pair (x, x + 1) sits at (x ^ (2^n - 1) ^ 1, its successor) in reverse
     // order.
     const bool pf = a.psi_flip != 0;
-    float2 l[32], p[32];
+    float2 l[16], p[16];
     {
-        const uint64_t o0 = base + scat(L::t0(lane, wave));
+        const uint64_t o0 = base + scat(qt<0>(lane, wave));
         const float2* const pb = a.psi + (pf ? o0 ^ all ^ 1ull : o0);
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
-            const uint64_t d = scat(L::s0(2 * jj));
+        for (int jj = 0; jj < 8; ++jj) {
+            const uint64_t d = scat(qs<0>(2 * jj));
             const float4 qp = ld4<STREAM>(pf ? pb - d : pb + d);
             p[2 * jj] = pf ? make_float2(qp.z, qp.w) : make_float2(qp.x, qp.y);
             p[2 * jj + 1] = pf ? make_float2(qp.x, qp.y) : make_float2(qp.z, qp.w);
@@ -229,21 +404,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     }
     float acc_pre = 0.f, acc_g = 0.f, acc_post = 0.f;
     {
-        const uint32_t m = a.pre_mask;
-        float w = a.pre_w;
-        adj_mix(l, p, L::sm0(m), a.pre_t, a.pre_r, w, acc_pre);
-        if (L::sm1(m)) {
-            xpose2<TB, 0, 1>(lds, l, p, lane, wave);
-            adj_mix(l, p, L::sm1(m), a.pre_t, a.pre_r, w, acc_pre);
-            xpose2<TB, 1, 2>(lds, l, p, lane, wave);
-        } else {
-            xpose2<TB, 0, 2>(lds, l, p, lane, wave);
-        }
-        adj_mix(l, p, L::sm2(m), a.pre_t, a.pre_r, w, acc_pre);
+        float wt = a.pre_w;
+        q_mix_down<USE1>(lds, l, p, a.pre_mask, a.pre_t, a.pre_r, wt, acc_pre, lane, wave);
+        asm volatile("" : "+v"(acc_pre));
     }
     if (PHASE) {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
+        for (int j = 0; j < 16; ++j) {
             const uint32_t c = cval(j);
             const float im = fmaf(l[j].x, p[j].y, -l[j].y * p[j].x);
             acc_g = fmaf((float)c, im, acc_g);
@@ -251,56 +418,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
             l[j] = cmul(l[j], e);
             p[j] = cmul(p[j], e);
         }
+        asm volatile("" : "+v"(acc_g));
     }
-    // No memory access moves across this point: without it the compiler
-    // interleaves the phase step's table reads with the inverse mixing below
-    // and the boundary kind needs 440 registers instead of 344 (172 rather
-    // than 252 spilled at two waves per SIMD). It orders nothing that
-    // another thread depends on.
+    // No memory access moves across this point: left to itself the compiler
+    // interleaves the phase step's table reads with the inverse mixing below,
+    // which raises the register demand. It orders nothing that another thread
+    // depends on.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (POST) {
-        const uint32_t m = a.post_mask;
-        float w = a.post_w;
-        adj_mix(l, p, L::sm2(m), a.post_t, a.post_r, w, acc_post);
-        if (L::sm1(m)) {
-            xpose2<TB, 2, 1>(lds, l, p, lane, wave);
-            adj_mix(l, p, L::sm1(m), a.post_t, a.post_r, w, acc_post);
-            xpose2<TB, 1, 0>(lds, l, p, lane, wave);
-        } else {
-            xpose2<TB, 2, 0>(lds, l, p, lane, wave);
-        }
-        adj_mix(l, p, L::sm0(m), a.post_t, a.post_r, w, acc_post);
-        const uint64_t o0 = base + scat(L::t0(lane, wave));
+        float wt = a.post_w;
+        q_mix_up<USE1>(lds, l, p, a.post_mask, a.post_t, a.post_r, wt, acc_post, lane, wave);
+        // The pair sums are complete before the stores: left to itself the
+        // compiler sinks them below the stores and holds the states' values
+        // from before the last butterflies across them (40 spilled registers).
+        asm volatile("" : "+v"(acc_post));
+        const uint64_t o0 = base + scat(qt<0>(lane, wave));
         float2* const pb = a.psi + (pf ? o0 ^ all ^ 1ull : o0);
-        // lam's stores, then psi's under a branch on the (uniform) relabelling:
-        // one loop selecting order and address per element spills 161 instead
-        // of 64 dwords per lane in this kind.
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
-            const uint64_t d = scat(L::s0(2 * jj));
+        for (int jj = 0; jj < 8; ++jj) {
+            const uint64_t d = scat(qs<0>(2 * jj));
             st4<STREAM>(a.lam + o0 + d, make_float4(l[2 * jj].x, l[2 * jj].y, l[2 * jj + 1].x, l[2 * jj + 1].y));
         }
         if (a.store_psi) {
             if (pf) {
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj)
-                    st4<STREAM>(pb - scat(L::s0(2 * jj)),
-                            make_float4(p[2 * jj + 1].x, p[2 * jj + 1].y, p[2 * jj].x, p[2 * jj].y));
+                for (int jj = 0; jj < 8; ++jj)
+                    st4<STREAM>(pb - scat(qs<0>(2 * jj)),
+                                make_float4(p[2 * jj + 1].x, p[2 * jj + 1].y, p[2 * jj].x, p[2 * jj].y));
             } else {
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj)
-                    st4<STREAM>(pb + scat(L::s0(2 * jj)),
-                            make_float4(p[2 * jj].x, p[2 * jj].y, p[2 * jj + 1].x, p[2 * jj + 1].y));
+                for (int jj = 0; jj < 8; ++jj)
+                    st4<STREAM>(pb + scat(qs<0>(2 * jj)),
+                                make_float4(p[2 * jj].x, p[2 * jj].y, p[2 * jj + 1].x, p[2 * jj + 1].y));
             }
         }
     } else {
-        const uint64_t o2 = base + scat(L::t2(lane, wave));
-        float2* const pb = a.psi + (pf ? o2 ^ all : o2);
+        const uint64_t o3 = base + scat(qt<3>(lane, wave));
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const uint64_t d = scat(L::s2(j));
-            st2<STREAM>(a.lam + o2 + d, l[j]);
-            if (a.store_psi) st2<STREAM>(pf ? pb - d : pb + d, p[j]);
+        for (int j = 0; j < 16; ++j) st2<STREAM>(a.lam + o3 + scat(qs<3>(j)), l[j]);
+        if (a.store_psi) {
+            float2* const pb = a.psi + (pf ? o3 ^ all : o3);
+            if (pf) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) st2<STREAM>(pb - scat(qs<3>(j)), p[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) st2<STREAM>(pb + scat(qs<3>(j)), p[j]);
+            }
         }
     }
     double d0 = acc_pre, d1 = acc_g, d2 = acc_post;
@@ -317,7 +481,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
     __syncthreads();
     if (threadIdx.x < 3) {
         double sum = 0.0;
-        for (int q = 0; q < (1 << WB); ++q) sum += red[threadIdx.x][q];
+        for (int q = 0; q < NWV; ++q) sum += red[threadIdx.x][q];
         a.partials[3 * (size_t)t + threadIdx.x] = sum;
     }
 }
@@ -460,21 +624,30 @@ __global__ __launch_bounds__(kResidentGradThreads) void resident_grad_batch_kern
     resident_grad_body<CT>(a);
 }
 
-template <typename CT, bool NT>
-hipError_t launch_adjoint_ct(int kind, const AdjointArgs& a, hipStream_t s, bool weigh) {
-    const dim3 grid(1u << a.nw), block(256);
+template <typename CT, bool NT, bool USE1>
+hipError_t launch_adjoint_q(int kind, const AdjointArgs& a, hipStream_t s, bool weigh) {
+    const dim3 grid(1u << a.nw), block(kQThreads);
     if (weigh) {
         if (kind != AK_MIDDLE || a.psi_flip || a.cost_flip) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((adjoint_kernel<CT, AK_MIDDLE, true, NT>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((adjoint_kernel<CT, AK_MIDDLE, true, NT, USE1>), grid, block, 0, s, a);
         return hipGetLastError();
     }
     switch (kind) {
-        case AK_MIDDLE: hipLaunchKernelGGL((adjoint_kernel<CT, AK_MIDDLE, false, NT>), grid, block, 0, s, a); break;
-        case AK_BOUNDARY: hipLaunchKernelGGL((adjoint_kernel<CT, AK_BOUNDARY, false, NT>), grid, block, 0, s, a); break;
-        case AK_END: hipLaunchKernelGGL((adjoint_kernel<CT, AK_END, false, NT>), grid, block, 0, s, a); break;
+        case AK_MIDDLE: hipLaunchKernelGGL((adjoint_kernel<CT, AK_MIDDLE, false, NT, USE1>), grid, block, 0, s, a); break;
+        case AK_BOUNDARY:
+            hipLaunchKernelGGL((adjoint_kernel<CT, AK_BOUNDARY, false, NT, USE1>), grid, block, 0, s, a);
+            break;
+        case AK_END: hipLaunchKernelGGL((adjoint_kernel<CT, AK_END, false, NT, USE1>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename CT, bool NT>
+hipError_t launch_adjoint_ct(int kind, const AdjointArgs& a, hipStream_t s, bool weigh) {
+    const uint32_t masks = a.pre_mask | (kind == AK_BOUNDARY ? a.post_mask : 0u);
+    return (masks & 0xfu) != 0u ? launch_adjoint_q<CT, NT, true>(kind, a, s, weigh)
+                                : launch_adjoint_q<CT, NT, false>(kind, a, s, weigh);
 }
 
 }  // namespace

@@ -49,12 +49,13 @@ def short_name(name: str) -> str:
         ckpt = "_ckpt" if m.group(5) == "true" else ""
         return (f"sweep_kernel<TB={m.group(1)},{m.group(2).replace('unsigned ', 'u')}{half}> "
                 f"{KIND_NAMES[m.group(3)]}{ckpt}")
-    m = re.match(r"void adjoint_kernel<([a-z ]+), (\d)(?:, (true|false))?(?:, (true|false))?>", name)
+    m = re.match(r"void adjoint_kernel<([a-z ]+), (\d)(?:, (true|false))?(?:, (true|false))?(?:, (true|false))?>", name)
     if m:
         kind = {"0": "middle", "1": "boundary", "2": "end"}[m.group(2)]
         weigh = "_weigh" if m.group(3) == "true" else ""
         stream = ",stream" if m.group(4) == "true" else ""
-        return f"adjoint_kernel<{m.group(1).replace('unsigned ', 'u')}{stream}> adjoint_{kind}{weigh}"
+        q1 = ",q1" if m.group(5) == "true" else ""
+        return f"adjoint_kernel<{m.group(1).replace('unsigned ', 'u')}{stream}{q1}> adjoint_{kind}{weigh}"
     return name.split("(")[0].replace("void ", "")
 
 
