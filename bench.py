@@ -511,6 +511,34 @@ def grad_bench(q, ctx, reps=20, adam_steps=200):
                        "forward_ms": t_fwd2 * 1e3, "grad_ms": t_grad2 * 1e3, "grad_over_forward": t_grad2 / t_fwd2}}
 
 
+def gradient_only(n, reps):
+    """The gradient leg's recipe at one size (the stored n = 22 workload, or a
+    random instance with m = round(2.1 n) for other n): one forward run, then
+    `reps` gradients; prints the mean gradient time. For profiling runs."""
+    import torch
+    import paper_2401_02852_amd as q
+    from workloads import instances as inst
+    torch.cuda.set_device(0)
+    ctx = q.Context(0)
+    if n == 22:
+        _, cl, g0, b0 = load_workload("nae3_n22_p12")
+        m = len(cl)
+    else:
+        m = inst.clause_count(n, 2.1)
+        cl = inst.instance(n, 3, m, 0)
+        g0, b0 = inst.ramp_angles(12)
+    b0 = -b0
+    cost = q.build_cost_diagonal(cl, n, ctx=ctx)
+    q.qaoa_run(cost, n, m, g0, b0, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q.qaoa_grad(cost, n, m, g0, b0, w_psucc=1.0, w_energy=0.0, checkpoint_every=4, ctx=ctx)
+    torch.cuda.synchronize()
+    print(json.dumps({"gradient_only": {"n": n, "m": m, "p": len(g0), "reps": reps,
+                                        "grad_ms": (time.perf_counter() - t0) * 1e3 / reps}}))
+
+
 def serving_bench(q, ctx, count=2000, warm=100, rate=200.0, autotune=True):
     """Poisson request trace (n 14..26, p 2..20, k in {3, 5}) through the
     continuous-batching server and through the plain path one request at a
@@ -626,6 +654,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (reference for HBM byte counters)")
+    ap.add_argument("--gradient-only", type=int, default=0, metavar="N",
+                    help="only run the gradient recipe (p = 12 linear ramp, checkpoints every 4) at n = N: "
+                         "one forward run and --steps gradients, for profiling")
     args = ap.parse_args()
     if args.headline_only:
         for leg in ("cpu_baseline", "scale", "latency", "batched", "serving", "grad", "sampling", "z2", "pretrain",
@@ -639,6 +670,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy << 20}))
+        return
+    if args.gradient_only:
+        gradient_only(args.gradient_only, max(args.steps, 1))
         return
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "

@@ -29,16 +29,24 @@ from collections import OrderedDict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/sweep.hip", "csrc/tile.h", "csrc/cost.hip"]
+ADJOINT_SOURCES = ["csrc/adjoint.hip", "csrc/tile.h"]
 
 KIND_NAMES = {"0": "sweep_first", "1": "sweep_middle", "2": "sweep_boundary", "3": "sweep_final", "4": "sweep_p0"}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
+    """Hash of the forward kernels' sources (the headline traffic figure is
+    tied to it), or of the given sources."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def _hash_lines():
+    return [f"kernel_sources_sha256_16: {kernel_source_hash()}",
+            f"adjoint_sources_sha256_16: {kernel_source_hash(ADJOINT_SOURCES)}"]
 
 
 def short_name(name: str) -> str:
@@ -61,8 +69,7 @@ def short_name(name: str) -> str:
 
 def trace(dirpath, prefix, out, cmd):
     rows = list(csv.DictReader(open(os.path.join(dirpath, f"{prefix}_kernel_stats.csv"))))
-    lines = [f"# rocprofv3 kernel trace summary", f"command: {cmd}",
-             f"kernel_sources_sha256_16: {kernel_source_hash()}", "",
+    lines = [f"# rocprofv3 kernel trace summary", f"command: {cmd}", *_hash_lines(), "",
              f"{'kernel':62s} {'calls':>6s} {'avg_ms':>9s} {'min_ms':>9s} {'max_ms':>9s} {'pct':>6s}"]
     for r in rows:
         lines.append(f"{short_name(r['Name']):62s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:9.4f} "
@@ -97,7 +104,7 @@ def pmc(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, n, out, cmd):
     amps = float(2 ** n)
     lines = ["# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate runs)",
              f"command: {cmd}",
-             f"kernel_sources_sha256_16: {kernel_source_hash()}",
+             *_hash_lines(),
              f"copy_calibration: plain device copy of {copy_bytes} bytes; FETCH_SIZE scale {fscale:.4f}, "
              f"WRITE_SIZE scale {wscale:.4f} (bytes per counter KiB / 1024)",
              f"state_amplitudes: {int(amps)}", "",
@@ -122,7 +129,7 @@ def counters(out, cmd, csvs):
             a[0] += 1
             a[1] += float(r["Counter_Value"])
     lines = ["# rocprofv3 counters per launch (average over launches of each kernel kind)", f"command: {cmd}",
-             f"kernel_sources_sha256_16: {kernel_source_hash()}", "",
+             *_hash_lines(), "",
              f"{'kernel':62s} " + " ".join(f"{c:>34s}" for c in names)]
     for k, per in agg.items():
         lines.append(f"{k:62s} " + " ".join(f"{per[c][1] / per[c][0]:34.1f}" if c in per else f"{'-':>34s}"
