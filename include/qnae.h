@@ -376,11 +376,14 @@ typedef struct {
 } qnae_tune;
 
 /* Times every candidate shape (tile_bits 12..14 x low_run_bits 4..5 x
- * page_bit 18 or 64, split 0; then splits 1..3 of the fastest of those, when
- * its groups have a third) on `reps` two-layer runs of an n-qubit state in the
- * context's scratch memory, on `stream`, keeps the fastest for later
- * qnae_qaoa_run calls at this n and cost type on this context, and writes it
- * to *out. Needs 2^n * (8 + cost bytes) of device memory. For n <= 14 the
+ * page_bit 18 or 64, split 0; then splits 1..3 of the fastest of those for
+ * each tile size, when its groups have a third) on `reps` two-layer and
+ * `reps` four-layer runs of
+ * an n-qubit state in the context's scratch memory, on `stream`, ranks them
+ * by the time per layer of a ten-layer run (extrapolated linearly in the
+ * layer count from the two; written to ms_per_layer), keeps the fastest for
+ * later qnae_qaoa_run calls at this n and cost type on this context, and
+ * writes it to *out. Needs 2^n * (8 + cost bytes) of device memory. For n <= 14 the
  * whole circuit runs in one workgroup and there is nothing to tune: *out is
  * all zeros. Synchronous. Errors: QNAE_EINVAL (n outside [1, QNAE_MAX_N], bad
  * cost_dtype, reps outside [1, 1000], null out), QNAE_ENOMEM, QNAE_EHIP. */

@@ -87,8 +87,13 @@ __device__ __forceinline__ void move(float* lds, float2 (&v)[32], uint32_t lane,
 }
 
 // One workgroup's work on tile t of one sweep. Readout kinds write the three
-// block sums to partial[0..2].
-template <int TB, typename CT, int KIND, bool HALF, bool CKPT = false>
+// block sums to partial[0..2]. L1M: whether the mixing passes through layout
+// L1 is decided per tile from the masks (0, ragged batches), or fixed for the
+// launch (1 through L1, 2 not): a branch around the transposes raises the
+// register demand (with 14-bit tiles at four waves per SIMD the boundary
+// kind spilled 21 instead of 3 dwords per lane, the final kind 15 instead of
+// none).
+template <int TB, typename CT, int KIND, bool HALF, bool CKPT = false, int L1M = 0>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, double* partial) {
     constexpr int WB = TB - 11;
     constexpr int NT = 64 << WB;
@@ -245,7 +250,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         const uint32_t m = a.post_mask;
         const float tt = a.post_t;
         mix32<UNCOND>(v, L::sm0(m), tt);
-        if (L::sm1(m)) {
+        if (L1M == 1 || (L1M == 0 && L::sm1(m))) {
             move<TB, PLANES, 0, 1, false>(lds, v, lane, wave);  // inside the wave's quarter
             mix32<UNCOND>(v, L::sm1(m), tt);
             wave_lds_sync();
@@ -291,7 +296,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         const uint32_t m = a.pre_mask;
         const float tt = a.pre_t;
         mix32<UNCOND>(v, L::sm0(m), tt);
-        if (L::sm1(m)) {
+        if (L1M == 1 || (L1M == 0 && L::sm1(m))) {
             move<TB, PLANES, 0, 1, false>(lds, v, lane, wave);  // inside the wave's quarter
             mix32<UNCOND>(v, L::sm1(m), tt);
             wave_lds_sync();
@@ -326,7 +331,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
         const float tt = a.post_t;
         mix32<UNCOND>(v, L::sm2(m), tt);
         if (PRE) __syncthreads();  // every wave has read its L2 part
-        if (L::sm1(m)) {
+        if (L1M == 1 || (L1M == 0 && L::sm1(m))) {
             move<TB, PLANES, 2, 1, true>(lds, v, lane, wave);
             mix32<UNCOND>(v, L::sm1(m), tt);
             wave_lds_sync();
@@ -399,10 +404,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
 }
 
 // One sweep over one state: block b handles tile b.
-template <int TB, typename CT, int KIND, bool HALF = false, bool CKPT = false>
+template <int TB, typename CT, int KIND, bool HALF = false, bool CKPT = false, int L1M = 0>
 __global__ __launch_bounds__(64 << (TB - 11)) __attribute__((amdgpu_waves_per_eu(sweep_waves(TB, KIND, HALF)))) void sweep_kernel(
     const SweepArgs a) {
-    sweep_tile<TB, CT, KIND, HALF, CKPT>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
+    sweep_tile<TB, CT, KIND, HALF, CKPT, L1M>(a, blockIdx.x, a.partials + 3 * (size_t)blockIdx.x);
+}
+
+// L1M of a single-state launch: 1 when a mask the kind mixes has bits that
+// only layout L1 holds, else 2.
+template <int TB, int KIND>
+int sweep_l1_mode(const SweepArgs& a) {
+    using L = Lay<TB>;
+    const bool pre = KIND == SK_MIDDLE || KIND == SK_BOUNDARY || KIND == SK_FINAL;
+    const bool post = KIND == SK_FIRST || KIND == SK_BOUNDARY;
+    const bool l1 = (pre && L::sm1(a.pre_mask) != 0u) || (post && L::sm1(a.post_mask) != 0u);
+    return l1 ? 1 : 2;
 }
 
 // Instance of work item b in a ragged batch: the largest i with first[i] <= b.
@@ -591,12 +607,26 @@ __global__ __launch_bounds__(1024) void final_reduce_batch_kernel(const double* 
     final_reduce_body(partials[blockIdx.x], blocks[blockIdx.x], outs[blockIdx.x]);
 }
 
+template <int TB, typename CT, int KIND, int L1M>
+void launch_kind_l1(const SweepArgs& a, hipStream_t s) {
+    if (a.half && a.vbit >= 0)
+        hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND, true, false, L1M>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND, false, false, L1M>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0,
+                           s, a);
+}
+
+// The L1 choice is fixed per launch, except in the first and final kinds of
+// 13-bit tiles, which measured faster with the per-tile branch at n = 30
+// (1.81 and 1.62 ms against 1.93 and 1.75 ms: the first kind fits four
+// workgroups per CU without the branch instead of three, and that is
+// slower for this write-only kind).
 template <int TB, typename CT, int KIND>
 hipError_t launch_kind(const SweepArgs& a, hipStream_t s) {
-    if (a.half && a.vbit >= 0)
-        hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND, true>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0, s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<TB, CT, KIND, false>), dim3(1u << a.nw), dim3(64 << (TB - 11)), 0, s, a);
+    if (TB == 13 && (KIND == SK_FIRST || KIND == SK_FINAL)) launch_kind_l1<TB, CT, KIND, 0>(a, s);
+    else if (KIND == SK_P0 || sweep_l1_mode<TB, KIND>(a) == 2) launch_kind_l1<TB, CT, KIND, 2>(a, s);
+    else launch_kind_l1<TB, CT, KIND, 1>(a, s);
     return hipGetLastError();
 }
 
@@ -674,10 +704,14 @@ hipError_t launch_sweep_ckpt(int dtype, const SweepArgs& a, hipStream_t s) {
     constexpr int TB = kAdjointTileBits;
     if (a.half || !a.ckpt || a.nw < 0) return hipErrorInvalidValue;
     const dim3 grid(1u << a.nw), block(64 << (TB - 11));
-    if (dtype == 1)
-        hipLaunchKernelGGL((sweep_kernel<TB, uint8_t, SK_BOUNDARY, false, true>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<TB, uint16_t, SK_BOUNDARY, false, true>), grid, block, 0, s, a);
+    const bool l1 = sweep_l1_mode<TB, SK_BOUNDARY>(a) == 1;
+    if (dtype == 1) {
+        if (l1) hipLaunchKernelGGL((sweep_kernel<TB, uint8_t, SK_BOUNDARY, false, true, 1>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<TB, uint8_t, SK_BOUNDARY, false, true, 2>), grid, block, 0, s, a);
+    } else {
+        if (l1) hipLaunchKernelGGL((sweep_kernel<TB, uint16_t, SK_BOUNDARY, false, true, 1>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<TB, uint16_t, SK_BOUNDARY, false, true, 2>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -103,10 +103,12 @@ struct Lay {
         return e;
     }
     // Does L1 mix tile bits 4 and 5 for mask m?
-    __device__ static __forceinline__ bool r1_takes_45(uint32_t m) { return !L2_HAS_45 || (m & 0xeu) != 0u; }
+    __host__ __device__ static __forceinline__ constexpr bool r1_takes_45(uint32_t m) {
+        return !L2_HAS_45 || (m & 0xeu) != 0u;
+    }
     // Slot masks of the tile bits each round mixes.
     __device__ static __forceinline__ uint32_t sm0(uint32_t m) { return (m & 1u) | (((m >> 7) & 15u) << 1); }
-    __device__ static __forceinline__ uint32_t sm1(uint32_t m) {
+    __host__ __device__ static __forceinline__ constexpr uint32_t sm1(uint32_t m) {
         return r1_takes_45(m) ? (m >> 1) & 31u : (m >> 1) & 7u;
     }
     __device__ static __forceinline__ uint32_t sm2(uint32_t m) {

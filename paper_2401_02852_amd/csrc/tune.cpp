@@ -1,8 +1,11 @@
 // Sweep tile-shape autotuning (include/qnae.h, qnae_autotune / qnae_set_tune /
-// qnae_get_tune). A candidate is timed on two-layer runs of the real sweep
-// kernels over scratch memory: cost diagonal all zero, phase tables of 64
-// entries, angles away from the special values, so every sweep kind of a
-// p >= 2 plan runs (first, middle, boundary, final).
+// qnae_get_tune). A candidate is timed on two- and four-layer runs of the
+// real sweep kernels over scratch memory: the cost diagonal of a fixed
+// random 3-NAE-SAT instance with 63 clauses (so the phase-table reads spread
+// over the table as in real runs; an all-zero diagonal makes every read the
+// same entry), phase tables of 64 entries, angles away from the special
+// values, so every sweep kind of a p >= 2 plan runs (first, middle,
+// boundary, final).
 #include <algorithm>
 #include <chrono>
 #include <string>
@@ -42,6 +45,33 @@ bool has_split(int n, const qnae_tune& t) {
     return make_group_specs(n, t.tile_bits, t.low_run_bits, t.page_bit, 0, spec) == 3;
 }
 
+// The fixed tuning instance: m clauses of 3 distinct variables below n with
+// random signs, from a splitmix64 stream with a fixed seed (n >= 3).
+std::vector<int32_t> tuning_clauses(int n, int m) {
+    uint64_t state = 0x9e3779b97f4a7c15ull;
+    auto next = [&state]() {
+        uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    };
+    std::vector<int32_t> lits;
+    lits.reserve((size_t)3 * m);
+    for (int c = 0; c < m; ++c) {
+        int v[3];
+        for (int i = 0; i < 3; ++i) {
+            bool fresh;
+            do {
+                v[i] = (int)(next() % (uint64_t)n);
+                fresh = true;
+                for (int j = 0; j < i; ++j) fresh = fresh && v[j] != v[i];
+            } while (!fresh);
+            lits.push_back((next() & 1u) ? -(v[i] + 1) : v[i] + 1);
+        }
+    }
+    return lits;
+}
+
 int check_tune_target(int32_t n, int32_t dtype, int32_t lo) {
     if (n < lo || n > QNAE_MAX_N) return fail(QNAE_EINVAL, "n=%d outside [%d, %d]", n, lo, QNAE_MAX_N);
     if (dtype != QNAE_U8 && dtype != QNAE_U16) return fail(QNAE_EINVAL, "cost_dtype=%d is not QNAE_U8/QNAE_U16", dtype);
@@ -60,8 +90,13 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     *out = qnae_tune{0, 0, 0, 0, 0.0};
     if (n <= kResidentMaxN) return QNAE_OK;
     hipStream_t s = (hipStream_t)stream;
-    const int p = 2, m = 63, lut_len = m + 1;
-    const double gammas[p] = {0.4, 0.7}, betas[p] = {0.3, 0.2};
+    // Two- and four-layer runs; a shape is ranked by its time per layer of a
+    // ten-layer run, extrapolated linearly in the layer count (a two-layer
+    // run alone gives its first and last sweeps two of five sweeps instead
+    // of two of 21, and ranked 14-bit tiles first at n = 28 and 30, where a
+    // ten-layer run on them was 2-5% slower).
+    const int p = 4, p_lo = 2, m = 63, lut_len = m + 1;
+    const double gammas[p] = {0.4, 0.7, 0.5, 0.3}, betas[p] = {0.3, 0.2, 0.25, 0.15};
     HIP_TRY(ctx->h_luts.reserve(sizeof(float2) * p * lut_len));
     HIP_TRY(ctx->h_forms.reserve(sizeof(MixForm) * p));
     float2* tables = (float2*)ctx->h_luts.ptr;
@@ -72,7 +107,12 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     HIP_TRY(ctx->state.reserve(sizeof(float2) << n));
     const size_t cbytes = (size_t)(cost_dtype == QNAE_U8 ? 1 : 2) << n;
     HIP_TRY(ctx->tune_cost.reserve(cbytes));
-    HIP_TRY(hipMemsetAsync(ctx->tune_cost.ptr, 0, cbytes, s));
+    {
+        const std::vector<int32_t> lits = tuning_clauses(n, m);
+        if (int rc = qnae_build_cost_diagonal(ctx, lits.data(), m, n, 3, ctx->tune_cost.ptr, cost_dtype, nullptr,
+                                              stream))
+            return rc;
+    }
     HIP_TRY(ctx->partials.reserve(sizeof(double) * 3 * ((size_t)1 << (n - 12))));
     HIP_TRY(hipEventRecord(ctx->staging_done, s));
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -92,28 +132,41 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     };
     qnae_tune best{0, 0, 0, 0, 1e300};
     hipError_t err = hipSuccess;
-    auto time_shape = [&](const qnae_tune& t) {
+    // Mean time of one run of an `layers`-layer plan under shape t.
+    auto time_plan = [&](const qnae_tune& t, int layers, double* ms_out) -> hipError_t {
         SweepPlan P;
-        plan_sweeps(P, n, m, p, cost_dtype, t.tile_bits, t.low_run_bits, t.page_bit, t.split, false, forms,
+        plan_sweeps(P, n, m, layers, cost_dtype, t.tile_bits, t.low_run_bits, t.page_bit, t.split, false, forms,
                     final_scale);
-        if ((err = run(P, t.tile_bits))) return;  // warm-up
-        if ((err = hipEventRecord(ev[0], s))) return;
-        for (int r = 0; r < reps && !err; ++r) err = run(P, t.tile_bits);
-        if (err || (err = hipEventRecord(ev[1], s)) || (err = hipEventSynchronize(ev[1]))) return;
+        hipError_t e = run(P, t.tile_bits);  // warm-up
+        if (e || (e = hipEventRecord(ev[0], s))) return e;
+        for (int r = 0; r < reps && !e; ++r) e = run(P, t.tile_bits);
+        if (e || (e = hipEventRecord(ev[1], s)) || (e = hipEventSynchronize(ev[1]))) return e;
         float ms = 0.f;
-        if ((err = hipEventElapsedTime(&ms, ev[0], ev[1]))) return;
-        const double per_layer = ms / (double)(reps * p);
-        if (per_layer < best.ms_per_layer) best = qnae_tune{t.tile_bits, t.low_run_bits, t.page_bit, t.split, per_layer};
+        if ((e = hipEventElapsedTime(&ms, ev[0], ev[1]))) return e;
+        *ms_out = ms / reps;
+        return hipSuccess;
+    };
+    qnae_tune best_of[3] = {best, best, best};  // fastest split-0 shape per tile size
+    auto time_shape = [&](const qnae_tune& t) {
+        double t_lo = 0.0, t_hi = 0.0;
+        if ((err = time_plan(t, p_lo, &t_lo)) || (err = time_plan(t, p, &t_hi))) return;
+        const double ten = t_lo + (10.0 - p_lo) * (t_hi - t_lo) / (p - p_lo);
+        const qnae_tune timed{t.tile_bits, t.low_run_bits, t.page_bit, t.split, ten / 10.0};
+        if (timed.ms_per_layer < best.ms_per_layer) best = timed;
+        qnae_tune& b = best_of[t.tile_bits - 12];
+        if (t.split == 0 && timed.ms_per_layer < b.ms_per_layer) b = timed;
     };
     for (int TB = 12; TB <= 14 && !err; ++TB)
         for (int low = 4; low <= 5 && !err; ++low)
             for (int page : {18, 64})
                 if (!err) time_shape(qnae_tune{TB, low, page, 0, 0.0});
-    if (!err && has_split(n, best)) {
-        const qnae_tune base = best;
-        for (int split = 1; split <= 3 && !err; ++split)
-            time_shape(qnae_tune{base.tile_bits, base.low_run_bits, base.page_bit, split, 0.0});
-    }
+    // The splits of the fastest shape of every tile size: a split can
+    // reorder the tile sizes (at n = 30, 14-bit tiles led 13-bit ones
+    // without splits, and 13-bit tiles with split 1 were fastest overall).
+    for (const qnae_tune& base : best_of)
+        if (!err && base.tile_bits != 0 && has_split(n, base))
+            for (int split = 1; split <= 3 && !err; ++split)
+                time_shape(qnae_tune{base.tile_bits, base.low_run_bits, base.page_bit, split, 0.0});
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (err) return fail(QNAE_EHIP, "autotune: %s", hipGetErrorString(err));
@@ -159,6 +212,7 @@ int qnae_autotune_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
     std::vector<qnae_result> res((size_t)count);
     const auto saved = ctx->tunes;
     qnae_tune best{0, 0, 0, 0, 1e300};
+    qnae_tune best_of[3] = {best, best, best};  // fastest split-0 shape per tile size
     auto time_shape = [&](const qnae_tune& shape) -> int {
         for (const auto& c : classes) ctx->tunes[c] = shape;
         // one warm-up run plans the shape and captures its launches
@@ -173,20 +227,24 @@ int qnae_autotune_batched(qnae_ctx* ctx, const qnae_instance* inst, int32_t coun
         const double ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
         const double per_layer = ms / std::max(layers, 1);
-        if (per_layer < best.ms_per_layer)
-            best = qnae_tune{shape.tile_bits, shape.low_run_bits, shape.page_bit, shape.split, per_layer};
+        const qnae_tune timed{shape.tile_bits, shape.low_run_bits, shape.page_bit, shape.split, per_layer};
+        if (per_layer < best.ms_per_layer) best = timed;
+        qnae_tune& b = best_of[shape.tile_bits - 12];
+        if (shape.split == 0 && per_layer < b.ms_per_layer) b = timed;
         return QNAE_OK;
     };
     for (int TB = 12; TB <= 14; ++TB)
         for (int low = 4; low <= 5; ++low)
             for (int page : {18, 64})
                 if (int rc = time_shape(qnae_tune{TB, low, page, 0, 0.0})) return rc;
-    bool splits = false;
-    for (const auto& c : classes) splits |= has_split(c.first, best);
-    if (splits) {
-        const qnae_tune base = best;
-        for (int split = 1; split <= 3; ++split)
-            if (int rc = time_shape(qnae_tune{base.tile_bits, base.low_run_bits, base.page_bit, split, 0.0})) return rc;
+    // the splits of the fastest shape of every tile size, as qnae_autotune
+    for (const qnae_tune& base : best_of) {
+        bool splits = false;
+        for (const auto& c : classes) splits |= base.tile_bits != 0 && has_split(c.first, base);
+        if (splits)
+            for (int split = 1; split <= 3; ++split)
+                if (int rc = time_shape(qnae_tune{base.tile_bits, base.low_run_bits, base.page_bit, split, 0.0}))
+                    return rc;
     }
     for (const auto& c : classes) ctx->tunes[c] = best;
     *out = best;
