@@ -51,7 +51,9 @@ def _hash_lines():
 
 def short_name(name: str) -> str:
     name = re.sub(r"qnae::\(anonymous namespace\)::", "", name)
-    m = re.match(r"void sweep_kernel<(\d+), ([a-z ]+), (\d)(?:, (true|false))?(?:, (true|false))?>", name)
+    # (a sixth argument, whether the tiles pass through layout L1, is not
+    # shown: both variants of a kind move the same bytes and are summed)
+    m = re.match(r"void sweep_kernel<(\d+), ([a-z ]+), (\d)(?:, (true|false))?(?:, (true|false))?(?:, \d)?>", name)
     if m:
         half = ",half" if m.group(4) == "true" else ""
         ckpt = "_ckpt" if m.group(5) == "true" else ""
@@ -71,9 +73,16 @@ def trace(dirpath, prefix, out, cmd):
     rows = list(csv.DictReader(open(os.path.join(dirpath, f"{prefix}_kernel_stats.csv"))))
     lines = [f"# rocprofv3 kernel trace summary", f"command: {cmd}", *_hash_lines(), "",
              f"{'kernel':62s} {'calls':>6s} {'avg_ms':>9s} {'min_ms':>9s} {'max_ms':>9s} {'pct':>6s}"]
+    agg = OrderedDict()  # rows of one short name summed
     for r in rows:
-        lines.append(f"{short_name(r['Name']):62s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:9.4f} "
-                     f"{float(r['MinNs']) / 1e6:9.4f} {float(r['MaxNs']) / 1e6:9.4f} {float(r['Percentage']):6.2f}")
+        a = agg.setdefault(short_name(r["Name"]), [0, 0.0, float("inf"), 0.0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["AverageNs"]) * int(r["Calls"])
+        a[2] = min(a[2], float(r["MinNs"]))
+        a[3] = max(a[3], float(r["MaxNs"]))
+        a[4] += float(r["Percentage"])
+    for k, (calls, tot, lo, hi, pct) in sorted(agg.items(), key=lambda kv: -kv[1][4]):
+        lines.append(f"{k:62s} {calls:6d} {tot / calls / 1e6:9.4f} {lo / 1e6:9.4f} {hi / 1e6:9.4f} {pct:6.2f}")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
