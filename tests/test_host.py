@@ -357,3 +357,32 @@ def test_prepared_batch_marshalling_without_gpu():
     cb = b.PreparedCostBuild([cl, inst.instance(11, 3, 5, 1)], [10, 11], outs=costs, ctx=ctx)
     with pytest.raises(b.QNAEError, match="null context"):
         cb.build(count_solutions=True, stream=0)
+
+
+def test_profile_summaries_name_and_sum_kernel_variants(tmp_path):
+    """Profile summaries: short kernel names for every template form the
+    library launches, and one row per short name (the per-launch layout
+    variants of a sweep kind summed, calls weighting the average)."""
+    from paper_2401_02852_amd import profiling as pr
+    ns = "void qnae::(anonymous namespace)::"
+    assert pr.short_name(ns + "sweep_kernel<13, unsigned char, 2, false, false, 1>(qnae::SweepArgs)") == \
+        "sweep_kernel<TB=13,uchar> sweep_boundary"
+    assert pr.short_name(ns + "sweep_kernel<14, unsigned short, 3, true, false, 2>(qnae::SweepArgs)") == \
+        "sweep_kernel<TB=14,ushort,half> sweep_final"
+    assert pr.short_name(ns + "sweep_kernel<13, unsigned char, 2, false, true, 0>(qnae::SweepArgs)") == \
+        "sweep_kernel<TB=13,uchar> sweep_boundary_ckpt"
+    assert pr.short_name(ns + "adjoint_kernel<unsigned char, 1, false, true, true>(qnae::AdjointArgs)") == \
+        "adjoint_kernel<uchar,stream,q1> adjoint_boundary"
+    assert pr.short_name(ns + "adjoint_kernel<unsigned short, 0, true, false, false>(qnae::AdjointArgs)") == \
+        "adjoint_kernel<ushort> adjoint_middle_weigh"
+    stats = tmp_path / "p_kernel_stats.csv"
+    stats.write_text(
+        '"Name","Calls","TotalDurationNs","AverageNs","Percentage","MinNs","MaxNs","StdDev"\n'
+        f'"{ns}sweep_kernel<13, unsigned char, 1, false, false, 1>(qnae::SweepArgs)",3,9000,3000,60,2900,3100,1\n'
+        f'"{ns}sweep_kernel<13, unsigned char, 1, false, false, 2>(qnae::SweepArgs)",1,1000,1000,40,1000,1000,0\n')
+    out = tmp_path / "trace.txt"
+    pr.trace(str(tmp_path), "p", str(out), "cmd")
+    rows = [l for l in out.read_text().splitlines() if l.startswith("sweep_kernel")]
+    assert len(rows) == 1
+    f = rows[0].split()
+    assert f[-5:] == ["4", "0.0025", "0.0010", "0.0031", "100.00"]
