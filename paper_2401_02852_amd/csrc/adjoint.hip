@@ -643,6 +643,8 @@ hipError_t launch_adjoint_q(int kind, const AdjointArgs& a, hipStream_t s, bool 
     return hipGetLastError();
 }
 
+// A launch passes through layout Q1 when a mask it mixes has a bit of the low
+// run e{0..3} (the first group's tiles).
 template <typename CT, bool NT>
 hipError_t launch_adjoint_ct(int kind, const AdjointArgs& a, hipStream_t s, bool weigh) {
     const uint32_t masks = a.pre_mask | (kind == AK_BOUNDARY ? a.post_mask : 0u);
