@@ -458,31 +458,63 @@ __global__ __launch_bounds__(256) void reverse_kernel(float2* psi, uint64_t N) {
 // Whole circuit in one workgroup for n <= 14 (state resident in LDS).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void mix16(float2 (&v)[16], int nb, float t) {
-    if (nb > 0) bfly<16, 0>(v, t);
-    if (nb > 1) bfly<16, 1>(v, t);
-    if (nb > 2) bfly<16, 2>(v, t);
-    if (nb > 3) bfly<16, 3>(v, t);
-}
-
 // LDS slot of amplitude x: one pad slot per 16, so that the threads of the
 // bits-0..3 pass, each holding 16 consecutive amplitudes, fall in different
 // banks instead of all in one (a stride of 16 float2 is 32 banks).
 __device__ __forceinline__ uint32_t rslot(uint32_t x) { return x + (x >> 4); }
 
-// 1024 threads: one workgroup's 136 KiB of LDS leaves room for no second one
-// on a CU, so its own waves (four per SIMD) hide the LDS latency.
+// 1024 threads: one workgroup's LDS (the 136 KiB state, uint8 costs) leaves
+// room for no second one on a CU, so its own waves (four per SIMD) hide the
+// LDS latency.
 constexpr int kResidentThreads = 1024;
+
+// Radix-2^NBP butterfly passes of one layer over the LDS state: each task
+// holds the 2^nb amplitudes of one coset of nb consecutive qubits.
+template <int NBP>
+__device__ __forceinline__ void resident_mix(float2* s, int n, uint32_t N, float t) {
+    for (int g0 = 0; g0 < n; g0 += NBP) {
+        const int nb = n - g0 < NBP ? n - g0 : NBP;
+        const uint32_t tasks = N >> nb;
+        for (uint32_t task = threadIdx.x; task < tasks; task += kResidentThreads) {
+            const uint32_t bs = ((task >> g0) << (g0 + nb)) | (task & ((1u << g0) - 1u));
+            float2 v[1 << NBP];
+#pragma unroll
+            for (int i = 0; i < (1 << NBP); ++i)
+                v[i] = i < (1 << nb) ? s[rslot(bs | ((uint32_t)i << g0))] : make_float2(0.f, 0.f);
+            if (nb > 0) bfly<(1 << NBP), 0>(v, t);
+            if (NBP > 1 && nb > 1) bfly<(1 << NBP), (NBP > 1 ? 1 : 0)>(v, t);
+            if (NBP > 2 && nb > 2) bfly<(1 << NBP), (NBP > 2 ? 2 : 0)>(v, t);
+            if (NBP > 3 && nb > 3) bfly<(1 << NBP), (NBP > 3 ? 3 : 0)>(v, t);
+#pragma unroll
+            for (int i = 0; i < (1 << NBP); ++i)
+                if (i < (1 << nb)) s[rslot(bs | ((uint32_t)i << g0))] = v[i];
+        }
+        __syncthreads();
+    }
+}
+
+// Qubits per pass: four at n = 14 (1024 cosets, one per thread), three
+// below (at n = 12 and 13 measured 1-2 us faster per solve than four).
+constexpr int kResidentSmallNbp = 3;
 
 template <typename CT>
 __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
     constexpr uint32_t NT = kResidentThreads;
     __shared__ float2 s[(1 << 14) + (1 << 10)];
     __shared__ double red[3][NT / 64];
+    // uint8 costs are read from global memory once and kept beside the state
+    // (16 KiB at n = 14); uint16 ones would not fit and are read per layer.
+    constexpr bool COST_LDS = sizeof(CT) == 1;
+    __shared__ CT cs[COST_LDS ? 1 << 14 : 1];
     const int n = a.n;
     const uint32_t N = 1u << n;
     const uint32_t tid = threadIdx.x;
-    const CT* cost = (const CT*)a.cost;
+    const CT* const cost_g = (const CT*)a.cost;
+    if (COST_LDS) {
+        for (uint32_t x = tid; x < N; x += NT) cs[x] = cost_g[x];
+        __syncthreads();
+    }
+    const CT* const cost = COST_LDS ? cs : cost_g;
     const uint32_t last = (uint32_t)a.lut_len - 1u;
     const int layers = a.p > 0 ? a.p : 1;
     // The butterflies drop the X of the cot form; `flip` records that the
@@ -496,23 +528,10 @@ __device__ __forceinline__ void resident_body(const ResidentArgs& a) {
         }
         __syncthreads();
         if (a.p == 0) break;
-        const MixForm f = a.forms[l];
-        for (int g0 = 0; g0 < n; g0 += 4) {
-            const int nb = n - g0 < 4 ? n - g0 : 4;
-            const uint32_t tasks = N >> nb;
-            for (uint32_t task = tid; task < tasks; task += NT) {
-                const uint32_t bs = ((task >> g0) << (g0 + nb)) | (task & ((1u << g0) - 1u));
-                float2 v[16];
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    v[i] = i < (1 << nb) ? s[rslot(bs | ((uint32_t)i << g0))] : make_float2(0.f, 0.f);
-                mix16(v, nb, f.t);
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (i < (1 << nb)) s[rslot(bs | ((uint32_t)i << g0))] = v[i];
-            }
-            __syncthreads();
-        }
+    const MixForm f = a.forms[l];
+        if (n >= 14) resident_mix<4>(s, n, N, f.t);
+        else if (n == 13) resident_mix<3>(s, n, N, f.t);
+        else resident_mix<kResidentSmallNbp>(s, n, N, f.t);
         if (f.flip) flip ^= N - 1u;
     }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
@@ -550,7 +569,8 @@ __global__ __launch_bounds__(kResidentThreads) void resident_kernel(const Reside
 }
 
 // Tables from the kernel arguments, staged in LDS (3.5 KiB beside the
-// state's 136 KiB) and read through generic pointers.
+// state and costs: 156 of the CU's 160 KiB) and read through generic
+// pointers.
 template <typename CT>
 __global__ __launch_bounds__(kResidentThreads) void resident_inline_kernel(const ResidentInlineArgs ia) {
     __shared__ float2 tab[kResidentInline];
