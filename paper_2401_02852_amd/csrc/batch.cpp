@@ -64,7 +64,7 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
     ClauseRec* recs = (ClauseRec*)(h + rec_at);
     // each job's records start at the sum of the clause counts before it
     std::vector<size_t> rec_off(count);
-    std::vector<int> nrec(count);
+    std::vector<int> nrec(count), nlow(count);
     size_t at = 0;
     for (int i = 0; i < count; ++i) {
         rec_off[i] = at;
@@ -73,7 +73,8 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
     constexpr int kChunk = 16;  // jobs per host task
     parallel_for(ctx, (count + kChunk - 1) / kChunk, total_recs, [&](int c) {
         for (int i = c * kChunk; i < std::min(count, (c + 1) * kChunk); ++i)
-            nrec[i] = make_clause_records(jobs[i].clauses, jobs[i].m, jobs[i].k, recs + rec_off[i], jobs[i].predicate);
+            nrec[i] = make_clause_records(jobs[i].clauses, jobs[i].m, jobs[i].k, recs + rec_off[i], jobs[i].predicate,
+                                          &nlow[i]);
     });
     std::memset(h + zero_at, 0, sizeof(unsigned long long) * count);
     unsigned long long* zeros_dev = (unsigned long long*)(d + zero_at);
@@ -87,6 +88,7 @@ int qnae_build_cost_diagonal_batched(qnae_ctx* ctx, const qnae_cost_job* jobs, i
             const int i = groups[g][q];
             args[q].clauses = (const ClauseRec*)(d + rec_at) + rec_off[i];
             args[q].num_clauses = nrec[i];
+            args[q].num_low = nlow[i];
             const int states = jobs[i].n - (jobs[i].half ? 1 : 0);
             args[q].n = states;
             args[q].cost = jobs[i].cost_dev;

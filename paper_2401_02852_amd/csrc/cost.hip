@@ -7,9 +7,10 @@
 // thread's index), and the part on variables 0..4 is a per-clause table built
 // on the host. The per-state counters are kept as NP bit-planes (a vertical
 // counter); clauses go in eight at a time through a carry-save adder tree, so
-// one clause costs about 9 integer operations per 32 states. At the end the
-// planes are transposed into bytes (uint8) or half-words (uint16) and written
-// with 16-byte stores.
+// one clause costs about 9 integer operations per 32 states (clauses on
+// variables >= 5 only are constant over the run and are counted as one
+// integer instead). At the end the planes are transposed into bytes (uint8)
+// or half-words (uint16) and written with 16-byte stores.
 #include "internal.h"
 
 namespace qnae {
@@ -63,7 +64,7 @@ __device__ __forceinline__ void cost_chunk(const CostArgs& a, uint64_t tid) {
         // the counter value after the block is exactly the sum it had plus
         // the eight violation bits, per state.
         int i = 0;
-        for (; i + 8 <= a.num_clauses; i += 8) {
+        for (; i + 8 <= a.num_low; i += 8) {
             const uint32_t c2a = csa(plane[0], viol(i), viol(i + 1));
             const uint32_t c2b = csa(plane[0], viol(i + 2), viol(i + 3));
             const uint32_t c2c = csa(plane[0], viol(i + 4), viol(i + 5));
@@ -72,7 +73,22 @@ __device__ __forceinline__ void cost_chunk(const CostArgs& a, uint64_t tid) {
             const uint32_t c4b = csa(plane[1], c2c, c2d);
             add_at(3, csa(plane[2], c4a, c4b));
         }
-        for (; i < a.num_clauses; ++i) add_at(0, viol(i));
+        for (; i < a.num_low; ++i) add_at(0, viol(i));
+        // The other clauses only have variables >= 5: each is violated on all
+        // 32 states of the run or on none, so they are counted as one integer
+        // (about 5 operations per clause instead of 9) and the count is added
+        // to every state's counter once, as a ripple-carry over the planes.
+        uint32_t cnt = 0u;
+        for (; i < a.num_clauses; ++i) cnt += viol(i) & 1u;
+        uint32_t carry = 0u;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            const uint32_t cb = 0u - ((cnt >> b) & 1u);
+            const uint32_t t = plane[b] ^ cb;
+            const uint32_t nc = (plane[b] & cb) | (t & carry);
+            plane[b] = t ^ carry;
+            carry = nc;
+        }
         const uint32_t valid = a.n >= 5 ? 0xffffffffu : ((1u << (1u << a.n)) - 1u);
         uint32_t any = 0u;
 #pragma unroll

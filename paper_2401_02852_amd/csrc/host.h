@@ -205,8 +205,10 @@ hipError_t timed(qnae_ctx* ctx, int kind, double bytes, hipStream_t s, F&& fn) {
 }
 
 // Clause records for the cost kernel (drops clauses that can never be
-// violated); returns the number written to `out` (room for m records).
-int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* out, int predicate = QNAE_PRED_NAE);
+// violated); returns the number written to `out` (room for m records), those
+// with a variable below 5 first (*num_low, when given, of them).
+int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* out,
+                        int predicate = QNAE_PRED_NAE, int* num_low = nullptr);
 // QNAE_EINVAL if some literal is 0 or outside +-[1, n].
 int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k);
 

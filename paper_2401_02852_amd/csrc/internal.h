@@ -27,6 +27,7 @@ struct ClauseRec {
 struct CostArgs {
     const ClauseRec* clauses;
     int32_t num_clauses;
+    int32_t num_low;            // records 0 .. num_low-1 have a variable below 5; the rest only higher ones
     int32_t n;
     void* cost;                 // uint8 or uint16 [2^n]
     unsigned long long* zeros;  // optional counter of states with cost 0

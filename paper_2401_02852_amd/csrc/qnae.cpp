@@ -108,7 +108,8 @@ int build_cost(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int3
 
     HIP_TRY(ctx->h_clauses.reserve(sizeof(ClauseRec) * (size_t)(m > 0 ? m : 1)));
     ClauseRec* recs = (ClauseRec*)ctx->h_clauses.ptr;
-    const int nrec = make_clause_records(clauses, m, k, recs, predicate);
+    int nlow = 0;
+    const int nrec = make_clause_records(clauses, m, k, recs, predicate, &nlow);
     HIP_TRY(ctx->clauses.reserve(sizeof(ClauseRec) * (size_t)(nrec > 0 ? nrec : 1)));
     if (nrec > 0)
         HIP_TRY(hipMemcpyAsync(ctx->clauses.ptr, recs, sizeof(ClauseRec) * nrec, hipMemcpyHostToDevice, s));
@@ -118,6 +119,7 @@ int build_cost(qnae_ctx* ctx, const int32_t* clauses, int32_t m, int32_t n, int3
     qnae::CostArgs a;
     a.clauses = (const ClauseRec*)ctx->clauses.ptr;
     a.num_clauses = nrec;
+    a.num_low = nlow;
     a.n = states;
     a.cost = cost_dev;
     a.zeros = num_solutions ? zeros : nullptr;

@@ -309,8 +309,11 @@ int check_literals(const int32_t* clauses, int32_t m, int32_t n, int32_t k) {
 
 // Clause records for the cost kernel; clauses that can never be violated (a
 // variable with both signs: one literal is always true and one false) are
-// dropped. k-SAT clauses only get the all-false table (Section 2.2).
-int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* recs, int predicate) {
+// dropped. k-SAT clauses only get the all-false table (Section 2.2). Records
+// of clauses with a variable below 5 come first (*num_low of them), in input
+// order, then those on higher variables only, in input order.
+int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::ClauseRec* recs, int predicate,
+                        int* num_low) {
     int nrec = 0;
     for (int i = 0; i < m; ++i) {
         uint64_t mask = 0, pat = 0;
@@ -349,6 +352,10 @@ int make_clause_records(const int32_t* clauses, int32_t m, int32_t k, qnae::Clau
         r.full_tab = predicate == QNAE_PRED_NAE ? full : 0u;
         recs[nrec++] = r;
     }
+    // A clause with a low variable has zero_tab != ~0 (half the run or less).
+    const qnae::ClauseRec* mid =
+        std::stable_partition(recs, recs + nrec, [](const qnae::ClauseRec& r) { return r.zero_tab != ~0u; });
+    if (num_low) *num_low = (int)(mid - recs);
     return nrec;
 }
 

@@ -199,7 +199,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
     struct New {
         Request* r;
         size_t rec_at, tab_at;
-        int nrec;
+        int nrec, nlow = 0;
         std::vector<ClauseRec> recs;
         std::vector<float2> tabs;
         std::vector<MixForm> forms;
@@ -210,7 +210,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
         New& w = nw[i];
         w.r = &r;
         w.recs.resize((size_t)std::max(r.m, 1));
-        w.nrec = make_clause_records(r.clauses.data(), r.m, r.k, w.recs.data());
+        w.nrec = make_clause_records(r.clauses.data(), r.m, r.k, w.recs.data(), QNAE_PRED_NAE, &w.nlow);
         w.rec_at = B.take(sizeof(ClauseRec) * (size_t)std::max(w.nrec, 1));
         const int T = r.p > 0 ? r.p : 1;
         w.tabs.resize((size_t)T * (r.m + 1));
@@ -308,6 +308,7 @@ int qnae_server::tick(std::vector<Request*>& admitted) try {
             const New& w = *cgroups[g][q];
             args[q].clauses = (const ClauseRec*)(d + w.rec_at);
             args[q].num_clauses = w.nrec;
+            args[q].num_low = w.nlow;
             const int states = w.r->n - (w.r->half ? 1 : 0);  // half: the lower half of the diagonal
             args[q].n = states;
             args[q].cost = pool + w.r->cost_off;
