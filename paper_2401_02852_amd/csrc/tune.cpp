@@ -132,7 +132,7 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     };
     qnae_tune best{0, 0, 0, 0, 1e300};
     hipError_t err = hipSuccess;
-    // Mean time of one run of an `layers`-layer plan under shape t.
+    // Mean time of one run of a plan of `layers` layers under shape t.
     auto time_plan = [&](const qnae_tune& t, int layers, double* ms_out) -> hipError_t {
         SweepPlan P;
         plan_sweeps(P, n, m, layers, cost_dtype, t.tile_bits, t.low_run_bits, t.page_bit, t.split, false, forms,
@@ -150,7 +150,9 @@ int qnae_autotune(qnae_ctx* ctx, int32_t n, int32_t cost_dtype, int32_t reps, qn
     auto time_shape = [&](const qnae_tune& t) {
         double t_lo = 0.0, t_hi = 0.0;
         if ((err = time_plan(t, p_lo, &t_lo)) || (err = time_plan(t, p, &t_hi))) return;
-        const double ten = t_lo + (10.0 - p_lo) * (t_hi - t_lo) / (p - p_lo);
+        // (timing noise on a tiny state could make the four-layer run look no
+        // slower than the two-layer one: then its own time per layer is used)
+        const double ten = t_hi > t_lo ? t_lo + (10.0 - p_lo) * (t_hi - t_lo) / (p - p_lo) : t_hi * 10.0 / p;
         const qnae_tune timed{t.tile_bits, t.low_run_bits, t.page_bit, t.split, ten / 10.0};
         if (timed.ms_per_layer < best.ms_per_layer) best = timed;
         qnae_tune& b = best_of[t.tile_bits - 12];
