@@ -216,6 +216,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, uint32_t t, doubl
             for (int q = 0; q < PK; ++q) wv |= (uint32_t)c2[scat(L::s2((PK * i + q) ^ cj))] << (8 * sizeof(CT) * q);
             cvp[i] = wv;
         }
+        // With 14-bit tiles (128 registers) the bytes are packed as they
+        // arrive instead of held one per register until the phase step: the
+        // boundary kind then spills nothing instead of 3-4 dwords (n = 24
+        // 2.05 -> 2.10e11 amp-layer updates/s). With 13-bit tiles the same
+        // slowed the boundary kind (3.16 -> 3.27 ms at n = 30).
+        if constexpr (TB == 14) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) asm volatile("" : "+v"(cvp[i]));
+        }
         if (NEED_LUT && LUT_LDS)
             for (int i = threadIdx.x; i < a.lut_len; i += NT) lut_s[i] = a.lut[i];
     }
