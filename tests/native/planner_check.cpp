@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <random>
 #include <string>
 #include <new>
@@ -425,12 +426,49 @@ static void check_split_layouts() {
         }
 }
 
+// Records of clauses with a variable below 5 come first (num_low of them),
+// each part in input order; a record on higher variables only has the
+// all-ones zero table, the kernel's test for the constant part.
+static void check_record_order() {
+    std::mt19937_64 rng(11);
+    for (int trial = 0; trial < 500; ++trial) {
+        const int n = 6 + (int)(rng() % 40), k = 1 + (int)(rng() % 5), m = (int)(rng() % 60);
+        std::vector<int32_t> cl((size_t)m * k);
+        for (auto& l : cl) {
+            const int v = 1 + (int)(rng() % n);
+            l = (rng() & 1u) ? -v : v;
+        }
+        for (int pred : {QNAE_PRED_NAE, QNAE_PRED_SAT}) {
+            std::vector<qnae::ClauseRec> recs((size_t)std::max(m, 1)), one(1);
+            int nlow = -1;
+            const int nrec = make_clause_records(cl.data(), m, k, recs.data(), pred, &nlow);
+            CHECK(nlow >= 0 && nlow <= nrec);
+            // the same records, one clause at a time in input order
+            std::vector<qnae::ClauseRec> lo, hi;
+            for (int i = 0; i < m; ++i) {
+                if (make_clause_records(cl.data() + (size_t)i * k, 1, k, one.data(), pred) != 1) continue;
+                bool low = false;
+                for (int j = 0; j < k; ++j) low = low || (cl[(size_t)i * k + j] > 0 ? cl[(size_t)i * k + j]
+                                                                                    : -cl[(size_t)i * k + j]) <= 5;
+                (low ? lo : hi).push_back(one[0]);
+                CHECK((one[0].zero_tab != ~0u) == low);
+            }
+            CHECK((int)lo.size() == nlow && (int)(lo.size() + hi.size()) == nrec);
+            for (int i = 0; i < nrec; ++i) {
+                const qnae::ClauseRec& want = i < nlow ? lo[(size_t)i] : hi[(size_t)(i - nlow)];
+                CHECK(std::memcmp(&recs[(size_t)i], &want, sizeof want) == 0);
+            }
+        }
+    }
+}
+
 int main() {
     check_fixed_planner_matches_vectors();
     check_half_addressing();
     check_groups_and_plans();
     check_split_layouts();
     check_clause_records();
+    check_record_order();
     check_phase_rows();
     check_host_exception();
     check_worker_pool();
