@@ -183,6 +183,28 @@ def test_grad_n24_streaming(q):
     torch.cuda.empty_cache()
 
 
+def test_grad_u16_streaming(q):
+    """n = 24 with m = 300: 16-bit cost values in the nontemporal reverse
+    kinds (weighing, boundary, end) and the checkpointing forward sweeps,
+    checkpoints every layer, both butterfly forms, against the oracle's
+    adjoint."""
+    import torch
+    n, m, p = 24, 300, 2
+    cl = inst.instance(n, 3, m, 5)
+    rng = np.random.default_rng(2400)
+    g, b = rng.uniform(0, 0.1, p), np.array([0.3, 1.4])
+    c = q.build_cost_diagonal(cl, n)
+    assert str(c.dtype) == "torch.uint16"
+    cost = oracle.cost(cl, n)
+    w = (0.3, 0.4)
+    dg, db, r = q.qaoa_grad(c, n, m, g, b, w_psucc=w[0], w_energy=w[1], checkpoint_every=1)
+    rg, rb, ro = oracle.qaoa_grad(cost, n, g, b, *w)
+    check(dg, db, rg, rb, w)
+    assert abs(r.expected_cost - ro[1]) <= 1e-5 * ro[1], (r, ro)
+    del c
+    torch.cuda.empty_cache()
+
+
 def test_grad_workload_n22_p12(q, golden):
     """The differentiation workload: n = 22, m = 46, p = 12 from the linear
     ramp (beta negated), checkpoints every 4 layers, against the oracle's
