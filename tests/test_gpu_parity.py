@@ -300,6 +300,29 @@ def test_n30_workload_every_tile_shape(q, golden):
     torch.cuda.empty_cache()
 
 
+def test_u16_costs_every_tile_size(q):
+    """16-bit cost values (m = 300) at n = 25 under 12-, 13- and 14-bit tiles
+    (three qubit groups with 13- and 14-bit tiles) and each group split, in
+    every sweep kind (first, middle, boundary, final; tiles through layout
+    L1 and not), against the oracle's readout: the uint16 cost reads and
+    their packing into registers."""
+    import torch
+    n, m, p = 25, 300, 2
+    cl = inst.instance(n, 3, m, 6)
+    ctx = q.Context()
+    c = q.build_cost_diagonal(cl, n, ctx=ctx)
+    assert str(c.dtype) == "torch.uint16"
+    rng = np.random.default_rng(25)
+    g, b = rng.uniform(0, 0.1, p), np.array([0.35, 1.3])
+    ref = oracle.qaoa(oracle.cost(cl, n), n, g, b)
+    for tb, split in [(12, 0), (13, 0), (13, 1), (13, 3), (14, 0), (14, 1), (14, 2)]:
+        ctx.set_tune(n, {"tile_bits": tb, "low_run_bits": 4, "page_bit": 18, "split": split}, "u16")
+        check_result(q.qaoa_run(c, n, m, g, b, ctx=ctx), ref, f"shape {tb}/4/18/{split}")
+    ctx.close()
+    del c
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n", [24, 30, 33, 34])
 def test_ring_closed_form_at_scale(q, n):
     """k = 2 ring of all-positive clauses at p = 1:
